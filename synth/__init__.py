@@ -1,0 +1,188 @@
+"""Seeded synthetic inputs shared by the tests and the benchmark.
+
+This module holds no dedispersion or matched-filter arithmetic.  It makes
+filterbank blocks of quantised Gaussian noise, adds pulses at per-channel
+sample positions that the caller computes, describes the benchmark workloads
+(band, sampling time, DM grid, boxcar widths) and draws arrival times.
+Everything is a pure function of its seed.
+
+Noise recipe: ``x = clip(rint(mean + std * z + pulse), 0, 255)`` as uint8 with
+``z`` standard normal float32 from ``numpy.random.Generator(PCG64(seed))``,
+drawn row block by row block (64 channels at a time).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ROWS_PER_DRAW = 64
+
+
+def _apply_pulses(z, row0, pulses):
+    """Add pulse amplitudes to the float rows ``z`` (channels row0 .. row0+len)."""
+    rows, nsamp = z.shape
+    for start, width, amp in pulses:
+        start = np.asarray(start, dtype=np.int64)
+        amp_arr = np.broadcast_to(np.asarray(amp, dtype=np.float64), start.shape)
+        for r in range(rows):
+            ch = row0 + r
+            a = int(start[ch])
+            b = min(a + int(width), nsamp)
+            a = max(a, 0)
+            if a < b:
+                z[r, a:b] += np.float32(amp_arr[ch])
+
+
+def normal_u8(nchan, nsamp, seed, *, mean=128.0, std=16.0, pulses=()):
+    """[nchan, nsamp] uint8 block of clipped, rounded N(mean, std^2) noise.
+
+    ``pulses`` is a sequence of (start[nchan], width, amplitude) where
+    ``start[ch]`` is the first sample of the pulse in channel ``ch`` and the
+    amplitude (scalar or per channel) is added before rounding."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.empty((nchan, nsamp), dtype=np.uint8)
+    for r0 in range(0, nchan, ROWS_PER_DRAW):
+        r1 = min(nchan, r0 + ROWS_PER_DRAW)
+        z = rng.standard_normal((r1 - r0, nsamp), dtype=np.float32)
+        z *= np.float32(std)
+        z += np.float32(mean)
+        _apply_pulses(z, r0, pulses)
+        np.rint(z, out=z)
+        np.clip(z, 0, 255, out=z)
+        out[r0:r1] = z.astype(np.uint8)
+    return out
+
+
+def pooled_normal_u8(nchan, nsamp, seed, *, pool=64, mean=128.0, std=16.0, pulses=()):
+    """Like ``normal_u8`` but fast for large blocks: ``pool`` noise rows are
+    drawn once and channel ``ch`` is pool row ``k[ch]`` rotated by ``s[ch]``
+    samples (``k`` and ``s`` drawn from the same seed).  Channels are then not
+    independent, which matters for statistics but not for throughput or
+    exactness checks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pool = min(pool, nchan)
+    base = rng.standard_normal((pool, nsamp), dtype=np.float32)
+    base *= np.float32(std)
+    base += np.float32(mean)
+    k = rng.integers(0, pool, size=nchan)
+    s = rng.integers(0, nsamp, size=nchan)
+    out = np.empty((nchan, nsamp), dtype=np.uint8)
+    for r0 in range(0, nchan, ROWS_PER_DRAW):
+        r1 = min(nchan, r0 + ROWS_PER_DRAW)
+        z = np.stack([np.roll(base[k[c]], int(s[c])) for c in range(r0, r1)])
+        _apply_pulses(z, r0, pulses)
+        np.rint(z, out=z)
+        np.clip(z, 0, 255, out=z)
+        out[r0:r1] = z.astype(np.uint8)
+    return out
+
+
+def uniform_u8(nchan, nsamp, seed):
+    """[nchan, nsamp] uint8, every value 0..255 equally likely."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, 256, size=(nchan, nsamp), dtype=np.uint8)
+
+
+def uniform_i32(nrows, nsamp, seed, lo, hi):
+    """[nrows, nsamp] int32 uniform on [lo, hi]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(lo, hi + 1, size=(nrows, nsamp), dtype=np.int64).astype(np.int32)
+
+
+def band_centres(f_top, f_bottom, nchan):
+    """Centre frequencies (MHz) of ``nchan`` equal channels filling the band,
+    highest first (the usual filterbank order with a negative channel step)."""
+    bw = (float(f_top) - float(f_bottom)) / nchan
+    return np.array([float(f_top) - (c + 0.5) * bw for c in range(nchan)], dtype=np.float64)
+
+
+def pow2_widths(wmax):
+    """1, 2, 4, ..., wmax."""
+    out, w = [], 1
+    while w <= wmax:
+        out.append(w)
+        w *= 2
+    return out
+
+
+@dataclass
+class Workload:
+    name: str
+    freqs: np.ndarray
+    tsamp: float
+    dms: np.ndarray
+    nsub: int
+    nt: int
+    widths: list
+    seed: int
+    gamma: float = 6.0
+    pulses: list = field(default_factory=list)   # (dm, t, width, snr-or-amp spec)
+
+
+def workload(name):
+    """The benchmark workloads, by name.
+
+    * ``plain-256``: 256 channels over 856-1712 MHz, 306.24 us, 8192 output
+      samples, 128 DM trials 0..508 step 4, 16 sub-bands, widths 1..64, one
+      pulse (DM 200, width 4, +6 sigma per channel = +96 counts, t = 4000).
+    * ``paper-4096``: 4096 channels over 856-1712 MHz, 153.12 us, 65536 output
+      samples, 4096 DM trials 0..2047.5 step 0.5, 64 sub-bands, widths 1..512,
+      ten pulses (random DM, width 1..32, integrated S/N 3..10).
+    * ``served-4096``: the served-stream block: 4096 channels, 153.12 us, 32768
+      samples, 2048 DM trials 0..1023.5, 64 sub-bands, widths 1..512.
+    * ``octave-8192``: 8192 channels over 544-1088 MHz, 153.12 us, 65536
+      samples, 8192 trials evenly over 0..5000, 64 sub-bands, widths 1..1024.
+    """
+    if name == "plain-256":
+        return Workload(name, band_centres(1712.0, 856.0, 256), 306.24e-6,
+                        np.arange(128, dtype=np.float64) * 4.0, 16, 8192, pow2_widths(64), 1,
+                        pulses=[("amp", 200.0, 4000, 4, 96.0)])
+    if name == "paper-4096":
+        rng = np.random.Generator(np.random.PCG64(2002))
+        pulses = []
+        slots = rng.permutation(10)
+        for k in range(10):
+            dm = float(rng.uniform(0.0, 2047.5))
+            w = int(rng.integers(1, 33))
+            snr = float(rng.uniform(3.0, 10.0))
+            t = int(slots[k]) * 6400 + 1000          # non-overlapping start times
+            pulses.append(("snr", dm, t, w, snr))
+        return Workload(name, band_centres(1712.0, 856.0, 4096), 153.12e-6,
+                        np.arange(4096, dtype=np.float64) * 0.5, 64, 65536, pow2_widths(512), 2,
+                        pulses=pulses)
+    if name == "served-4096":
+        return Workload(name, band_centres(1712.0, 856.0, 4096), 153.12e-6,
+                        np.arange(2048, dtype=np.float64) * 0.5, 64, 32768, pow2_widths(512), 4)
+    if name == "octave-8192":
+        return Workload(name, band_centres(1088.0, 544.0, 8192), 153.12e-6,
+                        np.linspace(0.0, 5000.0, 8192), 64, 65536, pow2_widths(1024), 5,
+                        pulses=[("snr-index", 2500.0, 30000, 8, 12.0)])
+    raise KeyError(name)
+
+
+def pulse_amplitude(spec, width, nchan, std=16.0):
+    """Per-channel amplitude for a pulse spec: ``("amp", ..., a)`` is a fixed
+    amplitude; ``("snr", ..., s)`` spreads an integrated S/N ``s`` evenly over
+    channels and samples, a = std * s / sqrt(nchan * width)."""
+    kind = spec[0]
+    if kind == "amp":
+        return float(spec[-1])
+    return float(std * spec[-1] / np.sqrt(nchan * width))
+
+
+def spectral_amplitudes(freqs, f0, index, scale):
+    """Per-channel amplitude ``scale * (f / f0) ** index`` (a power-law spectrum)."""
+    return scale * (np.asarray(freqs, dtype=np.float64) / f0) ** index
+
+
+def poisson_arrivals(nbeams, nblocks, period_s, speed, seed):
+    """Arrival times [nbeams, nblocks] in seconds: each beam starts at a
+    uniform time in [0, period) and then waits exponential gaps of mean
+    period / speed between blocks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    start = rng.uniform(0.0, period_s, size=nbeams)
+    gaps = rng.exponential(period_s / speed, size=(nbeams, nblocks))
+    gaps[:, 0] = 0.0
+    return start[:, None] + np.cumsum(gaps, axis=1)

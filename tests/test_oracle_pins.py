@@ -1,0 +1,475 @@
+"""Pins of the CPU oracle to facts that the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints, closed forms, exact rational arithmetic, special cases that
+reduce the method to brute force, invariants, and brute force on tiny inputs.
+"""
+
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _paper():
+    with open(os.path.join(GOLDEN, "paper_values.json")) as f:
+        return json.load(f)
+
+
+def _rand_plan(seed, nchan=32, nsub=8, ndm=23, f_top=1500.0, f_bot=1100.0, tsamp=1e-3, dm_max=300.0, g=None):
+    rng = np.random.default_rng(seed)
+    freqs = synth.band_centres(f_top, f_bot, nchan)
+    dms = np.sort(rng.uniform(0.0, dm_max, ndm))
+    dms[0] = 0.0
+    return oracle.make_plan(freqs, tsamp, dms, nsub, g=g)
+
+
+# ---------------------------------------------------------------------------
+# The delay (Sec. 2.3, Eq. 1)
+# ---------------------------------------------------------------------------
+
+def test_dispersion_constant_matches_paper_zeta_coefficient():
+    """Eq. 4's printed 6.91e-3 is 2 k sqrt(ln 2) with k in ms GHz^2: it fixes
+    the dispersion constant to three digits."""
+    z = _paper()["zeta_coefficient"]
+    k_ms_ghz2 = oracle.K_DM * 1e3 / 1e6          # s MHz^2 -> ms GHz^2
+    coeff = 2.0 * k_ms_ghz2 * 1e-3 * math.sqrt(math.log(2.0))   # per MHz of bandwidth
+    assert float(f"{coeff:.{z['significant_digits']}g}") == pytest.approx(z["value"], rel=1e-12)
+
+
+def test_dispersion_constant_from_physical_constants():
+    """k = e^2 / (2 pi m_e c) in Gaussian units, converted to s MHz^2 pc^-1 cm^3."""
+    e = 4.80320471e-10          # statcoulomb
+    m_e = 9.1093837015e-28      # g
+    c = 2.99792458e10           # cm / s
+    pc = 3.0856775814913673e18  # cm
+    k = e * e / (2.0 * math.pi * m_e * c)      # cm^3 s^-2 ... per (cm^-3 cm) -> s * Hz^2 * cm^2
+    k_astro = k * pc / 1e12                    # DM in pc cm^-3, f in MHz
+    assert k_astro == pytest.approx(oracle.K_DM, rel=2e-4)
+
+
+def test_delay_matches_exact_rational_evaluation():
+    """The float64 delay equals floor(k DM (1/f^2 - 1/fref^2) / tsamp + 1/2)
+    evaluated exactly on the same inputs, except within 1e-9 of a tie."""
+    rng = np.random.default_rng(11)
+    fref = 1712.0
+    checked = 0
+    for _ in range(3000):
+        dm = float(rng.uniform(0, 3000))
+        f = float(rng.uniform(300, fref))
+        ts = float(rng.choice([64e-6, 153.12e-6, 306.24e-6, 1e-3]))
+        x = Fraction(oracle.K_DM) * Fraction(dm) * (1 / Fraction(f) ** 2 - 1 / Fraction(fref) ** 2) / Fraction(ts)
+        exact = math.floor(x + Fraction(1, 2))
+        frac = x - math.floor(x)
+        if abs(frac - Fraction(1, 2)) < Fraction(1, 10 ** 9):
+            continue
+        assert int(oracle.delay_samples(dm, f, fref, ts)) == exact
+        checked += 1
+    assert checked > 2900
+
+
+def test_delay_special_values():
+    f = synth.band_centres(1712, 856, 64)
+    fref = f.max()
+    assert np.all(oracle.delay_samples(0.0, f, fref, 1e-4) == 0)
+    assert np.all(oracle.delay_samples(np.arange(10) * 100.0, fref, fref, 1e-4) == 0)
+    d = oracle.delay_samples(500.0, f, fref, 1e-4)
+    assert np.all(np.diff(d) >= 0)          # lower frequency (later channel) arrives later
+    assert d[-1] > 0
+    # Half-up rounding: a float64 delay of exactly 2.5 samples rounds to 3, not
+    # to the even 2.  f = 1024, fref = 2048 make 1/f^2 - 1/fref^2 exact, and this
+    # tsamp makes the quotient exactly 2.5 in float64.
+    tau = (oracle.K_DM * 0.5) * (1.0 / (1024.0 * 1024.0) - 1.0 / (2048.0 * 2048.0))
+    ts = tau / 2.5
+    assert tau / ts == 2.5
+    assert int(oracle.delay_samples(0.5, 1024.0, 2048.0, ts)) == 3
+    assert int(oracle.delay_samples(0.5, 1024.0, 2048.0, tau / 2.25)) == 2
+    assert int(oracle.delay_samples(0.5, 1024.0, 2048.0, tau / 2.75)) == 3
+
+
+# ---------------------------------------------------------------------------
+# Dedispersion: brute force, and the sub-band method's reductions to it
+# ---------------------------------------------------------------------------
+
+def _python_brute(x, freqs, tsamp, dms, nt):
+    fref = max(freqs)
+    out = []
+    for dm in dms:
+        row = []
+        for t in range(nt):
+            acc = 0
+            for ch, f in enumerate(freqs):
+                acc += int(x[ch][t + int(oracle.delay_samples(dm, f, fref, tsamp))])
+            row.append(acc)
+        out.append(row)
+    return np.array(out, dtype=np.int64)
+
+
+def test_brute_force_matches_triple_loop():
+    freqs = list(synth.band_centres(1400, 1000, 6))
+    dms = [0.0, 3.0, 17.5, 40.0, 41.0]
+    tsamp = 5e-4
+    fref = max(freqs)
+    need = 20 + int(oracle.delay_samples(max(dms), min(freqs), fref, tsamp))
+    x = synth.uniform_u8(6, need, 5)
+    y = oracle.dedisperse_brute(x, freqs, tsamp, dms, 20)
+    assert np.array_equal(y, _python_brute(x, freqs, tsamp, dms, 20))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_one_trial_per_group_is_brute_force(seed):
+    plan = _rand_plan(seed, g=1)
+    nt = 97
+    x = synth.uniform_u8(plan.nchan, nt + plan.overlap, seed)
+    ys = oracle.dedisperse_subband(x, plan, nt)
+    yb = oracle.dedisperse_brute(x, plan.freqs, plan.tsamp, plan.dms, nt)
+    assert np.array_equal(ys, yb)
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_one_channel_per_subband_is_brute_force(seed):
+    plan = _rand_plan(seed, nchan=24, nsub=24)
+    assert plan.g == plan.ndm
+    nt = 64
+    x = synth.uniform_u8(plan.nchan, nt + plan.overlap, seed)
+    assert np.array_equal(oracle.dedisperse_subband(x, plan, nt),
+                          oracle.dedisperse_brute(x, plan.freqs, plan.tsamp, plan.dms, nt))
+
+
+@pytest.mark.parametrize("seed", [6, 7, 8])
+def test_group_representatives_are_brute_force(seed):
+    plan = _rand_plan(seed, nchan=64, nsub=8, ndm=40, dm_max=900.0)
+    assert 1 < plan.g < plan.ndm
+    nt = 80
+    x = synth.uniform_u8(plan.nchan, nt + plan.overlap, seed)
+    ys = oracle.dedisperse_subband(x, plan, nt)
+    yb = oracle.dedisperse_brute(x, plan.freqs, plan.tsamp, plan.dms, nt)
+    reps = np.arange(0, plan.ndm, plan.g)
+    assert np.array_equal(ys[reps], yb[reps])
+    assert not np.array_equal(ys, yb)   # the approximation is real elsewhere
+
+
+def test_zero_dm_is_channel_sum():
+    plan = _rand_plan(9, nchan=48, nsub=6)
+    nt = 50
+    x = synth.uniform_u8(plan.nchan, nt + plan.overlap, 9)
+    ys = oracle.dedisperse_subband(x, plan, nt)
+    assert plan.dms[0] == 0.0
+    assert np.array_equal(ys[0], x[:, :nt].astype(np.int64).sum(axis=0))
+
+
+@pytest.mark.parametrize("seed", [10, 11])
+def test_two_stages_equal_effective_offset_sum(seed):
+    plan = _rand_plan(seed, nchan=96, nsub=12, ndm=57, dm_max=1200.0)
+    nt = 123
+    x = synth.uniform_u8(plan.nchan, nt + plan.overlap, seed)
+    assert np.array_equal(oracle.dedisperse_subband(x, plan, nt),
+                          oracle.dedisperse_offsets(x, plan.offsets, nt))
+
+
+def test_constant_input_gives_nchan_times_value():
+    plan = _rand_plan(12)
+    nt = 40
+    for v in (0, 1, 128, 255):
+        x = np.full((plan.nchan, nt + plan.overlap), v, dtype=np.uint8)
+        assert np.all(oracle.dedisperse_subband(x, plan, nt) == plan.nchan * v)
+
+
+def test_linear_in_input():
+    plan = _rand_plan(13)
+    nt = 33
+    a = synth.uniform_u8(plan.nchan, nt + plan.overlap, 1).astype(np.int64)
+    b = synth.uniform_u8(plan.nchan, nt + plan.overlap, 2).astype(np.int64)
+    ya = oracle.dedisperse_subband(a, plan, nt)
+    yb = oracle.dedisperse_subband(b, plan, nt)
+    assert np.array_equal(oracle.dedisperse_subband(3 * a + b, plan, nt), 3 * ya + yb)
+
+
+def test_impulse_response():
+    """A single 1 at (ch, tau) shows up at t = tau - off(i, ch) in every row."""
+    plan = _rand_plan(14, nchan=40, nsub=5, ndm=30, dm_max=600.0)
+    nt = 150
+    ch = 31
+    tau = plan.overlap + 20
+    x = np.zeros((plan.nchan, nt + plan.overlap), dtype=np.uint8)
+    x[ch, tau] = 1
+    y = oracle.dedisperse_subband(x, plan, nt)
+    for i in range(plan.ndm):
+        t = tau - int(plan.offsets[i, ch])
+        expect = np.zeros(nt, dtype=np.int64)
+        if 0 <= t < nt:
+            expect[t] = 1
+        assert np.array_equal(y[i], expect)
+
+
+def test_block_split_invariance():
+    """Dedispersing [0, a) and [a, a + b) of one stream equals [0, a + b)."""
+    plan = _rand_plan(15)
+    a, b = 37, 58
+    x = synth.uniform_u8(plan.nchan, a + b + plan.overlap, 15)
+    whole = oracle.dedisperse_subband(x, plan, a + b)
+    first = oracle.dedisperse_subband(x[:, :a + plan.overlap], plan, a)
+    second = oracle.dedisperse_subband(x[:, a:], plan, b)
+    assert np.array_equal(np.concatenate([first, second], axis=1), whole)
+
+
+def test_input_length_is_exactly_output_plus_overlap():
+    plan = _rand_plan(16)
+    nt = 10
+    x = synth.uniform_u8(plan.nchan, nt + plan.overlap, 16)
+    oracle.dedisperse_subband(x, plan, nt)
+    with pytest.raises(ValueError):
+        oracle.dedisperse_subband(x[:, :-1], plan, nt)
+    assert plan.overlap >= plan.offsets.max()
+    assert plan.overlap >= int(oracle.delay_samples(plan.dms[-1], plan.freqs.min(), plan.fref, plan.tsamp))
+
+
+@pytest.mark.parametrize("name", ["plain-256", "paper-4096", "octave-8192"])
+def test_group_rule_bounds_subband_smearing(name):
+    """The coarse grid's promise: the sub-band method's per-channel offset
+    differs from the brute-force delay by at most half the full-band delay
+    change of one fine DM step, plus the rounding of the four delays."""
+    wl = synth.workload(name)
+    plan = oracle.make_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    step = float(np.max(np.diff(wl.dms)))
+    a_full = 1.0 / plan.freqs.min() ** 2 - 1.0 / plan.fref ** 2
+    half_step_delay = 0.5 * oracle.K_DM * step * a_full / plan.tsamp
+    rows = np.linspace(0, plan.ndm - 1, 97).astype(int)
+    brute = oracle.delay_samples(plan.dms[rows][:, None], plan.freqs[None, :], plan.fref, plan.tsamp)
+    err = np.abs(plan.offsets[rows] - brute)
+    assert err.max() <= half_step_delay + 2.0
+    # and the rule is not trivially loose: one more trial per group breaks it
+    plan2 = oracle.make_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub, g=2 * plan.g + 2)
+    brute2 = oracle.delay_samples(plan2.dms[rows][:, None], plan2.freqs[None, :], plan2.fref, plan2.tsamp)
+    assert np.abs(plan2.offsets[rows] - brute2).max() > half_step_delay + 2.0
+
+
+def test_plain256_plan_matches_hand_values():
+    """256 channels, 16 sub-bands: the coarse groups, overlap and the brute
+    reach checked by hand from the delay formula."""
+    wl = synth.workload("plain-256")
+    plan = oracle.make_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    fmin, fref = wl.freqs.min(), wl.freqs.max()
+    reach = oracle.K_DM * 508.0 * (1 / fmin ** 2 - 1 / fref ** 2) / wl.tsamp
+    assert plan.overlap == math.floor(reach + 0.5)
+    assert plan.g == 4 and plan.ngroups == 32
+
+
+# ---------------------------------------------------------------------------
+# Matched filter (Sec. 2.4)
+# ---------------------------------------------------------------------------
+
+def test_window_sums_from_running_sum_equal_direct_sums():
+    y = synth.uniform_i32(1, 300, 3, -1000, 1000)[0]
+    p = oracle.ref._prefix(y)
+    for w in (1, 2, 3, 7, 64, 300):
+        S = oracle.ref._window_sums(p, w)
+        direct = np.array([int(np.sum(y[t:t + w].astype(np.int64))) for t in range(300 - w + 1)])
+        assert np.array_equal(S, direct)
+
+
+def test_stats_are_population_moments():
+    y = synth.uniform_i32(1, 5000, 4, 0, 2_000_000)[0]
+    st = oracle.dm_stats(y)
+    assert st.sum_y == int(np.sum(y.astype(np.int64)))
+    assert st.var == pytest.approx(np.var(y.astype(np.float64)), rel=1e-11)
+    assert st.sigma == pytest.approx(np.std(y.astype(np.float64)), rel=1e-11)
+
+
+def test_snr_is_mean_removed_sum_over_sigma_root_w():
+    y = synth.uniform_i32(1, 777, 5, 0, 5000)[0]
+    st = oracle.dm_stats(y)
+    mean = st.sum_y / 777
+    for S, w in ((123456, 32), (1, 1), (4000 * 8, 8), (0, 4)):
+        want = (S - w * mean) / (st.sigma * math.sqrt(w))
+        assert oracle.snr_from_sum(S, w, 777, st.sum_y, st.inv_d) == pytest.approx(want, rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("W", [3, 8, 16, 40])
+def test_width_mismatch_loss_closed_form(W):
+    """Sec. 2.4, Eq. 8: S/N / S/N_opt = sqrt((W + dW) / W) for dW <= 0 and
+    sqrt(W / (W + dW)) for dW > 0, on a noise-free boxcar pulse."""
+    T = 400
+    y = np.zeros(T)
+    y[150:150 + W] = 1.0
+    widths = list(range(1, 81))
+    snr = oracle.boxcar_snr_fixed(y, widths, 0.0, 1.0)
+    opt = math.sqrt(W)
+    for w, s in zip(widths, snr):
+        dW = w - W
+        want = math.sqrt((W + dW) / W) if dW <= 0 else math.sqrt(W / (W + dW))
+        assert s / opt == pytest.approx(want, abs=1e-12)
+
+
+def test_false_alarm_rate_matches_erfc():
+    """Sec. 2.4, Eq. 6: on white Gaussian noise the fraction of windows with
+    S/N >= gamma is erfc(gamma / sqrt 2) / 2, for every width."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    T = 1 << 20
+    y = np.rint(1000.0 * rng.standard_normal(T)).astype(np.int64)
+    for gamma in (2.0, 3.0):
+        p = 0.5 * math.erfc(gamma / math.sqrt(2.0))
+        for w in (1, 4, 32):
+            snr = oracle.boxcar_snr_series(y, w)
+            frac = float(np.mean(snr >= gamma))
+            se = math.sqrt(p * (1 - p) / (T / w))
+            assert abs(frac - p) < 5 * se, (gamma, w, frac, p)
+
+
+def _brute_peak(y, widths):
+    T = len(y)
+    st = oracle.dm_stats(y)
+    if not st.var > 0:
+        return (0.0, widths[0], 0)
+    best = None
+    for w in sorted(widths):
+        if w > T:
+            continue
+        bS, bt = None, None
+        for t in range(T - w + 1):
+            S = int(sum(int(v) for v in y[t:t + w]))
+            if bS is None or S > bS:
+                bS, bt = S, t
+        snr = oracle.snr_from_sum(bS, w, T, st.sum_y, st.inv_d)
+        if best is None or snr > best[0]:
+            best = (snr, w, bt)
+    return best if best is not None else (0.0, widths[0], 0)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_peak_matches_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    T = int(rng.integers(5, 90))
+    y = rng.integers(0, 6, size=T)          # small alphabet: many exact ties
+    widths = [1, 2, 4, 8, 16, 32, 64]
+    assert oracle.boxcar_peak(y, widths) == _brute_peak(y, widths)
+
+
+@pytest.mark.parametrize("y,want", [
+    ([3, 2, 3, 2, 2, 1, 3, 0, 2], (1, 0)),
+    ([3, 1, 3, 2, 3, 2, 0], (1, 0)),
+    ([1, 3, 2, 3, 0, 0], (1, 1)),
+    ([0, 0, 2, 1, 1, 2], (1, 2)),
+])
+def test_peak_equal_snr_across_widths_goes_to_smaller_width(y, want):
+    """Series where widths 1 and 4 reach bit-identical S/N: the smaller wins."""
+    y = np.array(y)
+    st = oracle.dm_stats(y)
+    T = len(y)
+    p = oracle.ref._prefix(y)
+    s1 = oracle.ref._window_sums(p, 1).max()
+    s4 = oracle.ref._window_sums(p, 4).max()
+    assert oracle.snr_from_sum(int(s1), 1, T, st.sum_y, st.inv_d) == \
+        oracle.snr_from_sum(int(s4), 4, T, st.sum_y, st.inv_d)
+    snr, w, t = oracle.boxcar_peak(y, [1, 2, 4])
+    assert (w, t) == want
+
+
+def test_peak_degenerate_cases():
+    assert oracle.boxcar_peak(np.full(50, 7), [2, 4]) == (0.0, 2, 0)
+    assert oracle.boxcar_peak(np.arange(3), [4, 8]) == (0.0, 4, 0)
+    snr, w, t = oracle.boxcar_peak(np.array([0, 0, 5, 0]), [1, 2, 8])
+    assert (w, t) == (1, 2) and snr > 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_candidates_match_brute_force(seed):
+    rng = np.random.default_rng(100 + seed)
+    Y = rng.integers(0, 10, size=(5, 60))
+    Y[2, 30:34] += 25
+    widths = [1, 2, 4, 8]
+    gamma = 2.5
+    want = []
+    for d in range(5):
+        st = oracle.dm_stats(Y[d])
+        if not st.var > 0:
+            continue
+        for t in range(60):
+            best = None
+            for w in widths:
+                if t + w > 60:
+                    continue
+                S = int(Y[d, t:t + w].sum())
+                s = oracle.snr_from_sum(S, w, 60, st.sum_y, st.inv_d)
+                if best is None or s > best[1]:
+                    best = (w, s)
+            if best is not None and best[1] >= gamma:
+                want.append((d, t, best[0], best[1]))
+    assert oracle.boxcar_candidates(Y, widths, gamma) == want
+
+
+# ---------------------------------------------------------------------------
+# Recovery of injected pulses and the spectral-index loss (Sec. 4.1)
+# ---------------------------------------------------------------------------
+
+def _plain256_block():
+    wl = synth.workload("plain-256")
+    plan = oracle.make_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    _, dm, t0, w, amp = wl.pulses[0]
+    start = t0 + oracle.delay_samples(dm, wl.freqs, plan.fref, wl.tsamp)
+    x = synth.normal_u8(plan.nchan, wl.nt + plan.overlap, wl.seed, pulses=[(start, w, amp)])
+    return wl, plan, x
+
+
+def test_injected_pulse_recovered_at_its_dm():
+    wl, plan, x = _plain256_block()
+    yb = oracle.dedisperse_brute(x, plan.freqs, plan.tsamp, plan.dms, wl.nt)
+    peaks_b = oracle.boxcar_peaks(yb, wl.widths)
+    ib = int(np.argmax(peaks_b[0]))
+    assert ib == 50 and plan.dms[ib] == 200.0
+    assert peaks_b[2][ib] == 4000 and peaks_b[1][ib] == 4
+    ys = oracle.dedisperse_subband(x, plan, wl.nt)
+    peaks_s = oracle.boxcar_peaks(ys, wl.widths)
+    i_s = int(np.argmax(peaks_s[0]))
+    assert i_s == 50
+    assert peaks_s[0][i_s] >= 0.5 * peaks_b[0][ib]
+    # the zero-variance rule never fires on noise
+    assert np.all(peaks_s[0] != 0.0)
+
+
+def _spectral_closed_form(alpha, eta):
+    a = -alpha + 1.0
+    b = -2.0 * alpha + 1.0
+    return ((eta ** a - 1.0) / a) / math.sqrt((eta - 1.0) * (eta ** b - 1.0) / b)
+
+
+def test_spectral_index_loss_matches_paper_value():
+    v = _paper()["spectral_index_loss_eta2_index2"]
+    loss = 1.0 - _spectral_closed_form(-2.0, 2.0)
+    assert abs(loss - v["value"]) < v["abs_tolerance"]
+
+
+def test_spectral_index_dedispersed_pulse_matches_discrete_closed_form():
+    """A noise-free pulse with per-channel amplitude a_j, dedispersed at its
+    DM, sums to w * sum(a_j); the equal-weight S/N over the optimally weighted
+    one is sum(a) / sqrt(N_f sum(a^2)), which approaches the continuum form of
+    Sec. 4.1 for many channels."""
+    freqs = synth.band_centres(1088.0, 544.0, 256)
+    tsamp = 153.12e-6
+    dms = np.array([0.0, 250.0, 500.0])
+    plan = oracle.make_plan(freqs, tsamp, dms, 16, g=1)
+    amps = synth.spectral_amplitudes(freqs, 816.0, -1.5, 3.0)
+    nt, w, t0 = 256, 8, 100
+    x = np.zeros((256, nt + plan.overlap))
+    start = t0 + oracle.delay_samples(500.0, freqs, plan.fref, tsamp)
+    for ch in range(256):
+        x[ch, start[ch]:start[ch] + w] = amps[ch]
+    y = oracle.dedisperse_subband(x, plan, nt)
+    assert y[2, t0:t0 + w] == pytest.approx(np.full(w, amps.sum()), rel=1e-12)
+    snr_eq = oracle.boxcar_snr_fixed(y[2], [w], 0.0, math.sqrt(256.0))[0]
+    snr_opt = w * np.sum(amps ** 2) / (math.sqrt(w) * math.sqrt(np.sum(amps ** 2)))
+    ratio = snr_eq / snr_opt
+    assert ratio == pytest.approx(amps.sum() / math.sqrt(256 * np.sum(amps ** 2)), rel=1e-12)
+    # discrete-channel efficiency vs the continuum closed form (eta = 2)
+    f8 = synth.band_centres(1088.0, 544.0, 8192)
+    a8 = (f8 / 816.0) ** -1.5
+    discrete = a8.sum() / math.sqrt(8192 * np.sum(a8 ** 2))
+    assert discrete == pytest.approx(_spectral_closed_form(1.5, 2.0), abs=2e-9)
