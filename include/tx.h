@@ -1,0 +1,286 @@
+/*
+ * libtx: two-stage sub-band incoherent dedispersion of uint8 filterbank blocks
+ * and the boxcar matched filter, on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Men & Barr, "TransientX: A high performance single
+ * pulse search package":
+ *   - cold-plasma delay, Sec. 2.3 Eq. 1;
+ *   - sub-band dedispersion, Sec. 2.3 (coarse DM grid per sub-band, then the
+ *     fine grid over the sub-banded series) and Fig. "subband";
+ *   - block processing with a carried-over tail ("shift data"), Sec. 2.3 and
+ *     Fig. "dedispersion_flow";
+ *   - boxcar S/N from a running sum, Sec. 2.4 Eq. 5;
+ *   - the thresholded DM-time plane (best width per DM and time), Sec. 2.5.
+ *
+ * Conventions for every call:
+ *   - Every call returns a tx_status; 0 is success.  Nothing throws across the
+ *     ABI.  Errors from work already queued on a stream surface as TX_EDEVICE
+ *     on a later call that synchronises, or from the caller's own stream sync.
+ *   - "d_" pointers are device memory on the current HIP device; "host_"
+ *     pointers are host memory.  The caller owns every buffer it passes;
+ *     no call frees caller memory.  Plans, streams and batches own their
+ *     tables, rings and scratch and release them in the matching destroy call.
+ *   - Device work is queued on the given hipStream_t (0 = the null stream) and
+ *     is asynchronous unless stated otherwise.
+ *   - Plans are immutable after creation and may be shared between threads and
+ *     streams.  Streams and batches have a single owner.
+ */
+#ifndef TX_H
+#define TX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tx_status {
+    TX_OK = 0,
+    TX_EINVAL = -1,     /* an argument is out of range or inconsistent */
+    TX_ENOMEM = -2,     /* host or device allocation failed */
+    TX_EDEVICE = -3,    /* a HIP runtime call failed (no device, launch error, fault) */
+    TX_ESTATE = -4,     /* the object is not in a state that allows this call */
+    TX_EOVERFLOW = -5,  /* a delay or size does not fit the exact integer path */
+    TX_ENOTSUP = -6     /* the call is valid but this build does not support it */
+} tx_status;
+
+/* Human-readable name of a status code.  Never NULL. */
+const char* tx_status_str(tx_status s);
+
+/* Version string of the library build. */
+const char* tx_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Plans (Sec. 2.3)                                                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct tx_plan_s* tx_plan_t;
+
+/* Flags for tx_plan_ex. */
+#define TX_PLAN_HOST_ONLY 1u   /* build the host tables only; no device upload */
+
+/*
+ * tx_plan: build a dedispersion plan.
+ *
+ *   freqs_mhz[nchan]  channel centre frequencies in MHz, any order; channel
+ *                     c of every input block is row c.  Finite and > 0.
+ *   tsamp_s           sampling interval in seconds, finite and > 0.
+ *   dms[ndm]          fine DM trials in pc cm^-3, finite, >= 0, non-decreasing.
+ *   nsub              number of sub-bands; must divide nchan, and
+ *                     nchan / nsub <= 256 (the first stage sums up to 256
+ *                     uint8 channels exactly in 16 bits).  0 asks the plan to
+ *                     pick nsub itself (the divisor of nchan with at most 256
+ *                     channels per sub-band that minimises the additions per
+ *                     output sample).
+ *
+ * Delays follow Sec. 2.3 Eq. 1 with k = 4.148808e3 s MHz^2 pc^-1 cm^3:
+ *   D(DM, f) = floor(((k*DM) * (1/(f*f) - 1/(fref*fref))) / tsamp + 0.5),
+ * evaluated on the host in IEEE float64 in that order, fref = the highest
+ * channel frequency.  Sub-band s is the run of nchan/nsub contiguous channels
+ * starting at s*nchan/nsub; its reference frequency is its highest channel.
+ * The fine trials are cut into consecutive groups of g; a group's coarse DM is
+ * its first trial.  g = 1 + floor((a_full / a_max) / 2), capped at ndm, where
+ * a = 1/f_lo^2 - 1/f_hi^2 over the whole band (a_full) and over the widest
+ * sub-band (a_max): the coarse-DM error inside a sub-band then stays within
+ * the full-band delay change of half a fine DM step.  With one channel per
+ * sub-band, g = ndm (exact).
+ *
+ * The plan's tables are uploaded to the current device.  On success *out
+ * holds a new plan that the caller releases with tx_plan_destroy.
+ * Errors: TX_EINVAL (bad argument), TX_EOVERFLOW (a delay >= 2^30 samples),
+ * TX_ENOMEM, TX_EDEVICE (no usable device or upload failed).
+ */
+tx_status tx_plan(const double* freqs_mhz, int32_t nchan, double tsamp_s,
+                  const double* dms, int32_t ndm, int32_t nsub, tx_plan_t* out);
+
+/*
+ * tx_plan_ex: tx_plan with two overrides.
+ *   dms_per_group  0 = the rule above; otherwise g itself (1 gives brute
+ *                  force: every trial is its own coarse DM).  Clamped to ndm.
+ *   flags          TX_PLAN_HOST_ONLY builds the host tables without touching
+ *                  any device (such a plan answers queries only; device calls
+ *                  on it return TX_ESTATE).
+ */
+tx_status tx_plan_ex(const double* freqs_mhz, int32_t nchan, double tsamp_s,
+                     const double* dms, int32_t ndm, int32_t nsub,
+                     int32_t dms_per_group, uint32_t flags, tx_plan_t* out);
+
+typedef struct tx_plan_info {
+    int32_t nchan;        /* channels */
+    int32_t ndm;          /* fine DM trials */
+    int32_t nsub;         /* sub-bands (after the automatic choice) */
+    int32_t chans_per_sub;/* nchan / nsub */
+    int32_t g;            /* fine trials per coarse group */
+    int32_t ngroups;      /* coarse groups = ceil(ndm / g) */
+    int64_t overlap;      /* O: input samples needed beyond the output length */
+    int64_t max_extent;   /* largest extra length of a first-stage series */
+    int64_t brute_reach;  /* D(max DM, lowest frequency) */
+    double fref_mhz;      /* reference frequency (highest channel) */
+    double tsamp_s;
+    int32_t on_device;    /* 1 if the tables live on a device */
+    int32_t device;       /* that device's ordinal, or -1 */
+} tx_plan_info;
+
+/* Fill *info.  Errors: TX_EINVAL on NULL arguments. */
+tx_status tx_plan_query(tx_plan_t plan, tx_plan_info* info);
+
+/*
+ * Effective per-(trial, channel) offsets host_off[ndm * nchan] (row-major by
+ * trial):  off(i, ch) = D(c_j, f_ch) + D(dm_i, f_s) - D(c_j, f_s), with j the
+ * group of trial i and s the sub-band of ch.  The two stages compute exactly
+ * Y[i][t] = sum over ch of x[ch][t + off(i, ch)].  Host memory, caller-owned.
+ */
+tx_status tx_plan_offsets(tx_plan_t plan, int32_t* host_off);
+
+/*
+ * Host copies of the plan tables; any pointer may be NULL.
+ *   coarse_chan[ngroups * nchan] = D(c_j, f_ch)
+ *   coarse_sub [ngroups * nsub]  = D(c_j, f_s)
+ *   fine_sub   [ndm * nsub]      = D(dm_i, f_s)
+ *   extent     [ngroups * nsub]  = max over i in j of D(dm_i, f_s) - D(c_j, f_s)
+ */
+tx_status tx_plan_tables(tx_plan_t plan, int32_t* coarse_chan, int32_t* coarse_sub,
+                         int32_t* fine_sub, int32_t* extent);
+
+/* Brute-force delays host_delay[nchan] = D(dm, f_ch) for one DM (>= 0). */
+tx_status tx_plan_delays(tx_plan_t plan, double dm, int32_t* host_delay);
+
+/* Release a plan.  The caller must not use it afterwards, nor destroy it while
+ * device work that uses it is still queued.  NULL is accepted. */
+tx_status tx_plan_destroy(tx_plan_t plan);
+
+/* ------------------------------------------------------------------------ */
+/* Stateless dedispersion (Sec. 2.3)                                         */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Bytes of device scratch that tx_dedisperse_ws needs for output length nt
+ * (the first-stage series of every coarse group and sub-band, uint16).
+ */
+tx_status tx_dedisperse_ws_size(tx_plan_t plan, int64_t nt, int64_t* bytes);
+
+/*
+ * tx_dedisperse: Y = two-stage sub-band dedispersion of one block.
+ *
+ *   d_in      uint8, nchan rows; row c starts at d_in + c*in_pitch and holds
+ *             at least nt + overlap valid samples (overlap from
+ *             tx_plan_query).  d_in and in_pitch must be multiples of 16.
+ *   nt        output samples per trial, >= 0 (0 queues nothing).
+ *   d_out     int32, ndm rows; row i starts at d_out + i*out_pitch elements
+ *             (out_pitch >= nt, a multiple of 2; d_out 8-byte aligned).
+ *             Y[i][t] = sum over s of B[j][s][t + D(dm_i,f_s) - D(c_j,f_s)],
+ *             B[j][s][u] = sum over ch in s of x[ch][u + D(c_j, f_ch)].
+ *   stream    HIP stream for all work.
+ *
+ * Every value is an exact integer sum (bit-exact for any tiling).  Scratch for
+ * the first stage comes from the device's stream-ordered memory pool and is
+ * returned to it on the same stream.
+ * Errors: TX_EINVAL, TX_ESTATE (host-only plan or another device current),
+ * TX_ENOMEM, TX_EDEVICE.
+ */
+tx_status tx_dedisperse(tx_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t nt,
+                        int32_t* d_out, int64_t out_pitch, hipStream_t stream);
+
+/* tx_dedisperse with caller-provided scratch d_ws of ws_bytes bytes
+ * (>= tx_dedisperse_ws_size, 256-byte aligned).  The scratch must not be used
+ * by other work on any stream until this call's work has finished. */
+tx_status tx_dedisperse_ws(tx_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t nt,
+                           int32_t* d_out, int64_t out_pitch, void* d_ws, int64_t ws_bytes,
+                           hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Matched filter (Sec. 2.4) and DM-time candidates (Sec. 2.5)               */
+/* ------------------------------------------------------------------------ */
+
+/* One thresholded point of the DM-time plane. */
+typedef struct tx_cand {
+    int32_t dm_index;  /* row of the DM x time array */
+    int32_t width;     /* boxcar width with the highest S/N at this point */
+    int64_t time;      /* first sample of the boxcar window */
+    double snr;        /* its S/N */
+} tx_cand;
+
+#define TX_MAX_WIDTHS 32
+#define TX_MAX_WIDTH 1024
+#define TX_MAX_NT_BOXCAR (1 << 20)
+#define TX_MAX_VALUE (1 << 21)
+
+/*
+ * tx_boxcar_snr: peak boxcar S/N of every row of a DM x time array.
+ *
+ *   d_dmt     int32 rows, row d at d_dmt + d*pitch elements, nt valid values,
+ *             each value in [0, 2^21) (any dedispersed block of <= 8224
+ *             channels).  A row holding a value outside that range yields
+ *             snr = NaN, width = -1, time = -1.
+ *   ndm, nt   rows and samples per row; 1 <= nt <= 2^20.
+ *   widths    HOST array of nw (1..32) strictly increasing widths in [1, 1024].
+ *   d_snr, d_width, d_time  device outputs [ndm].
+ *
+ * Per row (Sec. 2.4 Eq. 5, readings stated): the window of width w starting at
+ * t holds samples [t, t+w) and must lie inside the row; its sum S comes from
+ * the running sum of the row (uint32, exact as a difference).  The noise
+ * sigma is the population standard deviation of the row: c = floor(sum/nt),
+ * Q = sum (y - c)^2, r = sum - nt*c, var = Q/nt - (r/nt)^2 in float64; then
+ * snr = ((double)(nt*S - w*sum) * (1/(sigma*nt))) * (1/sqrt(w)).
+ * For each width the earliest t with the largest S is taken; the width with
+ * the largest S/N wins, ties to the smaller width.  A row with var <= 0, or
+ * with every width > nt, gives (0.0, widths[0], 0).
+ */
+tx_status tx_boxcar_snr(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64_t pitch,
+                        const int32_t* widths, int32_t nw,
+                        double* d_snr, int32_t* d_width, int64_t* d_time, hipStream_t stream);
+
+/*
+ * tx_candidates: the thresholded DM-time plane (Sec. 2.5).  For every row d
+ * and start t, w* is the width with the highest S/N at t (ties to the smaller
+ * width, only windows inside the row); (d, t, w*, snr) is emitted when
+ * snr >= gamma.  Rows with var <= 0 emit nothing.  Inputs as tx_boxcar_snr;
+ * gamma must be finite.
+ *
+ *   d_out[cap]   device array of records, in no particular order (sort by
+ *                (dm_index, time) on the host for a canonical list).
+ *   d_count      device int64: set to the total number of points found, even
+ *                when it exceeds cap (only the first cap found are stored).
+ *   d_snr, d_width, d_time  optional (NULL or all three): the per-row peaks
+ *                of tx_boxcar_snr, computed in the same pass.
+ */
+tx_status tx_candidates(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64_t pitch,
+                        const int32_t* widths, int32_t nw, double gamma,
+                        tx_cand* d_out, int64_t cap, int64_t* d_count,
+                        double* d_snr, int32_t* d_width, int64_t* d_time, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Kernels whose launches can be timed. */
+typedef enum tx_kernel {
+    TX_KERNEL_STAGE1 = 0,   /* first stage: sub-bands at the coarse DMs */
+    TX_KERNEL_STAGE2 = 1,   /* second stage: fine DMs from the sub-band series */
+    TX_KERNEL_BOXCAR = 2,   /* boxcar S/N, peaks and candidates */
+    TX_KERNEL_COUNT = 3
+} tx_kernel;
+
+/*
+ * tx_profile_enable: when on != 0, every later kernel launch of libtx is
+ * bracketed by two hipEvents recorded on the launch's own stream (process-wide
+ * switch; adds two event records per launch).  Turning it off keeps what was
+ * recorded.
+ */
+tx_status tx_profile_enable(int32_t on);
+
+/*
+ * tx_profile_collect: wait for the recorded events of one kernel, return the
+ * summed elapsed time in milliseconds and the number of launches, and forget
+ * them.  Host-blocking.  Errors: TX_EINVAL (bad kernel id or NULL), TX_EDEVICE.
+ */
+tx_status tx_profile_collect(int32_t kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TX_H */

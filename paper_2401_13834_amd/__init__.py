@@ -1,0 +1,251 @@
+"""Python binding of libtx (include/tx.h): argument marshalling only.
+
+Every computation runs in the HIP library ``libtx.so`` built in this
+directory (``python -m paper_2401_13834_amd.build``).  If the library is not
+built, importing the binding's functions raises; there is no fallback.
+
+Device buffers are passed as torch tensors (only their ``data_ptr()`` and
+shape are used); streams are torch streams or raw ``hipStream_t`` integers.
+The names mirror the C entry points.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtx.so")
+
+TX_OK = 0
+STATUS = {0: "TX_OK", -1: "TX_EINVAL", -2: "TX_ENOMEM", -3: "TX_EDEVICE", -4: "TX_ESTATE",
+          -5: "TX_EOVERFLOW", -6: "TX_ENOTSUP"}
+TX_PLAN_HOST_ONLY = 1
+TX_MAX_WIDTHS = 32
+
+CAND_DTYPE = np.dtype([("dm_index", "<i4"), ("width", "<i4"), ("time", "<i8"), ("snr", "<f8")])
+
+_c_i32p = ctypes.POINTER(ctypes.c_int32)
+_c_dblp = ctypes.POINTER(ctypes.c_double)
+
+
+class TxError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("nchan", ctypes.c_int32), ("ndm", ctypes.c_int32), ("nsub", ctypes.c_int32),
+                ("chans_per_sub", ctypes.c_int32), ("g", ctypes.c_int32), ("ngroups", ctypes.c_int32),
+                ("overlap", ctypes.c_int64), ("max_extent", ctypes.c_int64), ("brute_reach", ctypes.c_int64),
+                ("fref_mhz", ctypes.c_double), ("tsamp_s", ctypes.c_double), ("on_device", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "tx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "tx_version": (ctypes.c_char_p, []),
+    "tx_plan": (ctypes.c_int, [_c_dblp, ctypes.c_int32, ctypes.c_double, _c_dblp, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_void_p)]),
+    "tx_plan_ex": (ctypes.c_int, [_c_dblp, ctypes.c_int32, ctypes.c_double, _c_dblp, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
+    "tx_plan_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_PlanInfo)]),
+    "tx_plan_offsets": (ctypes.c_int, [ctypes.c_void_p, _c_i32p]),
+    "tx_plan_tables": (ctypes.c_int, [ctypes.c_void_p, _c_i32p, _c_i32p, _c_i32p, _c_i32p]),
+    "tx_plan_delays": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, _c_i32p]),
+    "tx_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "tx_dedisperse_ws_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "tx_dedisperse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "tx_dedisperse_ws": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p]),
+    "tx_boxcar_snr": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _c_i32p,
+                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "tx_candidates": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _c_i32p,
+                                     ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "tx_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
+    "tx_profile_collect": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int64)]),
+}
+
+TX_KERNEL_STAGE1, TX_KERNEL_STAGE2, TX_KERNEL_BOXCAR = 0, 1, 2
+
+
+def lib():
+    """The loaded libtx (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_13834_amd.build`")
+        # torch ships its own HIP runtime under the same soname.  Load it first
+        # so that libtx binds to that one runtime: torch's streams and device
+        # memory are then valid in libtx, and only one runtime owns the GPU.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def _check(status, what):
+    if status != TX_OK:
+        raise TxError(status, what)
+
+
+def _dbl(arr):
+    a = np.ascontiguousarray(arr, dtype=np.float64)
+    return a, a.ctypes.data_as(_c_dblp)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Owner of a ``tx_plan_t``."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+        info = _PlanInfo()
+        _check(lib().tx_plan_query(self._h, ctypes.byref(info)), "tx_plan_query")
+        self.info = {f: getattr(info, f) for f, _ in _PlanInfo._fields_}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __getattr__(self, name):
+        info = self.__dict__.get("info")
+        if info is not None and name in info:
+            return info[name]
+        raise AttributeError(name)
+
+    def offsets(self):
+        out = np.empty((self.info["ndm"], self.info["nchan"]), dtype=np.int32)
+        _check(lib().tx_plan_offsets(self._h, out.ctypes.data_as(_c_i32p)), "tx_plan_offsets")
+        return out
+
+    def tables(self):
+        i = self.info
+        cc = np.empty((i["ngroups"], i["nchan"]), dtype=np.int32)
+        cs = np.empty((i["ngroups"], i["nsub"]), dtype=np.int32)
+        fs = np.empty((i["ndm"], i["nsub"]), dtype=np.int32)
+        ex = np.empty((i["ngroups"], i["nsub"]), dtype=np.int32)
+        _check(lib().tx_plan_tables(self._h, *(a.ctypes.data_as(_c_i32p) for a in (cc, cs, fs, ex))),
+               "tx_plan_tables")
+        return {"coarse_chan": cc, "coarse_sub": cs, "fine_sub": fs, "extent": ex}
+
+    def delays(self, dm):
+        out = np.empty(self.info["nchan"], dtype=np.int32)
+        _check(lib().tx_plan_delays(self._h, float(dm), out.ctypes.data_as(_c_i32p)), "tx_plan_delays")
+        return out
+
+    def ws_size(self, nt):
+        b = ctypes.c_int64()
+        _check(lib().tx_dedisperse_ws_size(self._h, int(nt), ctypes.byref(b)), "tx_dedisperse_ws_size")
+        return b.value
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().tx_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tx_plan(freqs_mhz, tsamp_s, dms, nsub, *, dms_per_group=0, host_only=False):
+    f, fp = _dbl(freqs_mhz)
+    d, dp = _dbl(dms)
+    h = ctypes.c_void_p()
+    flags = TX_PLAN_HOST_ONLY if host_only else 0
+    _check(lib().tx_plan_ex(fp, len(f), float(tsamp_s), dp, len(d), int(nsub), int(dms_per_group), flags,
+                            ctypes.byref(h)), "tx_plan")
+    return Plan(h.value)
+
+
+def tx_dedisperse(plan, d_in, nt, d_out, stream=None, ws=None):
+    """d_in: uint8 device tensor [nchan, in_pitch]; d_out: int32 [ndm, out_pitch]."""
+    in_pitch = d_in.stride(0) * d_in.element_size()
+    out_pitch = d_out.stride(0)
+    if ws is None:
+        st = lib().tx_dedisperse(plan.handle, _ptr(d_in), in_pitch, int(nt), _ptr(d_out), out_pitch,
+                                 _stream(stream))
+    else:
+        st = lib().tx_dedisperse_ws(plan.handle, _ptr(d_in), in_pitch, int(nt), _ptr(d_out), out_pitch,
+                                    _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
+    _check(st, "tx_dedisperse")
+
+
+def _widths(widths):
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    return w, w.ctypes.data_as(_c_i32p)
+
+
+def tx_boxcar_snr(dmt, nt, widths, snr, width, time, stream=None):
+    """dmt: int32 device tensor [ndm, pitch]; outputs float64/int32/int64 device [ndm]."""
+    w, wp = _widths(widths)
+    _check(lib().tx_boxcar_snr(_ptr(dmt), dmt.shape[0], int(nt), dmt.stride(0), wp, len(w), _ptr(snr),
+                               _ptr(width), _ptr(time), _stream(stream)), "tx_boxcar_snr")
+
+
+def tx_candidates(dmt, nt, widths, gamma, cands, count, peaks=None, stream=None):
+    """cands: device tensor of at least cap*24 bytes (uint8 [cap, 24] or int64 [cap, 3]);
+    count: int64 device tensor [1]; peaks: optional (snr, width, time) device tensors."""
+    w, wp = _widths(widths)
+    cap = (cands.numel() * cands.element_size()) // CAND_DTYPE.itemsize
+    if peaks is None:
+        p = (ctypes.c_void_p(0),) * 3
+    else:
+        p = tuple(_ptr(t) for t in peaks)
+    _check(lib().tx_candidates(_ptr(dmt), dmt.shape[0], int(nt), dmt.stride(0), wp, len(w), float(gamma),
+                               _ptr(cands), cap, _ptr(count), *p, _stream(stream)), "tx_candidates")
+
+
+def parse_candidates(raw, count):
+    """Host view of candidate records (first min(count, cap) of them), sorted by (dm_index, time)."""
+    buf = np.ascontiguousarray(raw).view(np.uint8).reshape(-1)
+    rec = buf[: (buf.size // CAND_DTYPE.itemsize) * CAND_DTYPE.itemsize].view(CAND_DTYPE)
+    rec = rec[: min(int(count), rec.size)].copy()
+    return np.sort(rec, order=["dm_index", "time"])
+
+
+def tx_profile_enable(on=True):
+    _check(lib().tx_profile_enable(1 if on else 0), "tx_profile_enable")
+
+
+def tx_profile_collect(kernel):
+    """(total milliseconds, launches) of one kernel since the last collect."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().tx_profile_collect(int(kernel), ctypes.byref(ms), ctypes.byref(n)), "tx_profile_collect")
+    return ms.value, n.value

@@ -1,0 +1,120 @@
+"""Host-side checks of libtx: the library loads and exports every declared
+entry point, and the host plan (delay tables, groups, offsets, overlap)
+equals the oracle's bit for bit.  No device calls."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2401_13834_amd as tx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tx.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tx_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tx.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(tx.exported_names()) | set(dir(L))
+    assert L.tx_version().decode().startswith("libtx")
+    assert L.tx_status_str(-1).decode() == "TX_EINVAL"
+
+
+WORKLOADS = ["plain-256", "paper-4096", "served-4096", "octave-8192"]
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_host_plan_equals_oracle(name):
+    wl = synth.workload(name)
+    ref = oracle.make_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    p = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub, host_only=True)
+    assert (p.nsub, p.g, p.ngroups, p.overlap) == (ref.nsub, ref.g, ref.ngroups, ref.overlap)
+    assert p.max_extent == int(ref.extent.max())
+    assert p.on_device == 0
+    t = p.tables()
+    assert np.array_equal(t["coarse_chan"], ref.d_coarse_chan)
+    assert np.array_equal(t["coarse_sub"], ref.d_coarse_sub)
+    assert np.array_equal(t["fine_sub"], ref.d_fine_sub)
+    assert np.array_equal(t["extent"], ref.extent)
+    if ref.ndm * ref.nchan <= 16 * 1024 * 1024:
+        assert np.array_equal(p.offsets(), ref.offsets)
+    for dm in (0.0, float(wl.dms[len(wl.dms) // 3]), float(wl.dms[-1])):
+        assert np.array_equal(p.delays(dm), oracle.delay_samples(dm, wl.freqs, ref.fref, wl.tsamp))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_host_plan_random_shapes_equal_oracle(seed):
+    rng = np.random.default_rng(seed)
+    nsub = int(rng.choice([1, 2, 3, 4, 8]))
+    m = int(rng.integers(1, 40))
+    nchan = nsub * m
+    freqs = rng.uniform(300.0, 2000.0, nchan)          # any channel order
+    ndm = int(rng.integers(1, 60))
+    dms = np.sort(rng.uniform(0.0, 2000.0, ndm))
+    dms[rng.random(ndm) < 0.1] = 0.0
+    dms = np.sort(dms)
+    tsamp = float(rng.uniform(5e-5, 1e-3))
+    g = int(rng.choice([0, 1, 2, 5, 1000]))
+    ref = oracle.make_plan(freqs, tsamp, dms, nsub, g=None if g == 0 else g)
+    p = tx.tx_plan(freqs, tsamp, dms, nsub, dms_per_group=g, host_only=True)
+    assert (p.g, p.ngroups, p.overlap) == (ref.g, ref.ngroups, ref.overlap)
+    assert np.array_equal(p.offsets(), ref.offsets)
+    assert np.array_equal(p.tables()["extent"], ref.extent)
+
+
+def test_automatic_subband_count_minimises_additions():
+    wl = synth.workload("paper-4096")
+    p = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, 0, host_only=True)
+    nchan, ndm = len(wl.freqs), len(wl.dms)
+
+    def cost(ns):
+        g = oracle.group_size_rule(wl.freqs, ns, ndm)
+        return -(-ndm // g) * nchan + ndm * ns
+
+    cands = [ns for ns in range(1, nchan + 1) if nchan % ns == 0 and nchan // ns <= 256]
+    assert p.nsub in cands
+    assert cost(p.nsub) == min(cost(ns) for ns in cands)
+
+
+def _status(fn):
+    with pytest.raises(tx.TxError) as e:
+        fn()
+    return e.value.status
+
+
+def test_plan_argument_errors():
+    f = synth.band_centres(1712, 856, 64)
+    d = np.arange(10) * 5.0
+    assert _status(lambda: tx.tx_plan(f, 1e-4, d, 7, host_only=True)) == -1          # nsub does not divide
+    assert _status(lambda: tx.tx_plan(np.tile(f, 8), 1e-4, d, 1, host_only=True)) == -1  # 512 chans per sub-band
+    assert _status(lambda: tx.tx_plan(f, 0.0, d, 8, host_only=True)) == -1
+    assert _status(lambda: tx.tx_plan(f, 1e-4, d[::-1], 8, host_only=True)) == -1     # decreasing
+    assert _status(lambda: tx.tx_plan(f, 1e-4, -d, 8, host_only=True)) == -1
+    assert _status(lambda: tx.tx_plan(f, 1e-4, np.array([]), 8, host_only=True)) == -1
+    bad = f.copy()
+    bad[3] = np.nan
+    assert _status(lambda: tx.tx_plan(bad, 1e-4, d, 8, host_only=True)) == -1
+    assert _status(lambda: tx.tx_plan(f * 0.01, 1e-7, d * 1e4, 8, host_only=True)) == -5  # delay overflow
+
+
+def test_device_calls_on_host_only_plan_are_refused():
+    f = synth.band_centres(1712, 856, 64)
+    p = tx.tx_plan(f, 1e-4, np.arange(10) * 5.0, 8, host_only=True)
+    L = tx.lib()
+    st = L.tx_dedisperse(p.handle, 16, 4096, 8, 16, 8, None)
+    assert st == -4
+    with pytest.raises(tx.TxError):
+        p.delays(-1.0)

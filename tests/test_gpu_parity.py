@@ -1,0 +1,290 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Dedispersion outputs and candidate indices must be bit-exact; S/N values are
+compared for exact equality of the float64 results (the stated tolerance is
+1e-5 relative; the kernels evaluate the same IEEE expressions in the same
+order, so they agree exactly)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2401_13834_amd as tx
+from gpu_helpers import (as_tuples, device_block, gpu_candidates, gpu_dedisperse, gpu_peaks, round_up,
+                         torch_cuda)
+
+pytestmark = pytest.mark.gpu
+
+SNR_RTOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _assert_snr(got, want):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    assert np.allclose(got, want, rtol=SNR_RTOL, atol=1e-12, equal_nan=True)
+    # and exactly equal in practice: same IEEE operations in the same order
+    assert np.array_equal(got, want, equal_nan=True)
+
+
+# ---------------------------------------------------------------------------
+# Dedispersion on small random shapes (several tiles, ragged tails)
+# ---------------------------------------------------------------------------
+
+SHAPES = [
+    # (nchan, nsub, ndm, g, nt, f_top, f_bot, tsamp, dm_max, data)
+    (64, 8, 40, 0, 3000, 1712.0, 856.0, 306.24e-6, 300.0, "uniform"),
+    (256, 16, 128, 0, 8192, 1712.0, 856.0, 306.24e-6, 508.0, "uniform"),
+    (96, 12, 57, 0, 1025, 1500.0, 1100.0, 1e-3, 1200.0, "uniform"),
+    (48, 48, 33, 0, 777, 1500.0, 1100.0, 5e-4, 900.0, "uniform"),      # one channel per sub-band
+    (128, 8, 50, 1, 2049, 1400.0, 1000.0, 2e-4, 150.0, "uniform"),     # g = 1: brute force
+    (512, 2, 70, 0, 1500, 1712.0, 856.0, 153.12e-6, 200.0, "max"),     # 256 channels of 255 per sub-band
+    (1, 1, 5, 0, 300, 1400.0, 1400.0, 1e-3, 10.0, "uniform"),
+    (200, 10, 300, 20, 4100, 1712.0, 856.0, 153.12e-6, 600.0, "uniform"),  # g = 20: several trial chunks
+    (64, 4, 17, 0, 1, 1712.0, 856.0, 306.24e-6, 100.0, "uniform"),     # a single output sample
+    (320, 32, 240, 0, 5000, 1088.0, 544.0, 153.12e-6, 2000.0, "normal"),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"s{i}" for i in range(len(SHAPES))])
+def test_dedisperse_matches_oracle_small(shape):
+    nchan, nsub, ndm, g, nt, ft, fb, ts, dmmax, data = shape
+    _say(f"dedisperse shape={shape}")
+    freqs = synth.band_centres(ft, fb, nchan)
+    dms = np.linspace(0.0, dmmax, ndm)
+    ref = oracle.make_plan(freqs, ts, dms, nsub, g=None if g == 0 else g)
+    plan = tx.tx_plan(freqs, ts, dms, nsub, dms_per_group=g)
+    assert (plan.g, plan.overlap) == (ref.g, ref.overlap)
+    n = nt + ref.overlap
+    if data == "max":
+        x = np.full((nchan, n), 255, dtype=np.uint8)
+    elif data == "normal":
+        x = synth.normal_u8(nchan, n, 7)
+    else:
+        x = synth.uniform_u8(nchan, n, nchan + ndm)
+    want = oracle.dedisperse_subband(x, ref, nt)
+    got = gpu_dedisperse(plan, x, nt, out_pitch=round_up(nt, 2) + 64)
+    assert np.array_equal(got[:, :nt], want)
+    assert np.all(got[:, nt:] == -7)          # nothing written past nt
+    got_ws = gpu_dedisperse(plan, x, nt, ws=True)
+    assert np.array_equal(got_ws[:, :nt], want)
+
+
+def test_dedisperse_exact_input_length_and_pitch():
+    """Rows holding exactly nt + overlap valid bytes (the rest of the pitch is
+    garbage) give the same result: the kernels read nothing past nt + O."""
+    torch = torch_cuda()
+    freqs = synth.band_centres(1712.0, 856.0, 64)
+    dms = np.linspace(0, 400, 30)
+    ref = oracle.make_plan(freqs, 306.24e-6, dms, 8)
+    plan = tx.tx_plan(freqs, 306.24e-6, dms, 8)
+    nt = 2500
+    x = synth.uniform_u8(64, nt + ref.overlap, 3)
+    d = device_block(x, pitch=round_up(nt + ref.overlap, 16) + 512)
+    d[:, nt + ref.overlap:] = 201
+    got = gpu_dedisperse(plan, x, nt, d_in=d)
+    assert np.array_equal(got[:, :nt], oracle.dedisperse_subband(x, ref, nt))
+    del torch
+
+
+def test_dedisperse_rejects_bad_arguments():
+    torch = torch_cuda()
+    freqs = synth.band_centres(1712.0, 856.0, 64)
+    plan = tx.tx_plan(freqs, 306.24e-6, np.linspace(0, 400, 30), 8)
+    nt = 100
+    good = torch.zeros((64, round_up(nt + plan.overlap, 256)), dtype=torch.uint8, device="cuda")
+    out = torch.zeros((30, nt), dtype=torch.int32, device="cuda")
+    short = torch.zeros((64, round_up(nt + plan.overlap, 16) - 16), dtype=torch.uint8, device="cuda")
+    with pytest.raises(tx.TxError):
+        tx.tx_dedisperse(plan, short, nt, out)
+    with pytest.raises(tx.TxError):
+        tx.tx_dedisperse(plan, good[:, 1:], nt, out)   # misaligned rows
+    tx.tx_dedisperse(plan, good, 0, out)               # nt = 0 queues nothing
+    torch.cuda.synchronize()
+
+
+def test_dedisperse_is_deterministic():
+    wl = synth.workload("plain-256")
+    plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    x = synth.uniform_u8(256, wl.nt + plan.overlap, 9)
+    d = device_block(x)
+    a = gpu_dedisperse(plan, x, wl.nt, d_in=d)
+    b = gpu_dedisperse(plan, x, wl.nt, d_in=d)
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# Boxcar S/N and candidates on synthetic series
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nt,seed", [(1, 0), (5, 1), (4096, 2), (4097, 3), (10000, 4), (70001, 5)])
+def test_boxcar_peaks_match_oracle(nt, seed):
+    torch = torch_cuda()
+    _say(f"boxcar nt={nt}")
+    rng = np.random.default_rng(seed)
+    rows = 24
+    Y = rng.integers(0, 60, size=(rows, nt)).astype(np.int32)
+    Y[1] = 7                                        # zero variance
+    Y[2, :] = rng.integers(0, 2, size=nt) * (2 ** 21 - 1)   # extreme values
+    Y[3, nt // 2] += 5000 if nt > 2 else 0          # a spike
+    Y[4, :min(nt, 64)] += 300                       # a wide pulse at the start
+    Y[5, -min(nt, 3):] += 400                       # a pulse at the very end
+    widths = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024]
+    d = torch.from_numpy(Y).to("cuda")
+    snr, wid, tim = gpu_peaks(d, nt, widths)
+    want = oracle.boxcar_peaks(Y, widths)
+    _assert_snr(snr, want[0])
+    assert np.array_equal(wid, want[1])
+    assert np.array_equal(tim, want[2])
+
+
+def test_boxcar_out_of_range_rows_are_flagged():
+    torch = torch_cuda()
+    Y = np.random.default_rng(3).integers(0, 100, size=(3, 500)).astype(np.int32)
+    Y[0, 10] = -1
+    Y[2, 499] = 2 ** 21
+    snr, wid, tim = gpu_peaks(torch.from_numpy(Y).to("cuda"), 500, [1, 4])
+    assert np.isnan(snr[0]) and wid[0] == -1 and tim[0] == -1
+    assert np.isnan(snr[2]) and wid[2] == -1
+    want = oracle.boxcar_peak(Y[1], [1, 4])
+    assert (snr[1], wid[1], tim[1]) == want
+
+
+@pytest.mark.parametrize("gamma", [2.5, 4.0, 6.0])
+def test_candidates_match_oracle(gamma):
+    torch = torch_cuda()
+    rng = np.random.default_rng(int(gamma * 10))
+    rows, nt = 16, 9000
+    Y = np.rint(1000 + 30 * rng.standard_normal((rows, nt))).astype(np.int32)
+    Y[3, 4000:4008] += 200
+    Y[9, 8990:] += 150
+    Y[11] = 5
+    widths = [1, 2, 4, 8, 16, 32]
+    d = torch.from_numpy(Y).to("cuda")
+    n, rec, peaks = gpu_candidates(d, nt, widths, gamma, with_peaks=True)
+    want = oracle.boxcar_candidates(Y, widths, gamma)
+    assert n == len(want)
+    got = as_tuples(rec)
+    assert [g[:3] for g in got] == [w[:3] for w in want]
+    _assert_snr([g[3] for g in got], [w[3] for w in want])
+    wp = oracle.boxcar_peaks(Y, widths)
+    _assert_snr(peaks[0], wp[0])
+    assert np.array_equal(peaks[1], wp[1]) and np.array_equal(peaks[2], wp[2])
+
+
+def test_candidate_count_exceeds_cap():
+    torch = torch_cuda()
+    rng = np.random.default_rng(8)
+    Y = rng.integers(0, 50, size=(8, 3000)).astype(np.int32)
+    d = torch.from_numpy(Y).to("cuda")
+    want = oracle.boxcar_candidates(Y, [1, 2, 4], 1.0)
+    assert len(want) > 100
+    n, rec = gpu_candidates(d, 3000, [1, 2, 4], 1.0, cap=100)
+    assert n == len(want) and len(rec) == 100
+    assert set(as_tuples(rec)) <= set(want)
+    n0, rec0 = gpu_candidates(d, 3000, [1, 2, 4], 1.0, cap=0)
+    assert n0 == len(want) and len(rec0) == 0
+
+
+# ---------------------------------------------------------------------------
+# The benchmark workloads
+# ---------------------------------------------------------------------------
+
+def _inject(wl, ref, nchan):
+    pulses = []
+    for spec in wl.pulses:
+        kind, dm, t0, w = spec[0], spec[1], spec[2], spec[3]
+        start = t0 + oracle.delay_samples(dm, wl.freqs, ref.fref, wl.tsamp)
+        if kind == "snr-index":
+            amp = synth.spectral_amplitudes(wl.freqs, 816.0, -1.5, 1.0)
+            amp = amp * (16.0 * spec[4] / np.sqrt(w) / amp.sum())
+        else:
+            amp = synth.pulse_amplitude(spec, w, nchan)
+        pulses.append((start, w, amp))
+    return pulses
+
+
+def test_plain256_end_to_end_matches_oracle():
+    torch = torch_cuda()
+    wl = synth.workload("plain-256")
+    ref = oracle.make_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    x = synth.normal_u8(256, wl.nt + ref.overlap, wl.seed, pulses=_inject(wl, ref, 256))
+    want = oracle.dedisperse_subband(x, ref, wl.nt)
+    got = gpu_dedisperse(plan, x, wl.nt)
+    assert np.array_equal(got, want)
+    d = torch.from_numpy(got).to("cuda")
+    n, rec, peaks = gpu_candidates(d, wl.nt, wl.widths, wl.gamma, with_peaks=True)
+    wp = oracle.boxcar_peaks(want, wl.widths)
+    _assert_snr(peaks[0], wp[0])
+    assert np.array_equal(peaks[1], wp[1]) and np.array_equal(peaks[2], wp[2])
+    assert int(np.argmax(peaks[0])) == 50
+    wc = oracle.boxcar_candidates(want, wl.widths, wl.gamma)
+    assert n == len(wc)
+    got_c = as_tuples(rec)
+    assert [c[:3] for c in got_c] == [c[:3] for c in wc]
+    _assert_snr([c[3] for c in got_c], [c[3] for c in wc])
+
+
+def _full_size_check(name, rows_to_check):
+    torch = torch_cuda()
+    wl = synth.workload(name)
+    ref = oracle.make_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    nchan = len(wl.freqs)
+    _say(f"{name}: generating input {nchan} x {wl.nt + ref.overlap}")
+    x = synth.pooled_normal_u8(nchan, wl.nt + ref.overlap, wl.seed, pulses=_inject(wl, ref, nchan))
+    d_in = device_block(x)
+    out = torch.empty((plan.ndm, wl.nt), dtype=torch.int32, device="cuda")
+    _say(f"{name}: dedisperse on GPU")
+    tx.tx_dedisperse(plan, d_in, wl.nt, out)
+    n, rec, peaks = gpu_candidates(out, wl.nt, wl.widths, wl.gamma, with_peaks=True)
+    torch.cuda.synchronize()
+    rows = sorted(set(int(r) for r in rows_to_check(ref)))
+    got_rows = out[rows].cpu().numpy()
+    del out, d_in
+    _say(f"{name}: oracle on rows {rows}")
+    want_rows = oracle.dedisperse_offsets(x, ref.offsets[rows], wl.nt)
+    assert np.array_equal(got_rows, want_rows)
+    wp = oracle.boxcar_peaks(want_rows, wl.widths)
+    _assert_snr(peaks[0][rows], wp[0])
+    assert np.array_equal(peaks[1][rows], wp[1]) and np.array_equal(peaks[2][rows], wp[2])
+    wc = oracle.boxcar_candidates(want_rows, wl.widths, wl.gamma)
+    wc = [(rows[d], t, w, s) for (d, t, w, s) in wc]
+    got_c = [c for c in as_tuples(rec) if c[0] in set(rows)]
+    assert n < (1 << 20)
+    assert [c[:3] for c in got_c] == [c[:3] for c in wc]
+    _assert_snr([c[3] for c in got_c], [c[3] for c in wc])
+    return peaks
+
+
+def _pulse_rows(ref, wl):
+    rows = [0, ref.ndm - 1, ref.g, ref.g - 1 if ref.g > 1 else 1]
+    for spec in wl.pulses:
+        i = int(np.argmin(np.abs(ref.dms - spec[1])))
+        rows += [i, max(i - 1, 0)]
+    return rows
+
+
+@pytest.mark.slow
+def test_paper4096_full_size_sampled_rows():
+    wl = synth.workload("paper-4096")
+    _full_size_check("paper-4096", lambda ref: _pulse_rows(ref, wl)[:10] + [1777])
+
+
+@pytest.mark.slow
+def test_served4096_full_size_sampled_rows():
+    _full_size_check("served-4096", lambda ref: [0, 1, 700, 2047])
+
+
+@pytest.mark.slow
+def test_octave8192_full_size_sampled_rows():
+    wl = synth.workload("octave-8192")
+    _full_size_check("octave-8192", lambda ref: _pulse_rows(ref, wl) + [8191])
