@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--workload", default="paper-4096")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed steps, copy the DM x time array once (a plain copy of known size "
+                         "whose HBM counters scale the kernels' counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
@@ -150,6 +153,11 @@ def main():
         ms, n = tx.tx_profile_collect(k)
         kern[name] = {"avg_ms": ms / max(n, 1), "launches": n}
     ncand = int(count.item())
+    if args.copy_probe:
+        y2 = torch.empty_like(y)
+        y2.copy_(y)
+        torch.cuda.synchronize()
+        del y2
 
     value = ndm * nt * args.steps / elapsed
     adds1 = plan.ngroups * nchan * nt                 # first stage: N_c * N_f * T additions

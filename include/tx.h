@@ -53,6 +53,10 @@ const char* tx_status_str(tx_status s);
 /* Version string of the library build. */
 const char* tx_version(void);
 
+/* Text of the last HIP runtime error that made a call on this thread return
+ * TX_EDEVICE or TX_ENOMEM ("" if none).  Owned by the library. */
+const char* tx_last_error(void);
+
 /* ------------------------------------------------------------------------ */
 /* Plans (Sec. 2.3)                                                          */
 /* ------------------------------------------------------------------------ */
@@ -190,6 +194,33 @@ tx_status tx_dedisperse(tx_plan_t plan, const uint8_t* d_in, int64_t in_pitch, i
 tx_status tx_dedisperse_ws(tx_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t nt,
                            int32_t* d_out, int64_t out_pitch, void* d_ws, int64_t ws_bytes,
                            hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Tile shapes (choices of the kernel implementation; results never change)  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct tx_tiles {
+    int32_t stage1;      /* first-stage variant, 0..count-1, or -1 for the default */
+    int32_t stage1_lds;  /* LDS bytes per first-stage workgroup, 0 = default (raised
+                            to what the plan's longest staged row needs) */
+    int32_t stage2;      /* second-stage variant, or -1 */
+    int32_t stage2_lds;  /* LDS bytes per second-stage workgroup, 0 = default */
+} tx_tiles;
+
+/* Number of kernel variants of a stage (1 or 2). */
+tx_status tx_tile_variants(int32_t stage, int32_t* count);
+
+/* Shape of one variant: output samples per workgroup tile, and (stage 1) the
+ * coarse trials each of the workgroup's 4 wavefronts accumulates. */
+tx_status tx_tile_variant_info(int32_t stage, int32_t variant, int32_t* outputs_per_tile,
+                               int32_t* trials_per_wave);
+
+/* Read / replace the plan's tile choice.  Every choice gives bit-identical
+ * output; only speed and scratch size change.  The setter is the one mutation
+ * a plan allows: do not call it while device work using the plan is being
+ * queued from another thread. */
+tx_status tx_plan_get_tiles(tx_plan_t plan, tx_tiles* tiles);
+tx_status tx_plan_set_tiles(tx_plan_t plan, const tx_tiles* tiles);
 
 /* ------------------------------------------------------------------------ */
 /* Matched filter (Sec. 2.4) and DM-time candidates (Sec. 2.5)               */

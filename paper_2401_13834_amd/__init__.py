@@ -33,8 +33,17 @@ _c_dblp = ctypes.POINTER(ctypes.c_double)
 
 class TxError(RuntimeError):
     def __init__(self, status, what):
-        super().__init__(f"{what}: {STATUS.get(status, status)}")
+        detail = ""
+        if status in (-2, -3) and _lib is not None:
+            detail = " (" + (_lib.tx_last_error() or b"").decode() + ")"
+        super().__init__(f"{what}: {STATUS.get(status, status)}{detail}")
         self.status = status
+
+
+class Tiles(ctypes.Structure):
+    """tx_tiles: kernel variant and LDS bytes per workgroup of each stage (-1 / 0 = defaults)."""
+    _fields_ = [("stage1", ctypes.c_int32), ("stage1_lds", ctypes.c_int32), ("stage2", ctypes.c_int32),
+                ("stage2_lds", ctypes.c_int32)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -51,6 +60,7 @@ _lib = None
 _SIGS = {
     "tx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "tx_version": (ctypes.c_char_p, []),
+    "tx_last_error": (ctypes.c_char_p, []),
     "tx_plan": (ctypes.c_int, [_c_dblp, ctypes.c_int32, ctypes.c_double, _c_dblp, ctypes.c_int32, ctypes.c_int32,
                                ctypes.POINTER(ctypes.c_void_p)]),
     "tx_plan_ex": (ctypes.c_int, [_c_dblp, ctypes.c_int32, ctypes.c_double, _c_dblp, ctypes.c_int32, ctypes.c_int32,
@@ -73,6 +83,11 @@ _SIGS = {
                                      ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p]),
+    "tx_tile_variants": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "tx_tile_variant_info": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    "tx_plan_get_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tx_plan_set_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "tx_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "tx_profile_collect": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int64)]),
@@ -166,6 +181,15 @@ class Plan:
         _check(lib().tx_plan_delays(self._h, float(dm), out.ctypes.data_as(_c_i32p)), "tx_plan_delays")
         return out
 
+    def get_tiles(self):
+        t = Tiles()
+        _check(lib().tx_plan_get_tiles(self._h, ctypes.byref(t)), "tx_plan_get_tiles")
+        return (t.stage1, t.stage1_lds, t.stage2, t.stage2_lds)
+
+    def set_tiles(self, stage1=-1, stage1_lds=0, stage2=-1, stage2_lds=0):
+        t = Tiles(stage1, stage1_lds, stage2, stage2_lds)
+        _check(lib().tx_plan_set_tiles(self._h, ctypes.byref(t)), "tx_plan_set_tiles")
+
     def ws_size(self, nt):
         b = ctypes.c_int64()
         _check(lib().tx_dedisperse_ws_size(self._h, int(nt), ctypes.byref(b)), "tx_dedisperse_ws_size")
@@ -249,3 +273,15 @@ def tx_profile_collect(kernel):
     n = ctypes.c_int64()
     _check(lib().tx_profile_collect(int(kernel), ctypes.byref(ms), ctypes.byref(n)), "tx_profile_collect")
     return ms.value, n.value
+
+
+def tx_tile_variants(stage):
+    """[(outputs per tile, trials per wave)] of each variant of a stage (1 or 2)."""
+    n = ctypes.c_int32()
+    _check(lib().tx_tile_variants(int(stage), ctypes.byref(n)), "tx_tile_variants")
+    out = []
+    for v in range(n.value):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().tx_tile_variant_info(int(stage), v, ctypes.byref(a), ctypes.byref(b)), "tx_tile_variant_info")
+        out.append((a.value, b.value))
+    return out

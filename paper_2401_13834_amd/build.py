@@ -1,9 +1,10 @@
-"""Build libtx.so in-tree with hipcc for gfx950.
+"""Build libtx.so (and the tx_peaks microbenchmark) in-tree with hipcc for gfx950.
 
-    python -m paper_2401_13834_amd.build
+    python -m paper_2401_13834_amd.build [-v]
 
-Compiles every source under csrc/ and links them into
-paper_2401_13834_amd/libtx.so.  Always rebuilds.
+Compiles every source under csrc/ (in parallel) and links them into
+paper_2401_13834_amd/libtx.so; builds paper_2401_13834_amd/tx_peaks from
+csrc/tx_peaks.hip.  Always rebuilds.
 """
 
 from __future__ import annotations
@@ -17,9 +18,10 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtx.so")
+PEAKS = os.path.join(HERE, "tx_peaks")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["tx_kernels.hip"]
+HIP_SOURCES = ["tx_kernels_dedisp.hip", "tx_kernels_boxcar.hip"]
 HOST_SOURCES = ["tx_plan.cpp", "tx_api.cpp", "tx_profile.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-result"]
@@ -33,38 +35,41 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def _run(cmd):
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("command failed: " + " ".join(cmd))
-    return r
+def _run_all(cmds, verbose):
+    procs = []
+    for cmd in cmds:
+        if verbose:
+            print(" ".join(cmd))
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    failed = None
+    for cmd, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out)
+            failed = failed or cmd
+    if failed:
+        raise RuntimeError("command failed: " + " ".join(failed))
 
 
 def build(verbose=False):
     cc = hipcc()
-    objs = []
     with tempfile.TemporaryDirectory(prefix="txbuild_") as tmp:
+        objs, cmds = [], []
         for src in HIP_SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            cmd = [cc, "-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj] + COMMON + DEVICE
-            if verbose:
-                print(" ".join(cmd))
-            _run(cmd)
+            cmds.append([cc, "-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj] + COMMON + DEVICE)
             objs.append(obj)
         for src in HOST_SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            cmd = [cc, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + DEVICE
-            if verbose:
-                print(" ".join(cmd))
-            _run(cmd)
+            cmds.append([cc, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + DEVICE)
             objs.append(obj)
+        tmp_peaks = PEAKS + ".tmp"
+        cmds.append([cc, os.path.join(CSRC, "tx_peaks.hip"), "-o", tmp_peaks, "-O3", "-std=c++17"] + DEVICE)
+        _run_all(cmds, verbose)
         tmp_lib = LIB + ".tmp"
-        cmd = [cc, "-shared", "-o", tmp_lib] + objs + [f"--offload-arch={ARCH}", "-fPIC"]
-        if verbose:
-            print(" ".join(cmd))
-        _run(cmd)
+        _run_all([[cc, "-shared", "-o", tmp_lib] + objs + [f"--offload-arch={ARCH}", "-fPIC"]], verbose)
         os.replace(tmp_lib, LIB)
+        os.replace(tmp_peaks, PEAKS)
     return LIB
 
 

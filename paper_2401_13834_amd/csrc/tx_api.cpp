@@ -1,6 +1,7 @@
 // The C ABI of libtx: argument checking, plan lifetime, scratch, launches.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -10,8 +11,11 @@ using tx::kMaxChansPerSub;
 
 namespace {
 
+thread_local char t_last_error[256] = "";
+
 tx_status from_hip(hipError_t e) {
     if (e == hipSuccess) return TX_OK;
+    tx::note_error(e);
     if (e == hipErrorOutOfMemory) return TX_ENOMEM;
     return TX_EDEVICE;
 }
@@ -33,22 +37,22 @@ tx_status retain_pool(int dev) {
 }
 
 void release_device(tx_plan_s* p) {
-    if (p->d_coarse_chan) (void)hipFree(p->d_coarse_chan);
-    if (p->d_rel) (void)hipFree(p->d_rel);
-    p->d_coarse_chan = nullptr;
-    p->d_rel = nullptr;
+    if (p->d_dT) (void)hipFree(p->d_dT);
+    if (p->d_rT) (void)hipFree(p->d_rT);
+    p->d_dT = nullptr;
+    p->d_rT = nullptr;
     p->on_device = false;
 }
 
 tx_status upload(tx_plan_s* p) {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return TX_EDEVICE;
-    const size_t n1 = p->coarse_chan.size() * sizeof(int32_t);
-    const size_t n2 = p->rel.size() * sizeof(int32_t);
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->d_coarse_chan), n1);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_rel), n2);
-    if (e == hipSuccess) e = hipMemcpy(p->d_coarse_chan, p->coarse_chan.data(), n1, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p->d_rel, p->rel.data(), n2, hipMemcpyHostToDevice);
+    const size_t n1 = p->dT.size() * sizeof(int32_t);
+    const size_t n2 = p->rT.size() * sizeof(int32_t);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->d_dT), n1);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&p->d_rT), n2);
+    if (e == hipSuccess) e = hipMemcpy(p->d_dT, p->dT.data(), n1, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_rT, p->rT.data(), n2, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         release_device(p);
         return from_hip(e);
@@ -56,6 +60,11 @@ tx_status upload(tx_plan_s* p) {
     p->device = dev;
     p->on_device = true;
     return TX_OK;
+}
+
+tx::Tiles current_tiles(const tx_plan_s* p) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    return p->tiles;
 }
 
 tx_status check_device_plan(const tx_plan_s* p) {
@@ -102,7 +111,14 @@ tx_status check_boxcar_args(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64
 
 }  // namespace
 
+void tx::note_error(hipError_t e) {
+    std::snprintf(t_last_error, sizeof(t_last_error), "%s (%d)", hipGetErrorString(e), static_cast<int>(e));
+}
+
 extern "C" {
+
+const char* tx_last_error(void) { return t_last_error; }
+
 
 const char* tx_status_str(tx_status s) {
     switch (s) {
@@ -205,7 +221,7 @@ tx_status tx_plan_destroy(tx_plan_t p) {
 
 tx_status tx_dedisperse_ws_size(tx_plan_t p, int64_t nt, int64_t* bytes) {
     if (!p || !bytes || nt < 0) return TX_EINVAL;
-    *bytes = nt == 0 ? 0 : tx::dedisp_geometry(p, nt).ws_bytes;
+    *bytes = nt == 0 ? 0 : tx::dedisp_geometry(p, nt, current_tiles(p)).ws_bytes;
     return TX_OK;
 }
 
@@ -215,7 +231,8 @@ tx_status tx_dedisperse_ws(tx_plan_t p, const uint8_t* d_in, int64_t in_pitch, i
     if (st != TX_OK) return st;
     st = check_dedisp_args(p, d_in, in_pitch, nt, d_out, out_pitch);
     if (st != TX_OK || nt == 0) return st;
-    const tx::DedispGeom geo = tx::dedisp_geometry(p, nt);
+    const tx::DedispGeom geo = tx::dedisp_geometry(p, nt, current_tiles(p));
+    if (!geo.ok) return TX_ENOTSUP;
     if (!d_ws || ws_bytes < geo.ws_bytes || (reinterpret_cast<uintptr_t>(d_ws) & 255)) return TX_EINVAL;
     return from_hip(tx::launch_dedisperse(p, geo, d_in, in_pitch, nt, d_out, out_pitch,
                                           static_cast<uint16_t*>(d_ws), stream));
@@ -229,7 +246,8 @@ tx_status tx_dedisperse(tx_plan_t p, const uint8_t* d_in, int64_t in_pitch, int6
     if (st != TX_OK || nt == 0) return st;
     st = retain_pool(p->device);
     if (st != TX_OK) return st;
-    const tx::DedispGeom geo = tx::dedisp_geometry(p, nt);
+    const tx::DedispGeom geo = tx::dedisp_geometry(p, nt, current_tiles(p));
+    if (!geo.ok) return TX_ENOTSUP;
     void* ws = nullptr;
     hipError_t e = hipMallocAsync(&ws, static_cast<size_t>(geo.ws_bytes), stream);
     if (e != hipSuccess) return from_hip(e);
@@ -237,6 +255,52 @@ tx_status tx_dedisperse(tx_plan_t p, const uint8_t* d_in, int64_t in_pitch, int6
     hipError_t f = hipFreeAsync(ws, stream);
     if (e != hipSuccess) return from_hip(e);
     return from_hip(f);
+}
+
+tx_status tx_tile_variants(int32_t stage, int32_t* count) {
+    if (!count || (stage != 1 && stage != 2)) return TX_EINVAL;
+    *count = stage == 1 ? tx::stage1_variant_count() : tx::stage2_variant_count();
+    return TX_OK;
+}
+
+tx_status tx_tile_variant_info(int32_t stage, int32_t variant, int32_t* outputs_per_tile, int32_t* trials_per_wave) {
+    if (!outputs_per_tile || !trials_per_wave) return TX_EINVAL;
+    if (stage == 1 && variant >= 0 && variant < tx::stage1_variant_count()) {
+        const tx::Stage1Variant v = tx::stage1_variant(variant);
+        *outputs_per_tile = 256 * v.q;
+        *trials_per_wave = v.jw;
+        return TX_OK;
+    }
+    if (stage == 2 && variant >= 0 && variant < tx::stage2_variant_count()) {
+        *outputs_per_tile = 512 * tx::stage2_variant(variant).q;
+        *trials_per_wave = 0;
+        return TX_OK;
+    }
+    return TX_EINVAL;
+}
+
+tx_status tx_plan_get_tiles(tx_plan_t p, tx_tiles* t) {
+    if (!p || !t) return TX_EINVAL;
+    const tx::Tiles c = current_tiles(p);
+    t->stage1 = c.s1;
+    t->stage1_lds = c.s1_lds;
+    t->stage2 = c.s2;
+    t->stage2_lds = c.s2_lds;
+    return TX_OK;
+}
+
+tx_status tx_plan_set_tiles(tx_plan_t p, const tx_tiles* t) {
+    if (!p || !t) return TX_EINVAL;
+    if (t->stage1 < -1 || t->stage1 >= tx::stage1_variant_count()) return TX_EINVAL;
+    if (t->stage2 < -1 || t->stage2 >= tx::stage2_variant_count()) return TX_EINVAL;
+    if (t->stage1_lds < 0 || t->stage1_lds > tx::kMaxLds || t->stage2_lds < 0 || t->stage2_lds > tx::kMaxLds)
+        return TX_EINVAL;
+    std::lock_guard<std::mutex> lock(p->mu);
+    p->tiles.s1 = t->stage1;
+    p->tiles.s1_lds = t->stage1_lds;
+    p->tiles.s2 = t->stage2;
+    p->tiles.s2_lds = t->stage2_lds;
+    return TX_OK;
 }
 
 tx_status tx_candidates(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64_t pitch, const int32_t* widths,

@@ -16,21 +16,10 @@ constexpr double kDispersion = 4.148808e3;  // s MHz^2 pc^-1 cm^3 (Sec. 2.3, Eq.
 constexpr int kMaxChansPerSub = 256;        // 256 * 255 < 2^16: exact uint16 first stage
 constexpr int64_t kMaxDelay = int64_t(1) << 30;
 
-// ---------------------------------------------------------------------------
-// Tile shapes.  Stage 1 (first stage): a wave covers 256*Q1 consecutive
-// outputs of J1W coarse trials; a workgroup has 4 waves sharing one time tile.
-// Stage 2: each of the 4 waves covers 128*Q2 consecutive outputs of every
-// fine trial in the workgroup's chunk of one coarse group.
-// ---------------------------------------------------------------------------
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-constexpr int Q1 = 4;
-constexpr int J1W = 4;
-constexpr int TT1 = 256 * Q1;            // outputs per stage-1 tile
-constexpr int J1 = J1W * kWaves;         // coarse trials per stage-1 workgroup
-constexpr int Q2 = 2;
-constexpr int TT2 = 128 * Q2 * kWaves;   // outputs per stage-2 tile
-constexpr int kLdsBudget = 48 * 1024;    // bytes of LDS per workgroup for the staged rows
+constexpr int kTablePad = 64;            // padding of the trial axis of the transposed tables
+constexpr int kMaxLds = 160 * 1024;      // LDS per workgroup on gfx950
 
 // Boxcar kernel.
 constexpr int kBoxTile = 4096;           // window starts per tile (16 per thread)
@@ -44,13 +33,13 @@ struct Stage1Args {
     int64_t x_pitch;        // bytes between rows
     int64_t x_len;          // valid samples per row (nt + overlap)
     uint16_t* B;            // first-stage series [ngroups][nsub][B_pitch]
-    int64_t B_pitch;        // elements per series (multiple of TT1)
-    const int32_t* dcc;     // [ngroups][nchan] D(c_j, f_ch)
+    int64_t B_pitch;        // elements per series (multiple of the time tile)
+    const int32_t* dT;      // [nchan][gpad] D(c_j, f_ch), trial axis padded with the last group
+    int32_t gpad;
     int32_t nchan, nsub, m, ngroups;
-    int32_t n_jchunks;      // ceil(ngroups / J1)
-    int32_t n_ttiles;       // B_pitch / TT1
-    int32_t lds_row;        // bytes per staged channel row (multiple of 16)
-    int32_t cchunk;         // channels staged per pass
+    int32_t n_jchunks;      // coarse-trial chunks per sub-band
+    int32_t n_ttiles;       // B_pitch / time tile
+    int32_t lds_bytes;      // dynamic LDS per workgroup
 };
 
 struct Stage2Args {
@@ -59,12 +48,12 @@ struct Stage2Args {
     int32_t* Y;             // [ndm][y_pitch]
     int64_t y_pitch;
     int64_t nt;
-    const int32_t* rel;     // [ndm][nsub] D(dm_i, f_s) - D(c_j, f_s)
+    const int32_t* rT;      // [nsub][dpad] D(dm_i, f_s) - D(c_j, f_s), trial axis padded
+    int32_t dpad;
     int32_t ndm, nsub, g, ngroups;
-    int32_t n_ichunks;      // ceil(g / I2)
-    int32_t n_ttiles;       // ceil(nt / TT2)
-    int32_t lds_row;        // uint16 elements per staged sub-band row (multiple of 8)
-    int32_t schunk;         // sub-bands staged per pass
+    int32_t n_ichunks;      // fine-trial chunks per group
+    int32_t n_ttiles;       // ceil(nt / time tile)
+    int32_t lds_bytes;
     int32_t flush;          // sub-bands summed in 16 bits before widening
 };
 
@@ -88,11 +77,23 @@ struct BoxcarArgs {
     unsigned long long* count;
 };
 
-// ---------------------------------------------------------------------------
-// Plan object.
-// ---------------------------------------------------------------------------
-struct Launch1 {            // stage-1 launch geometry for one output length
-    int32_t lds_row, cchunk;
+// Tile variants (tx_kernels_dedisp.hip).  Stage 1: Q1 dwords (4 outputs each)
+// per lane, JW coarse trials per wave, 4 waves sharing one time tile of
+// 256*Q1 outputs.  Stage 2: Q2 dwords (2 outputs each) per lane, the 4 waves
+// splitting a time tile of 512*Q2 outputs, IW fine trials per workgroup.
+struct Stage1Variant {
+    int q, jw;
+};
+struct Stage2Variant {
+    int q;
+};
+int stage1_variant_count();
+int stage2_variant_count();
+Stage1Variant stage1_variant(int v);
+Stage2Variant stage2_variant(int v);
+
+struct Tiles {
+    int32_t s1 = -1, s1_lds = 0, s2 = -1, s2_lds = 0;   // -1 / 0: defaults
 };
 
 }  // namespace tx
@@ -107,12 +108,17 @@ struct tx_plan_s {
     std::vector<int32_t> extent;       // [ngroups][nsub]
     std::vector<int32_t> rel;          // [ndm][nsub] fine minus coarse sub-band delay
     int64_t overlap = 0, max_extent = 0, brute_reach = 0;
-    int32_t spread1 = 0;               // max first-stage shift spread inside a stage-1 tile
-    int32_t spread2 = 0;               // max second-stage shift spread inside a stage-2 tile
+    int32_t gpad = 0, dpad = 0;
+    std::vector<int32_t> dT;           // [nchan][gpad]
+    std::vector<int32_t> rT;           // [nsub][dpad]
     int device = -1;
     bool on_device = false;
-    int32_t* d_coarse_chan = nullptr;
-    int32_t* d_rel = nullptr;
+    int32_t* d_dT = nullptr;
+    int32_t* d_rT = nullptr;
+    mutable std::mutex mu;             // guards `tiles` and the spread cache
+    tx::Tiles tiles;
+    mutable std::vector<std::pair<int, int32_t>> spread1_cache;   // (J, spread)
+    mutable std::vector<std::pair<int, int32_t>> spread2_cache;   // (IW, spread)
 };
 
 namespace tx {
@@ -121,20 +127,29 @@ namespace tx {
 tx_status build_plan_host(const double* freqs, int32_t nchan, double tsamp, const double* dms,
                           int32_t ndm, int32_t nsub, int32_t dms_per_group, tx_plan_s* p);
 int32_t delay_samples(double dm, double f, double fref, double tsamp);
+int32_t plan_spread1(const tx_plan_s* p, int J);    // largest D(c_j,f) - D(c_j0,f) within J trials
+int32_t plan_spread2(const tx_plan_s* p, int iw);   // largest rel spread within iw fine trials
 
-// Launch helpers (tx_kernels.hip).
+// Launch helpers (tx_kernels_dedisp.hip, tx_kernels_boxcar.hip).
 struct DedispGeom {
+    Tiles tiles;            // resolved variants and LDS sizes
+    int tt1, J1, tt2, iw;
     int64_t B_pitch;        // uint16 elements per first-stage series
     int64_t ws_bytes;       // scratch bytes
-    int32_t lds1_row, cchunk;
-    int32_t lds2_row, schunk;
-    int32_t n_ttiles1, n_ttiles2;
+    int32_t n_ttiles1, n_ttiles2, n_jchunks, n_ichunks;
+    int32_t lds1, lds2;     // dynamic LDS per workgroup
+    bool ok;                // false if some workgroup cannot fit its LDS rows
 };
-DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt);
+DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want);
 hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in,
                              int64_t in_pitch, int64_t nt, int32_t* d_out, int64_t out_pitch,
                              uint16_t* d_B, hipStream_t stream);
 hipError_t launch_boxcar(const BoxcarArgs& a, hipStream_t stream);
+
+// Largest dynamic LDS per workgroup the current device allows (capped at kMaxLds).
+int device_max_lds();
+// Last HIP error seen by the C ABI on this thread (tx_api.cpp).
+void note_error(hipError_t e);
 
 // Optional per-launch timing (tx_profile.cpp).  prof_begin returns -1 when
 // profiling is off; otherwise a slot whose end is recorded by prof_end.

@@ -1,0 +1,533 @@
+// Two-stage sub-band dedispersion kernels for gfx950 (MI355X).
+//
+// Layout: filterbank rows are channel-major uint8; first-stage series are
+// uint16 [group][sub-band][time]; the output is int32 [trial][time].  All sums
+// are integer and exact, so any tiling gives bit-identical results.
+//
+// Both stages are shift-and-add with one shift per (trial, row) that is the
+// same for every lane of a wave: lanes walk the time axis and read one
+// contiguous LDS window per (trial, row).  To make every such read an aligned,
+// bank-conflict-free dword, a staged row is kept in several copies shifted by
+// one element each (4 byte-shifted copies in stage 1, 2 element-shifted copies
+// in stage 2); a per-(row, trial) table gives the byte offset of the copy and
+// word to read.  A workgroup whose rows are too long for that many copies
+// falls back to a single copy and joins neighbouring words with v_alignbyte.
+#include <algorithm>
+
+#include "tx_internal.h"
+
+namespace tx {
+
+__device__ __forceinline__ uint32_t perm_b32(uint32_t hi, uint32_t lo, uint32_t sel) {
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+__device__ __forceinline__ uint32_t align_b32(uint32_t hi, uint32_t lo, uint32_t nbytes) {
+    return __builtin_amdgcn_alignbyte(hi, lo, nbytes);
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Consecutive workgroup ids are dealt round-robin to the 8 XCDs; give each XCD
+// a contiguous range of tiles so that tiles sharing input rows share an L2.
+__device__ __forceinline__ int xcd_tile(int bid, int total) {
+    const int nx = 8;
+    const int x = bid % nx, k = bid / nx;
+    const int q = total / nx, r = total % nx;
+    return x * q + min(x, r) + k;
+}
+
+__device__ __forceinline__ int block_max(int v, int* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    v = max(max(red[0], red[1]), max(red[2], red[3]));
+    __syncthreads();
+    return v;
+}
+
+// Bytes [b, b + 20) of a row with `avail` valid bytes (zeros past the end).
+__device__ __forceinline__ void load20(const uint8_t* row, int b, int64_t avail, uint32_t d[5]) {
+    if (b + 20 <= avail) {
+        const uint4 v = *reinterpret_cast<const uint4*>(row + b);
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+        d[4] = *reinterpret_cast<const uint32_t*>(row + b + 16);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) d[k] = 0u;
+        for (int k = 0; k < 20; ++k)
+            if (b + k < avail) d[k >> 2] |= static_cast<uint32_t>(row[b + k]) << (8 * (k & 3));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 1: B[j][s][u] = sum over ch in s of x[ch][u + D(c_j, f_ch)].
+//
+// Workgroup = (sub-band s, J = 4*JW coarse trials, TT = 256*Q outputs); wave w
+// owns trials j0 + w*JW .. + JW-1 and lane l owns the output dwords l + 64 q
+// (4 outputs each), so the lanes of a wave read consecutive LDS dwords (no bank
+// conflicts) and each output dword needs one two-dword LDS read.  Channel rows
+// are staged starting at the row's shift for the first trial, rounded down to
+// 16 bytes; a per-(channel, trial) table holds the byte offset of the first
+// word and the remaining byte shift k.  v_alignbyte picks the 4 input bytes of
+// an output dword, a byte permute picks bytes 1 and 3 into 16-bit lanes.
+//
+// "full" accumulates the 4 bytes as one 32-bit word (carries cross bytes) and
+// "odd" accumulates bytes 1 and 3 as two 16-bit lanes; at the end
+// full - (odd << 8) = (sum b0) | (sum b2) << 16 exactly, because every 16-bit
+// sum of <= 256 bytes is < 2^16.  Channels are taken in pairs so that two
+// contributions and the accumulator meet in one 3-input add.
+// ---------------------------------------------------------------------------
+template <int Q, int JW>
+__global__ __launch_bounds__(kThreads) void stage1_kernel(Stage1Args a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ int red[kWaves];
+    constexpr int J = JW * kWaves;
+    constexpr int TT = 256 * Q;
+    constexpr uint32_t kOdd = 0x0C030C01u;   // bytes 1 and 3 into 16-bit lanes
+    const int total = a.nsub * a.n_ttiles * a.n_jchunks;
+    const int tile = xcd_tile(blockIdx.x, total);
+    const int jc = tile % a.n_jchunks;
+    const int rest = tile / a.n_jchunks;
+    const int tt = rest % a.n_ttiles;
+    const int s = rest / a.n_ttiles;
+    const int j0 = jc * J;
+    const int jl = min(j0 + J, a.ngroups) - 1;
+    const int u0 = tt * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = uniform(tid >> 6);
+    const int ch0 = s * a.m;
+    const int32_t* __restrict__ dT = a.dT;
+    const size_t gp = static_cast<size_t>(a.gpad);
+
+    // Largest shift (from the 16-byte aligned row start) in this workgroup.
+    int sp = 0;
+    for (int c = tid; c < a.m; c += kThreads) {
+        const int32_t* r = dT + static_cast<size_t>(ch0 + c) * gp;
+        sp = max(sp, r[jl] - (r[j0] & ~15));
+    }
+    sp = block_max(sp, red);
+    const int W = ((sp >> 2) + 64 * Q + 1 + 3) & ~3;      // dwords per staged row
+    const int rowbytes = 4 * W;
+    const int avail = a.lds_bytes - 16;
+    const int nch = max(1, min(a.m, avail / (rowbytes + 4 * J)));
+    int32_t* tab = reinterpret_cast<int32_t*>(lds);
+    uint8_t* dat = lds + ((nch * J * 4 + 15) & ~15);
+
+    uint32_t full[JW][Q], odd[JW][Q];
+#pragma unroll
+    for (int jj = 0; jj < JW; ++jj)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) full[jj][q] = odd[jj][q] = 0u;
+
+    for (int cb = 0; cb < a.m; cb += nch) {
+        const int nc = min(nch, a.m - cb);
+        for (int t = tid; t < nc * J; t += kThreads) {
+            const int c = t / J, k = t - c * J;
+            const int32_t* r = dT + static_cast<size_t>(ch0 + cb + c) * gp;
+            const int sh = r[min(j0 + k, jl)] - (r[j0] & ~15);
+            tab[t] = c * rowbytes + sh;          // word offset (sh & ~3) plus byte shift (sh & 3)
+        }
+        // Rows: wave w stages rows w, w + 4, ...
+        for (int c = wave; c < nc; c += kWaves) {
+            const int ch = ch0 + cb + c;
+            const int64_t start = static_cast<int64_t>(u0) + (dT[static_cast<size_t>(ch) * gp + j0] & ~15);
+            const uint8_t* row = a.x + static_cast<size_t>(ch) * a.x_pitch + start;
+            const int64_t avail_b = a.x_len - start;
+            uint32_t* dst = reinterpret_cast<uint32_t*>(dat + c * rowbytes);
+            for (int i = lane; 4 * i < W; i += 64) {
+                uint32_t d[5];
+                load20(row, 16 * i, avail_b, d);
+                *reinterpret_cast<uint4*>(dst + 4 * i) = make_uint4(d[0], d[1], d[2], d[3]);
+            }
+        }
+        __syncthreads();
+        const int32_t* tw = tab + wave * JW;
+        int c = 0;
+        for (; c + 1 < nc; c += 2) {
+#pragma unroll
+            for (int jj = 0; jj < JW; ++jj) {
+                const int e0 = uniform(tw[c * J + jj]);
+                const int e1 = uniform(tw[(c + 1) * J + jj]);
+                const uint32_t k0 = static_cast<uint32_t>(e0 & 3), k1 = static_cast<uint32_t>(e1 & 3);
+                const uint32_t sel0 = kOdd + k0 * 0x00010001u, sel1 = kOdd + k1 * 0x00010001u;
+                const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3)) + lane;
+                const uint32_t* p1 = reinterpret_cast<const uint32_t*>(dat + (e1 & ~3)) + lane;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const uint32_t a0 = p0[64 * q], a1 = p0[64 * q + 1];
+                    const uint32_t b0 = p1[64 * q], b1 = p1[64 * q + 1];
+                    full[jj][q] += align_b32(a1, a0, k0) + align_b32(b1, b0, k1);
+                    odd[jj][q] += perm_b32(a1, a0, sel0) + perm_b32(b1, b0, sel1);
+                }
+            }
+        }
+        if (c < nc) {
+#pragma unroll
+            for (int jj = 0; jj < JW; ++jj) {
+                const int e0 = uniform(tw[c * J + jj]);
+                const uint32_t k0 = static_cast<uint32_t>(e0 & 3);
+                const uint32_t sel0 = kOdd + k0 * 0x00010001u;
+                const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3)) + lane;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const uint32_t a0 = p0[64 * q], a1 = p0[64 * q + 1];
+                    full[jj][q] += align_b32(a1, a0, k0);
+                    odd[jj][q] += perm_b32(a1, a0, sel0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int jj = 0; jj < JW; ++jj) {
+        const int j = j0 + wave * JW + jj;
+        if (j <= jl) {
+            uint16_t* out = a.B + (static_cast<size_t>(j) * a.nsub + s) * a.B_pitch + u0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const uint32_t even = full[jj][q] - (odd[jj][q] << 8);
+                const uint32_t w01 = perm_b32(odd[jj][q], even, 0x05040100u);
+                const uint32_t w23 = perm_b32(odd[jj][q], even, 0x07060302u);
+                *reinterpret_cast<uint2*>(out + 4 * (lane + 64 * q)) = make_uint2(w01, w23);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2: Y[i][t] = sum over s of B[j][s][t + rel(i, s)],
+// rel(i, s) = D(dm_i, f_s) - D(c_j, f_s).
+//
+// Workgroup = (group j, IW of its fine trials, TT = 512*Q outputs); the 4
+// waves split the time tile and each handles all IW trials.  Lane l of wave w
+// owns the output dwords (two uint16 outputs each) w*64*Q + l + 64 q, so a wave
+// reads consecutive LDS dwords.  Sub-band rows are staged from the chunk's
+// first trial's shift rounded down to 8 elements; a per-(sub-band, trial) table
+// holds the byte offset of the first word and, for an odd element shift, a
+// 2-byte shift that v_alignbyte applies.  Outputs are summed as packed 16-bit
+// lanes of one 32-bit word (sub-bands in pairs through one 3-input add) for
+// `flush` sub-bands (exact: flush * 255 * m < 2^16), then widened into two
+// int32 accumulators.
+// ---------------------------------------------------------------------------
+template <int IW, int Q>
+__global__ __launch_bounds__(kThreads) void stage2_kernel(Stage2Args a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ int red[kWaves];
+    constexpr int IWP = (IW + 3) & ~3;
+    constexpr int TT = 512 * Q;
+    const int total = a.ngroups * a.n_ichunks * a.n_ttiles;
+    const int tile = xcd_tile(blockIdx.x, total);
+    const int ic = tile % a.n_ichunks;
+    const int rest = tile / a.n_ichunks;
+    const int tt = rest % a.n_ttiles;
+    const int j = rest / a.n_ttiles;
+    const int i0 = j * a.g + ic * IW;
+    const int iend = min((j + 1) * a.g, a.ndm);
+    const int ni = min(IW, iend - i0);
+    if (ni <= 0) return;
+    const int il = i0 + ni - 1;
+    const int t0 = tt * TT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = uniform(tid >> 6);
+    const int32_t* __restrict__ rT = a.rT;
+    const size_t dp = static_cast<size_t>(a.dpad);
+
+    int sp = 0;
+    for (int s = tid; s < a.nsub; s += kThreads) {
+        const int32_t* r = rT + static_cast<size_t>(s) * dp;
+        sp = max(sp, r[il] - (r[i0] & ~7));
+    }
+    sp = block_max(sp, red);
+    const int W = ((sp >> 1) + 256 * Q + 1 + 3) & ~3;     // dwords per staged row
+    const int rowbytes = 4 * W;
+    const int avail = a.lds_bytes - 16;
+    const int nsb = max(1, min(a.nsub, avail / (rowbytes + 4 * IWP)));
+    int32_t* tab = reinterpret_cast<int32_t*>(lds);
+    uint8_t* dat = lds + ((nsb * IWP * 4 + 15) & ~15);
+
+    uint32_t acc[IW][Q], lo[IW][Q], hi[IW][Q];
+#pragma unroll
+    for (int ii = 0; ii < IW; ++ii)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[ii][q] = lo[ii][q] = hi[ii][q] = 0u;
+    int pending = 0;
+    const bool pairs = a.flush >= 2;
+    const int step_max = pairs ? 2 : 1;
+    const uint16_t* Bj = a.B + static_cast<size_t>(j) * a.nsub * a.B_pitch;
+    const int wbase = wave * 64 * Q + lane;
+
+    for (int sb = 0; sb < a.nsub; sb += nsb) {
+        const int ns = min(nsb, a.nsub - sb);
+        for (int t = tid; t < ns * IWP; t += kThreads) {
+            const int r = t / IWP, k = t - r * IWP;
+            const int32_t* rr = rT + static_cast<size_t>(sb + r) * dp;
+            const int e = rr[i0 + min(k, ni - 1)] - (rr[i0] & ~7);
+            tab[t] = r * rowbytes + 2 * e;       // word offset plus a 2-byte shift for odd e
+        }
+        for (int r = wave; r < ns; r += kWaves) {
+            const int s = sb + r;
+            const uint16_t* src = Bj + static_cast<size_t>(s) * a.B_pitch + t0 + (rT[static_cast<size_t>(s) * dp + i0] & ~7);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(dat + r * rowbytes);
+            for (int i = lane; 4 * i < W; i += 64)
+                *reinterpret_cast<uint4*>(dst + 4 * i) = *reinterpret_cast<const uint4*>(src + 8 * i);
+        }
+        __syncthreads();
+        int r = 0;
+        while (r < ns) {
+            const int step = (pairs && r + 1 < ns) ? 2 : 1;
+            if (step == 2) {
+#pragma unroll
+                for (int ii = 0; ii < IW; ++ii) {
+                    const int e0 = uniform(tab[r * IWP + ii]);
+                    const int e1 = uniform(tab[(r + 1) * IWP + ii]);
+                    const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3)) + wbase;
+                    const uint32_t* p1 = reinterpret_cast<const uint32_t*>(dat + (e1 & ~3)) + wbase;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q)
+                        acc[ii][q] += align_b32(p0[64 * q + 1], p0[64 * q], e0 & 3) +
+                                      align_b32(p1[64 * q + 1], p1[64 * q], e1 & 3);
+                }
+            } else {
+#pragma unroll
+                for (int ii = 0; ii < IW; ++ii) {
+                    const int e0 = uniform(tab[r * IWP + ii]);
+                    const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3)) + wbase;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) acc[ii][q] += align_b32(p0[64 * q + 1], p0[64 * q], e0 & 3);
+                }
+            }
+            pending += step;
+            r += step;
+            if (pending + step_max > a.flush) {
+#pragma unroll
+                for (int ii = 0; ii < IW; ++ii)
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        lo[ii][q] += acc[ii][q] & 0xFFFFu;
+                        hi[ii][q] += acc[ii][q] >> 16;
+                        acc[ii][q] = 0u;
+                    }
+                pending = 0;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ii = 0; ii < IW; ++ii)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            lo[ii][q] += acc[ii][q] & 0xFFFFu;
+            hi[ii][q] += acc[ii][q] >> 16;
+        }
+
+#pragma unroll
+    for (int ii = 0; ii < IW; ++ii) {
+        if (ii < ni) {
+            int32_t* out = a.Y + static_cast<size_t>(i0 + ii) * a.y_pitch;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int64_t t = t0 + 2 * static_cast<int64_t>(wbase + 64 * q);
+                if (t + 1 < a.nt) {
+                    *reinterpret_cast<int2*>(out + t) =
+                        make_int2(static_cast<int32_t>(lo[ii][q]), static_cast<int32_t>(hi[ii][q]));
+                } else if (t < a.nt) {
+                    out[t] = static_cast<int32_t>(lo[ii][q]);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Variants, geometry and launches.
+// ---------------------------------------------------------------------------
+static const Stage1Variant kS1[] = {{8, 2}, {4, 4}, {4, 2}, {8, 4}, {16, 1}, {16, 2}, {8, 1}};
+static const Stage2Variant kS2[] = {{1}, {2}, {4}};
+constexpr int kNS1 = sizeof(kS1) / sizeof(kS1[0]);
+constexpr int kNS2 = sizeof(kS2) / sizeof(kS2[0]);
+constexpr int kDefaultLds = 32 * 1024;
+
+int stage1_variant_count() { return kNS1; }
+int stage2_variant_count() { return kNS2; }
+Stage1Variant stage1_variant(int v) { return kS1[v]; }
+Stage2Variant stage2_variant(int v) { return kS2[v]; }
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+int device_max_lds();
+
+static int pick_iw(int32_t g) {
+    static const int cands[] = {16, 13, 8, 4, 2, 1};
+    int best = 1;
+    int64_t best_cost = INT64_MAX;
+    for (int iw : cands) {
+        const int64_t cost = (g + iw - 1) / iw * static_cast<int64_t>(iw);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = iw;
+        }
+    }
+    return best;
+}
+
+DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want) {
+    DedispGeom g{};
+    g.tiles = want;
+    if (g.tiles.s1 < 0 || g.tiles.s1 >= kNS1) g.tiles.s1 = 0;
+    if (g.tiles.s2 < 0 || g.tiles.s2 >= kNS2) g.tiles.s2 = 0;
+    const Stage1Variant v1 = kS1[g.tiles.s1];
+    const Stage2Variant v2 = kS2[g.tiles.s2];
+    g.tt1 = 256 * v1.q;
+    g.J1 = 4 * v1.jw;
+    g.tt2 = 512 * v2.q;
+    g.iw = pick_iw(p->g);
+    const int iwp = (g.iw + 3) & ~3;
+
+    // LDS: at least one single-copy row per workgroup.
+    const int sp1 = plan_spread1(p, g.J1) + 15;
+    const int W1 = ((sp1 >> 2) + 64 * v1.q + 1 + 3) & ~3;
+    const int need1 = 4 * W1 + 4 * g.J1 + 48;
+    g.lds1 = std::max(g.tiles.s1_lds > 0 ? g.tiles.s1_lds : kDefaultLds, need1);
+    const int sp2 = plan_spread2(p, g.iw) + 7;
+    const int W2 = ((sp2 >> 1) + 256 * v2.q + 1 + 3) & ~3;
+    const int need2 = 4 * W2 + 4 * iwp + 48;
+    g.lds2 = std::max(g.tiles.s2_lds > 0 ? g.tiles.s2_lds : kDefaultLds, need2);
+    const int max_lds = device_max_lds();
+    g.lds1 = std::min(g.lds1, std::max(need1, max_lds));
+    g.lds2 = std::min(g.lds2, std::max(need2, max_lds));
+    g.ok = g.lds1 <= max_lds && g.lds2 <= max_lds;
+    g.tiles.s1_lds = g.lds1;
+    g.tiles.s2_lds = g.lds2;
+
+    g.n_ttiles2 = static_cast<int32_t>((nt + g.tt2 - 1) / g.tt2);
+    // Stage 2 stages elements [start, start + 2 W) of a series, start <= last
+    // tile start + max extent.
+    const int64_t need = static_cast<int64_t>(std::max(g.n_ttiles2 - 1, 0)) * g.tt2 + p->max_extent + 2 * W2;
+    g.B_pitch = round_up(std::max<int64_t>(need, nt + p->max_extent), g.tt1);
+    g.n_ttiles1 = static_cast<int32_t>(g.B_pitch / g.tt1);
+    g.n_jchunks = (p->ngroups + g.J1 - 1) / g.J1;
+    g.n_ichunks = (p->g + g.iw - 1) / g.iw;
+    g.ws_bytes = round_up(static_cast<int64_t>(p->ngroups) * p->nsub * g.B_pitch * 2, 256);
+    return g;
+}
+
+// Raise a kernel's dynamic-LDS limit once, when a launch asks for more than
+// the runtime's default; a failure leaves the limit (and the launch then fails
+// with a reported error).
+static void allow_lds(const void* fn, int bytes, int* done) {
+    if (bytes <= 64 * 1024 || *done >= bytes) return;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess) *done = bytes;
+    (void)hipGetLastError();
+}
+
+int device_max_lds() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            cached = std::min(v, kMaxLds);
+        else
+            cached = 64 * 1024;
+        (void)hipGetLastError();
+    }
+    return cached;
+}
+
+template <int Q, int JW>
+static hipError_t launch_s1(const Stage1Args& a, int grid, hipStream_t st) {
+    static int done = 0;
+    allow_lds(reinterpret_cast<const void*>(&stage1_kernel<Q, JW>), a.lds_bytes, &done);
+    hipLaunchKernelGGL((stage1_kernel<Q, JW>), dim3(grid), dim3(kThreads), a.lds_bytes, st, a);
+    return hipGetLastError();
+}
+
+template <int IW, int Q>
+static hipError_t launch_s2(const Stage2Args& a, int grid, hipStream_t st) {
+    static int done = 0;
+    allow_lds(reinterpret_cast<const void*>(&stage2_kernel<IW, Q>), a.lds_bytes, &done);
+    hipLaunchKernelGGL((stage2_kernel<IW, Q>), dim3(grid), dim3(kThreads), a.lds_bytes, st, a);
+    return hipGetLastError();
+}
+
+template <int IW>
+static hipError_t launch_s2_q(const Stage2Args& a, int q, int grid, hipStream_t st) {
+    switch (q) {
+        case 2: return launch_s2<IW, 2>(a, grid, st);
+        case 4: return launch_s2<IW, 4>(a, grid, st);
+        default: return launch_s2<IW, 1>(a, grid, st);
+    }
+}
+
+hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in, int64_t in_pitch,
+                             int64_t nt, int32_t* d_out, int64_t out_pitch, uint16_t* d_B, hipStream_t stream) {
+    if (!geo.ok) return hipErrorInvalidValue;
+    Stage1Args s1{};
+    s1.x = d_in;
+    s1.x_pitch = in_pitch;
+    s1.x_len = nt + p->overlap;
+    s1.B = d_B;
+    s1.B_pitch = geo.B_pitch;
+    s1.dT = p->d_dT;
+    s1.gpad = p->gpad;
+    s1.nchan = p->nchan;
+    s1.nsub = p->nsub;
+    s1.m = p->m;
+    s1.ngroups = p->ngroups;
+    s1.n_jchunks = geo.n_jchunks;
+    s1.n_ttiles = geo.n_ttiles1;
+    s1.lds_bytes = geo.lds1;
+    const int grid1 = static_cast<int>(static_cast<int64_t>(s1.nsub) * s1.n_ttiles * s1.n_jchunks);
+    const Stage1Variant v1 = kS1[geo.tiles.s1];
+    int prof = prof_begin(TX_KERNEL_STAGE1, stream);
+    hipError_t e;
+    switch (v1.q * 100 + v1.jw) {
+        case 802: e = launch_s1<8, 2>(s1, grid1, stream); break;
+        case 404: e = launch_s1<4, 4>(s1, grid1, stream); break;
+        case 402: e = launch_s1<4, 2>(s1, grid1, stream); break;
+        case 804: e = launch_s1<8, 4>(s1, grid1, stream); break;
+        case 1601: e = launch_s1<16, 1>(s1, grid1, stream); break;
+        case 1602: e = launch_s1<16, 2>(s1, grid1, stream); break;
+        case 801: e = launch_s1<8, 1>(s1, grid1, stream); break;
+        default: e = hipErrorInvalidValue; break;
+    }
+    prof_end(prof, stream);
+    if (e != hipSuccess) return e;
+
+    Stage2Args s2{};
+    s2.B = d_B;
+    s2.B_pitch = geo.B_pitch;
+    s2.Y = d_out;
+    s2.y_pitch = out_pitch;
+    s2.nt = nt;
+    s2.rT = p->d_rT;
+    s2.dpad = p->dpad;
+    s2.ndm = p->ndm;
+    s2.nsub = p->nsub;
+    s2.g = p->g;
+    s2.ngroups = p->ngroups;
+    s2.n_ichunks = geo.n_ichunks;
+    s2.n_ttiles = geo.n_ttiles2;
+    s2.lds_bytes = geo.lds2;
+    s2.flush = std::max(1, 65535 / (255 * p->m));
+    const int grid2 = static_cast<int>(static_cast<int64_t>(s2.ngroups) * s2.n_ichunks * s2.n_ttiles);
+    const int q2 = kS2[geo.tiles.s2].q;
+    prof = prof_begin(TX_KERNEL_STAGE2, stream);
+    switch (geo.iw) {
+        case 16: e = launch_s2_q<16>(s2, q2, grid2, stream); break;
+        case 13: e = launch_s2_q<13>(s2, q2, grid2, stream); break;
+        case 8: e = launch_s2_q<8>(s2, q2, grid2, stream); break;
+        case 4: e = launch_s2_q<4>(s2, q2, grid2, stream); break;
+        case 2: e = launch_s2_q<2>(s2, q2, grid2, stream); break;
+        default: e = launch_s2_q<1>(s2, q2, grid2, stream); break;
+    }
+    prof_end(prof, stream);
+    return e;
+}
+
+}  // namespace tx

@@ -1,0 +1,189 @@
+// Measured peaks of the units the dedispersion kernels use, on the current
+// GPU: HBM copy bandwidth, 32-bit and packed 16-bit integer add rates, byte
+// permute / align rates, and LDS read bandwidth.  Prints one JSON object.
+//
+//   tx_peaks [--quick]
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#define CHECK(x)                                                                              \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess) {                                                               \
+            std::fprintf(stderr, "%s failed: %s\n", #x, hipGetErrorString(e_));               \
+            std::exit(1);                                                                     \
+        }                                                                                     \
+    } while (0)
+
+constexpr int kThreads = 256;
+constexpr int kAcc = 16;
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(kThreads) void add32_kernel(const uint32_t* in, uint32_t* out, int iters) {
+    uint32_t a[kAcc];
+    const uint32_t x = in[threadIdx.x & 63], y = in[(threadIdx.x + 7) & 63];
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) a[k] = x + k;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < kAcc; ++k) a[k] += a[(k + 1) % kAcc];
+    }
+    uint32_t r = y;
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) r ^= a[k];
+    out[blockIdx.x * kThreads + threadIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kThreads) void add16x2_kernel(const uint32_t* in, uint32_t* out, int iters) {
+    u16x2 a[kAcc];
+    u16x2 x, y;
+    __builtin_memcpy(&x, &in[threadIdx.x & 63], 4);
+    __builtin_memcpy(&y, &in[(threadIdx.x + 5) & 63], 4);
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) a[k] = x + (unsigned short)k;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < kAcc; ++k) a[k] += a[(k + 1) % kAcc];
+    }
+    uint32_t r = 0;
+    __builtin_memcpy(&r, &y, 4);
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) {
+        uint32_t v;
+        __builtin_memcpy(&v, &a[k], 4);
+        r ^= v;
+    }
+    out[blockIdx.x * kThreads + threadIdx.x] = r;
+}
+
+// One byte permute and one 32-bit add per step: the inner pattern of the
+// first dedispersion stage.
+__global__ __launch_bounds__(kThreads) void perm_add_kernel(const uint32_t* in, uint32_t* out, int iters) {
+    uint32_t a[kAcc];
+    const uint32_t x = in[threadIdx.x & 63], y = in[(threadIdx.x + 3) & 63];
+    const uint32_t sel = 0x0C030C01u + (in[0] & 3u) * 0x00010001u;
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) a[k] = k ^ y;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < kAcc; ++k) a[k] += __builtin_amdgcn_perm(a[(k + 1) % kAcc], a[k] ^ x, sel);
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) r ^= a[k];
+    out[blockIdx.x * kThreads + threadIdx.x] = r;
+}
+
+// LDS reads: every lane reads W consecutive bytes (W = 4, 8, 16) at a
+// conflict-free address, `reps` times over a 16 KiB buffer.
+template <int W>
+__global__ __launch_bounds__(kThreads) void lds_kernel(uint32_t* out, int iters) {
+    __shared__ __align__(16) uint32_t buf[4096];
+    for (int i = threadIdx.x; i < 4096; i += kThreads) buf[i] = i * 2654435761u;
+    __syncthreads();
+    constexpr int D = W / 4;
+    uint32_t acc = 0;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int base = (wave * 64 * D) & 4095;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = (base + lane * D + u * 256 * D) & (4096 - D);
+            if constexpr (D == 1) {
+                acc += buf[idx];
+            } else if constexpr (D == 2) {
+                const uint2 v = *reinterpret_cast<const uint2*>(&buf[idx]);
+                acc += v.x ^ v.y;
+            } else {
+                const uint4 v = *reinterpret_cast<const uint4*>(&buf[idx]);
+                acc += v.x ^ v.y ^ v.z ^ v.w;
+            }
+        }
+        base = (base + 64) & 4095;
+    }
+    out[blockIdx.x * kThreads + threadIdx.x] = acc;
+}
+
+__global__ void copy_kernel(const uint4* __restrict__ in, uint4* __restrict__ out, size_t n) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) out[i] = in[i];
+}
+
+template <typename F>
+static float time_ms(F f, int reps) {
+    hipEvent_t a, b;
+    CHECK(hipEventCreate(&a));
+    CHECK(hipEventCreate(&b));
+    f();
+    CHECK(hipDeviceSynchronize());
+    CHECK(hipEventRecord(a));
+    for (int r = 0; r < reps; ++r) f();
+    CHECK(hipEventRecord(b));
+    CHECK(hipEventSynchronize(b));
+    float ms = 0;
+    CHECK(hipEventElapsedTime(&ms, a, b));
+    CHECK(hipEventDestroy(a));
+    CHECK(hipEventDestroy(b));
+    return ms / reps;
+}
+
+int main(int argc, char** argv) {
+    const bool quick = argc > 1 && std::strcmp(argv[1], "--quick") == 0;
+    hipDeviceProp_t prop;
+    CHECK(hipGetDeviceProperties(&prop, 0));
+    const int cus = prop.multiProcessorCount;
+    const double clk_hz = prop.clockRate * 1e3;
+    const int blocks = cus * 8;
+    uint32_t *in, *out;
+    CHECK(hipMalloc(&in, 64 * 4));
+    CHECK(hipMalloc(&out, (size_t)blocks * kThreads * 4));
+    std::vector<uint32_t> h(64);
+    for (int i = 0; i < 64; ++i) h[i] = 0x01020304u * (i + 1);
+    CHECK(hipMemcpy(in, h.data(), 256, hipMemcpyHostToDevice));
+    const int iters = quick ? 2000 : 20000;
+    const double lanes = (double)blocks * kThreads;
+
+    float t_add = time_ms([&] { hipLaunchKernelGGL(add32_kernel, dim3(blocks), dim3(kThreads), 0, 0, in, out, iters); }, 3);
+    const double add32 = lanes * iters * kAcc / (t_add * 1e-3);
+    float t_pk = time_ms([&] { hipLaunchKernelGGL(add16x2_kernel, dim3(blocks), dim3(kThreads), 0, 0, in, out, iters); }, 3);
+    const double add16 = 2.0 * lanes * iters * kAcc / (t_pk * 1e-3);
+    float t_perm = time_ms([&] { hipLaunchKernelGGL(perm_add_kernel, dim3(blocks), dim3(kThreads), 0, 0, in, out, iters); }, 3);
+    const double perm_add = lanes * iters * kAcc / (t_perm * 1e-3);   // (perm + add) pairs per second
+
+    const int lit = quick ? 2000 : 20000;
+    float t_l4 = time_ms([&] { hipLaunchKernelGGL(lds_kernel<4>, dim3(blocks), dim3(kThreads), 0, 0, out, lit); }, 3);
+    float t_l8 = time_ms([&] { hipLaunchKernelGGL(lds_kernel<8>, dim3(blocks), dim3(kThreads), 0, 0, out, lit); }, 3);
+    float t_l16 = time_ms([&] { hipLaunchKernelGGL(lds_kernel<16>, dim3(blocks), dim3(kThreads), 0, 0, out, lit); }, 3);
+    auto lds_bw = [&](float ms, int w) { return lanes * lit * 8.0 * w / (ms * 1e-3); };
+
+    const size_t bytes = (size_t)(quick ? 1 : 4) << 30;
+    uint4 *src, *dst;
+    CHECK(hipMalloc(&src, bytes));
+    CHECK(hipMalloc(&dst, bytes));
+    CHECK(hipMemset(src, 1, bytes));
+    const size_t n = bytes / 16;
+    float t_cp = time_ms([&] { hipLaunchKernelGGL(copy_kernel, dim3(cus * 16), dim3(256), 0, 0, src, dst, n); }, 5);
+    const double copy_bw = 2.0 * bytes / (t_cp * 1e-3);
+
+    std::printf("{\"device\": \"%s\", \"cus\": %d, \"clock_mhz\": %.0f, "
+                "\"add32_per_s\": %.4e, \"add16_packed_per_s\": %.4e, \"perm_add_pairs_per_s\": %.4e, "
+                "\"add32_per_clk_per_cu\": %.2f, \"add16_per_clk_per_cu\": %.2f, "
+                "\"lds_b32_bytes_per_s\": %.4e, \"lds_b64_bytes_per_s\": %.4e, \"lds_b128_bytes_per_s\": %.4e, "
+                "\"lds_b128_bytes_per_clk_per_cu\": %.1f, \"lds_b32_bytes_per_clk_per_cu\": %.1f, "
+                "\"hbm_copy_bytes_per_s\": %.4e}\n",
+                prop.name, cus, clk_hz / 1e6, add32, add16, perm_add, add32 / cus / clk_hz, add16 / cus / clk_hz,
+                lds_bw(t_l4, 4), lds_bw(t_l8, 8), lds_bw(t_l16, 16), lds_bw(t_l16, 16) / cus / clk_hz,
+                lds_bw(t_l4, 4) / cus / clk_hz, copy_bw);
+    CHECK(hipFree(src));
+    CHECK(hipFree(dst));
+    CHECK(hipFree(in));
+    CHECK(hipFree(out));
+    return 0;
+}

@@ -144,21 +144,54 @@ tx_status build_plan_host(const double* freqs, int32_t nchan, double tsamp, cons
     p->max_extent = max_ext;
     p->overlap = std::max(max_off, reach);
 
-    // Largest shift spread inside one stage-1 workgroup (J1 consecutive coarse
-    // trials, one channel) and one stage-2 chunk (fine trials of one group).
-    int32_t sp1 = 0;
-    for (int32_t j0 = 0; j0 < G; j0 += J1) {
-        int32_t jl = std::min(j0 + J1, G) - 1;
-        for (int32_t ch = 0; ch < nchan; ++ch)
-            sp1 = std::max(sp1, p->coarse_chan[static_cast<size_t>(jl) * nchan + ch] -
-                                    p->coarse_chan[static_cast<size_t>(j0) * nchan + ch]);
-    }
-    p->spread1 = sp1;
-    int32_t sp2 = 0;
-    for (int32_t j = 0; j < G; ++j)
-        for (int32_t s = 0; s < nsub; ++s) sp2 = std::max(sp2, p->extent[static_cast<size_t>(j) * nsub + s]);
-    p->spread2 = sp2;
+    // Transposed tables for the kernels: a wave reads the delays of its
+    // consecutive trials for one channel (or sub-band) from one row.  The
+    // trial axis is padded with copies of the last trial.
+    p->gpad = G + kTablePad;
+    p->dT.assign(static_cast<size_t>(nchan) * p->gpad, 0);
+    for (int32_t ch = 0; ch < nchan; ++ch)
+        for (int32_t j = 0; j < p->gpad; ++j)
+            p->dT[static_cast<size_t>(ch) * p->gpad + j] =
+                p->coarse_chan[static_cast<size_t>(std::min(j, G - 1)) * nchan + ch];
+    p->dpad = ndm + kTablePad;
+    p->rT.assign(static_cast<size_t>(nsub) * p->dpad, 0);
+    for (int32_t s = 0; s < nsub; ++s)
+        for (int32_t i = 0; i < p->dpad; ++i)
+            p->rT[static_cast<size_t>(s) * p->dpad + i] = p->rel[static_cast<size_t>(std::min(i, ndm - 1)) * nsub + s];
     return TX_OK;
+}
+
+int32_t plan_spread1(const tx_plan_s* p, int J) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    for (auto& e : p->spread1_cache)
+        if (e.first == J) return e.second;
+    int32_t sp = 0;
+    for (int32_t j0 = 0; j0 < p->ngroups; j0 += J) {
+        const int32_t jl = std::min(j0 + J, p->ngroups) - 1;
+        for (int32_t ch = 0; ch < p->nchan; ++ch)
+            sp = std::max(sp, p->coarse_chan[static_cast<size_t>(jl) * p->nchan + ch] -
+                                  p->coarse_chan[static_cast<size_t>(j0) * p->nchan + ch]);
+    }
+    p->spread1_cache.emplace_back(J, sp);
+    return sp;
+}
+
+int32_t plan_spread2(const tx_plan_s* p, int iw) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    for (auto& e : p->spread2_cache)
+        if (e.first == iw) return e.second;
+    int32_t sp = 0;
+    for (int32_t j = 0; j < p->ngroups; ++j) {
+        const int32_t iend = std::min((j + 1) * p->g, p->ndm);
+        for (int32_t i0 = j * p->g; i0 < iend; i0 += iw) {
+            const int32_t il = std::min(i0 + iw, iend) - 1;
+            for (int32_t s = 0; s < p->nsub; ++s)
+                sp = std::max(sp, p->rel[static_cast<size_t>(il) * p->nsub + s] -
+                                      p->rel[static_cast<size_t>(i0) * p->nsub + s]);
+        }
+    }
+    p->spread2_cache.emplace_back(iw, sp);
+    return sp;
 }
 
 }  // namespace tx

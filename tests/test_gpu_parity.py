@@ -288,3 +288,31 @@ def test_served4096_full_size_sampled_rows():
 def test_octave8192_full_size_sampled_rows():
     wl = synth.workload("octave-8192")
     _full_size_check("octave-8192", lambda ref: _pulse_rows(ref, wl) + [8191])
+
+
+# ---------------------------------------------------------------------------
+# Every tile variant and LDS size gives the same integers
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", [(256, 16, 128, 8192, 1712.0, 856.0, 306.24e-6, 508.0),
+                                  (320, 32, 240, 3000, 1088.0, 544.0, 153.12e-6, 2000.0),
+                                  (512, 2, 70, 1500, 1712.0, 856.0, 153.12e-6, 200.0)])
+def test_all_tile_variants_match_oracle(case):
+    nchan, nsub, ndm, nt, ft, fb, ts, dmmax = case
+    _say(f"tile variants case={case}")
+    freqs = synth.band_centres(ft, fb, nchan)
+    dms = np.linspace(0.0, dmmax, ndm)
+    ref = oracle.make_plan(freqs, ts, dms, nsub)
+    plan = tx.tx_plan(freqs, ts, dms, nsub)
+    x = synth.uniform_u8(nchan, nt + ref.overlap, 17)
+    want = oracle.dedisperse_subband(x, ref, nt)
+    d = device_block(x)
+    n1 = len(tx.tx_tile_variants(1))
+    n2 = len(tx.tx_tile_variants(2))
+    combos = [(s1, l1, 0, 0) for s1 in range(n1) for l1 in (0, 8192, 16384)]
+    combos += [(0, 0, s2, l2) for s2 in range(n2) for l2 in (0, 8192)]
+    for s1, l1, s2, l2 in combos:
+        _say(f"  tiles {s1} {l1} {s2} {l2}")
+        plan.set_tiles(s1, l1, s2, l2)
+        got = gpu_dedisperse(plan, x, nt, d_in=d)
+        assert np.array_equal(got[:, :nt], want), (s1, l1, s2, l2)
