@@ -284,6 +284,119 @@ tx_status tx_candidates(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64_t p
                         double* d_snr, int32_t* d_width, int64_t* d_time, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* Streams: a beam's consecutive blocks (Sec. 2.3, Fig. "dedispersion_flow") */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * A stream keeps, on the device, the last `overlap` samples of every channel
+ * of one beam (the not-yet-dedispersed tail that the paper's "shift data" step
+ * moves to the front of the buffer), so that consecutive blocks dedisperse
+ * exactly as their concatenation would.  The first `overlap` samples pushed
+ * only prime the stream; after that, a push of nt samples emits nt outputs,
+ * and output index k (counted from the first emitted sample) is
+ * Y[i][k] = sum over ch of x[ch][k + off(i, ch)] of the concatenated input.
+ */
+typedef struct tx_stream_s* tx_stream_t;
+
+/* Open a stream for blocks of at most max_block samples.  Allocates two
+ * device buffers of nchan x (overlap + max_block) bytes and the dedispersion
+ * scratch on the plan's device.  Errors: TX_EINVAL, TX_ESTATE (host-only
+ * plan), TX_ENOMEM, TX_EDEVICE. */
+tx_status tx_stream_open(tx_plan_t plan, int64_t max_block, tx_stream_t* out);
+
+/*
+ * Push nt (1..max_block) new samples of every channel.  block: nchan rows of
+ * nt samples, row c at block + c*block_pitch; host memory (pinned for an
+ * asynchronous copy) when block_on_device is 0, device memory otherwise.
+ * Writes *nt_out output samples per trial to d_out (ndm rows, out_pitch
+ * elements apart; out_pitch >= nt, even; 8-byte aligned) and sets *nt_out
+ * (0 while priming).  The block may be reused once the stream's work on
+ * `stream` has completed.  Errors: TX_EINVAL, TX_ENOMEM, TX_EDEVICE.
+ */
+tx_status tx_stream_push(tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt,
+                         int32_t block_on_device, int32_t* d_out, int64_t out_pitch, int64_t* nt_out,
+                         hipStream_t stream);
+
+/* Samples received and output samples emitted since open / reset. */
+tx_status tx_stream_position(tx_stream_t s, int64_t* received, int64_t* emitted);
+
+/* Forget the history: the next pushes prime the stream again. */
+tx_status tx_stream_reset(tx_stream_t s);
+
+/*
+ * Checkpoint: copy the held history (nchan x held samples, held <= overlap)
+ * to host_hist (row c at host_hist + c*held) and report held and the
+ * position; tx_stream_restore loads such a snapshot into an open stream of
+ * the same plan.  Both synchronise `stream`.
+ */
+tx_status tx_stream_snapshot(tx_stream_t s, uint8_t* host_hist, int64_t* held, int64_t* received,
+                             int64_t* emitted, hipStream_t stream);
+tx_status tx_stream_restore(tx_stream_t s, const uint8_t* host_hist, int64_t held, int64_t received,
+                            int64_t emitted, hipStream_t stream);
+
+/* Release a stream (after its queued work has finished).  NULL is accepted. */
+tx_status tx_stream_close(tx_stream_t s);
+
+/* ------------------------------------------------------------------------ */
+/* Batches: many beams of uneven shape in one set of persistent launches     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * A batch holds up to max_jobs jobs.  A job is one block of one beam: its
+ * plan (channels, DM grid and sample time may differ between jobs), its input
+ * (a device block, or a stream plus the next host/device block), its DM x
+ * time output and, optionally, its boxcar peaks and candidates.
+ * tx_batch_launch runs the first stage of every job in one persistent launch,
+ * then the second stage of every job (one launch per distinct trials-per-
+ * workgroup shape), then the boxcar of every job in one launch; each result is
+ * bit-identical to the job run alone.  With TX_BATCH_GRAPH the kernel launches
+ * are captured into a HIP graph on the first launch and replayed afterwards;
+ * the job table lives in device memory and is refreshed before every replay,
+ * so later launches may carry other jobs as long as every job's plan uses the
+ * same tile variant and fits the captured LDS sizes (else TX_ESTATE).
+ */
+typedef struct tx_batch_s* tx_batch_t;
+
+#define TX_BATCH_GRAPH 1u
+
+tx_status tx_batch_create(int32_t max_jobs, uint32_t flags, tx_batch_t* out);
+
+/* Remove all jobs (allocations are kept). */
+tx_status tx_batch_clear(tx_batch_t b);
+
+/* Boxcar part of a job (all device pointers; see tx_candidates).  widths is a
+ * host array copied at add time; d_cands/d_count may be NULL for peaks only. */
+typedef struct tx_batch_boxcar {
+    const int32_t* widths;
+    int32_t nw;
+    double gamma;
+    double* d_snr;
+    int32_t* d_width;
+    int64_t* d_time;
+    tx_cand* d_cands;
+    int64_t cap;
+    int64_t* d_count;
+} tx_batch_boxcar;
+
+/* Add a job on a device block (as tx_dedisperse).  box may be NULL. */
+tx_status tx_batch_add(tx_batch_t b, tx_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t nt,
+                       int32_t* d_out, int64_t out_pitch, const tx_batch_boxcar* box);
+
+/* Add a job that pushes the next block of a stream (as tx_stream_push); the
+ * number of output samples is reported by tx_batch_stream_output after the
+ * launch was queued.  A stream may appear at most once per batch. */
+tx_status tx_batch_add_stream(tx_batch_t b, tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt,
+                              int32_t block_on_device, int32_t* d_out, int64_t out_pitch,
+                              const tx_batch_boxcar* box);
+tx_status tx_batch_stream_output(tx_batch_t b, int32_t job, int64_t* nt_out);
+
+/* Queue all jobs on `stream`.  Errors: TX_EINVAL (no jobs), TX_ESTATE (a job
+ * does not fit a captured graph), TX_ENOMEM, TX_EDEVICE. */
+tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream);
+
+tx_status tx_batch_destroy(tx_batch_t b);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing                                                             */
 /* ------------------------------------------------------------------------ */
 

@@ -285,3 +285,169 @@ def tx_tile_variants(stage):
         _check(lib().tx_tile_variant_info(int(stage), v, ctypes.byref(a), ctypes.byref(b)), "tx_tile_variant_info")
         out.append((a.value, b.value))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Streams and batches
+# ---------------------------------------------------------------------------
+
+class BatchBoxcar(ctypes.Structure):
+    _fields_ = [("widths", ctypes.POINTER(ctypes.c_int32)), ("nw", ctypes.c_int32), ("gamma", ctypes.c_double),
+                ("d_snr", ctypes.c_void_p), ("d_width", ctypes.c_void_p), ("d_time", ctypes.c_void_p),
+                ("d_cands", ctypes.c_void_p), ("cap", ctypes.c_int64), ("d_count", ctypes.c_void_p)]
+
+
+TX_BATCH_GRAPH = 1
+
+_SIGS2 = {
+    "tx_stream_open": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p)]),
+    "tx_stream_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "tx_stream_position": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    "tx_stream_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "tx_stream_snapshot": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.c_void_p]),
+    "tx_stream_restore": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_void_p]),
+    "tx_stream_close": (ctypes.c_int, [ctypes.c_void_p]),
+    "tx_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
+    "tx_batch_clear": (ctypes.c_int, [ctypes.c_void_p]),
+    "tx_batch_add": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.POINTER(BatchBoxcar)]),
+    "tx_batch_add_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.POINTER(BatchBoxcar)]),
+    "tx_batch_stream_output": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "tx_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tx_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+}
+_SIGS.update(_SIGS2)
+
+
+def _setup_more():
+    L = lib()
+    for name, (res, args) in _SIGS2.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+class Stream:
+    """Owner of a tx_stream_t: a beam's device-resident overlap history."""
+
+    def __init__(self, plan, max_block):
+        self.plan = plan
+        self.max_block = int(max_block)
+        h = ctypes.c_void_p()
+        _check(_setup_more().tx_stream_open(plan.handle, self.max_block, ctypes.byref(h)), "tx_stream_open")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def push(self, block, nt, d_out, stream=None):
+        """block: uint8 tensor [nchan, >= nt] on the device or in (pinned) host memory."""
+        on_dev = 1 if block.is_cuda else 0
+        n = ctypes.c_int64()
+        _check(lib().tx_stream_push(self._h, _ptr(block), block.stride(0) * block.element_size(), int(nt), on_dev,
+                                    _ptr(d_out), d_out.stride(0), ctypes.byref(n), _stream(stream)),
+               "tx_stream_push")
+        return n.value
+
+    def position(self):
+        r, e = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tx_stream_position(self._h, ctypes.byref(r), ctypes.byref(e)), "tx_stream_position")
+        return r.value, e.value
+
+    def reset(self):
+        _check(lib().tx_stream_reset(self._h), "tx_stream_reset")
+
+    def snapshot(self, stream=None):
+        nchan = self.plan.nchan
+        buf = np.zeros(nchan * max(self.plan.overlap, 1), dtype=np.uint8)
+        held, rec, emi = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tx_stream_snapshot(self._h, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(held),
+                                        ctypes.byref(rec), ctypes.byref(emi), _stream(stream)), "tx_stream_snapshot")
+        return buf[: nchan * held.value].reshape(nchan, held.value).copy(), held.value, rec.value, emi.value
+
+    def restore(self, hist, held, received, emitted, stream=None):
+        h = np.ascontiguousarray(hist, dtype=np.uint8)
+        _check(lib().tx_stream_restore(self._h, h.ctypes.data_as(ctypes.c_void_p), int(held), int(received),
+                                       int(emitted), _stream(stream)), "tx_stream_restore")
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().tx_stream_close(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _box(widths, gamma, peaks, cands, count):
+    if peaks is None:
+        return None, None
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    cap = 0 if cands is None else (cands.numel() * cands.element_size()) // CAND_DTYPE.itemsize
+    bx = BatchBoxcar(w.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(w), float(gamma),
+                     peaks[0].data_ptr(), peaks[1].data_ptr(), peaks[2].data_ptr(),
+                     0 if cands is None else cands.data_ptr(), cap, 0 if count is None else count.data_ptr())
+    return bx, w
+
+
+class Batch:
+    """Owner of a tx_batch_t."""
+
+    def __init__(self, max_jobs, graph=False):
+        h = ctypes.c_void_p()
+        _check(_setup_more().tx_batch_create(int(max_jobs), TX_BATCH_GRAPH if graph else 0, ctypes.byref(h)),
+               "tx_batch_create")
+        self._h = h
+        self._keep = []
+
+    def clear(self):
+        _check(lib().tx_batch_clear(self._h), "tx_batch_clear")
+        self._keep = []
+
+    def add(self, plan, d_in, nt, d_out, widths=None, gamma=6.0, peaks=None, cands=None, count=None):
+        bx, w = _box(widths, gamma, peaks, cands, count)
+        self._keep.append(w)
+        _check(lib().tx_batch_add(self._h, plan.handle, _ptr(d_in), d_in.stride(0) * d_in.element_size(), int(nt),
+                                  _ptr(d_out), d_out.stride(0), None if bx is None else ctypes.byref(bx)),
+               "tx_batch_add")
+
+    def add_stream(self, stream_obj, block, nt, d_out, widths=None, gamma=6.0, peaks=None, cands=None, count=None):
+        bx, w = _box(widths, gamma, peaks, cands, count)
+        self._keep.append(w)
+        _check(lib().tx_batch_add_stream(self._h, stream_obj.handle, _ptr(block),
+                                         block.stride(0) * block.element_size(), int(nt),
+                                         1 if block.is_cuda else 0, _ptr(d_out), d_out.stride(0),
+                                         None if bx is None else ctypes.byref(bx)), "tx_batch_add_stream")
+
+    def stream_output(self, job):
+        n = ctypes.c_int64()
+        _check(lib().tx_batch_stream_output(self._h, int(job), ctypes.byref(n)), "tx_batch_stream_output")
+        return n.value
+
+    def launch(self, stream=None):
+        _check(lib().tx_batch_launch(self._h, _stream(stream)), "tx_batch_launch")
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().tx_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

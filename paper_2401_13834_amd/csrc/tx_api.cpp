@@ -13,12 +13,7 @@ namespace {
 
 thread_local char t_last_error[256] = "";
 
-tx_status from_hip(hipError_t e) {
-    if (e == hipSuccess) return TX_OK;
-    tx::note_error(e);
-    if (e == hipErrorOutOfMemory) return TX_ENOMEM;
-    return TX_EDEVICE;
-}
+tx_status from_hip(hipError_t e) { return tx::status_of(e); }
 
 // Keep freed stream-ordered scratch in the device pool instead of handing it
 // back to the driver at every synchronisation.
@@ -62,10 +57,7 @@ tx_status upload(tx_plan_s* p) {
     return TX_OK;
 }
 
-tx::Tiles current_tiles(const tx_plan_s* p) {
-    std::lock_guard<std::mutex> lock(p->mu);
-    return p->tiles;
-}
+tx::Tiles current_tiles(const tx_plan_s* p) { return tx::plan_tiles(p); }
 
 tx_status check_device_plan(const tx_plan_s* p) {
     if (!p) return TX_EINVAL;
@@ -83,15 +75,42 @@ tx_status check_dedisp_args(const tx_plan_s* p, const uint8_t* d_in, int64_t in_
     if (!d_in || !d_out) return TX_EINVAL;
     if ((reinterpret_cast<uintptr_t>(d_in) & 15) || (in_pitch & 15)) return TX_EINVAL;
     if (in_pitch < nt + p->overlap) return TX_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(d_out) & 7) || (out_pitch & 1) || out_pitch < nt) return TX_EINVAL;
-    return TX_OK;
+    return tx::check_out_args(d_out, out_pitch, nt);
 }
 
 tx_status check_boxcar_args(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64_t pitch, const int32_t* widths,
                             int32_t nw, tx::BoxcarArgs* a) {
     if (ndm < 0 || nt < 1 || nt > TX_MAX_NT_BOXCAR || pitch < nt) return TX_EINVAL;
-    if (!widths || nw < 1 || nw > TX_MAX_WIDTHS) return TX_EINVAL;
     if (ndm > 0 && !d_dmt) return TX_EINVAL;
+    const tx_status st = tx::boxcar_widths(widths, nw, nt, a);
+    if (st != TX_OK) return st;
+    a->y = d_dmt;
+    a->pitch = pitch;
+    a->ndm = ndm;
+    a->nt = static_cast<int32_t>(nt);
+    return TX_OK;
+}
+
+}  // namespace
+
+void tx::note_error(hipError_t e) {
+    std::snprintf(t_last_error, sizeof(t_last_error), "%s (%d)", hipGetErrorString(e), static_cast<int>(e));
+}
+
+tx_status tx::status_of(hipError_t e) {
+    if (e == hipSuccess) return TX_OK;
+    tx::note_error(e);
+    if (e == hipErrorOutOfMemory) return TX_ENOMEM;
+    return TX_EDEVICE;
+}
+
+tx::Tiles tx::plan_tiles(const tx_plan_s* p) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    return p->tiles;
+}
+
+tx_status tx::boxcar_widths(const int32_t* widths, int32_t nw, int64_t nt, tx::BoxcarArgs* a) {
+    if (!widths || nw < 1 || nw > TX_MAX_WIDTHS) return TX_EINVAL;
     int32_t wmax = 0;
     for (int32_t k = 0; k < nw; ++k) {
         if (widths[k] < 1 || widths[k] > TX_MAX_WIDTH) return TX_EINVAL;
@@ -100,19 +119,14 @@ tx_status check_boxcar_args(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64
         a->rsw[k] = 1.0 / std::sqrt(static_cast<double>(widths[k]));
         if (widths[k] <= nt) wmax = widths[k];
     }
-    a->y = d_dmt;
-    a->pitch = pitch;
-    a->ndm = ndm;
-    a->nt = static_cast<int32_t>(nt);
     a->nw = nw;
     a->wmax = wmax;
     return TX_OK;
 }
 
-}  // namespace
-
-void tx::note_error(hipError_t e) {
-    std::snprintf(t_last_error, sizeof(t_last_error), "%s (%d)", hipGetErrorString(e), static_cast<int>(e));
+tx_status tx::check_out_args(const int32_t* d_out, int64_t out_pitch, int64_t nt) {
+    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 7) || (out_pitch & 1) || out_pitch < nt) return TX_EINVAL;
+    return TX_OK;
 }
 
 extern "C" {

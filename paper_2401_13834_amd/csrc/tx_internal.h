@@ -121,7 +121,32 @@ struct tx_plan_s {
     mutable std::vector<std::pair<int, int32_t>> spread2_cache;   // (IW, spread)
 };
 
+struct tx_stream_s {
+    tx_plan_s* plan = nullptr;
+    int device = -1;
+    int64_t max_block = 0;
+    int64_t pitch = 0;                 // bytes per ring row (multiple of 256)
+    uint8_t* ring[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t held = 0;                  // valid samples at the front of ring[cur]
+    int64_t received = 0, emitted = 0;
+    void* ws = nullptr;                // dedispersion scratch for max_block outputs
+    int64_t ws_bytes = 0;
+};
+
 namespace tx {
+
+// Stream steps shared by tx_stream_push and batches (tx_stream.cpp): copy a
+// block behind the held history and report the outputs it completes; after
+// those outputs were computed, keep only the last `overlap` samples.
+tx_status stream_ingest(tx_stream_s* s, const uint8_t* block, int64_t block_pitch, int64_t nt, int block_on_device,
+                        hipStream_t st, int64_t* n_out);
+tx_status stream_advance(tx_stream_s* s, int64_t nt, hipStream_t st);
+tx_status check_out_args(const int32_t* d_out, int64_t out_pitch, int64_t nt);
+// Validate a width list and fill widths, 1/sqrt(w), nw and the longest width <= nt.
+tx_status boxcar_widths(const int32_t* widths, int32_t nw, int64_t nt, BoxcarArgs* a);
+tx_status status_of(hipError_t e);
+tx::Tiles plan_tiles(const tx_plan_s* p);
 
 // Host plan construction (tx_plan.cpp).
 tx_status build_plan_host(const double* freqs, int32_t nchan, double tsamp, const double* dms,
@@ -145,6 +170,21 @@ hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const ui
                              int64_t in_pitch, int64_t nt, int32_t* d_out, int64_t out_pitch,
                              uint16_t* d_B, hipStream_t stream);
 hipError_t launch_boxcar(const BoxcarArgs& a, hipStream_t stream);
+
+// Batch building blocks (tx_kernels_dedisp.hip, tx_kernels_boxcar.hip).
+void fill_stage_args(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in, int64_t in_pitch, int64_t nt,
+                     int32_t* d_out, int64_t out_pitch, uint16_t* d_B, Stage1Args* s1, Stage2Args* s2);
+int64_t stage1_tiles(const Stage1Args& a);
+int64_t stage2_tiles(const Stage2Args& a);
+int stage2_iw(int32_t g);
+hipError_t launch_stage1_batch(int variant, int lds, const Stage1Args* d_jobs, const int* d_prefix,
+                               const int* d_njobs, hipStream_t stream);
+hipError_t launch_stage2_batch(int iw, int variant, int lds, const Stage2Args* d_jobs, const int* d_prefix,
+                               const int* d_njobs, hipStream_t stream);
+// Boxcar over many row sets: rows of all jobs, job of a row by prefix sums.
+hipError_t launch_boxcar_batch(int nwt, const BoxcarArgs* d_jobs, const int* d_prefix, const int* d_njobs,
+                               hipStream_t stream);
+hipError_t launch_zero_counts(const BoxcarArgs* d_jobs, const int* d_njobs, int max_jobs, hipStream_t stream);
 
 // Largest dynamic LDS per workgroup the current device allows (capped at kMaxLds).
 int device_max_lds();

@@ -81,14 +81,10 @@ __device__ __forceinline__ void load20(const uint8_t* row, int b, int64_t avail,
 // contributions and the accumulator meet in one 3-input add.
 // ---------------------------------------------------------------------------
 template <int Q, int JW>
-__global__ __launch_bounds__(kThreads) void stage1_kernel(Stage1Args a) {
-    extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ int red[kWaves];
+__device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8_t* lds, int* red) {
     constexpr int J = JW * kWaves;
     constexpr int TT = 256 * Q;
     constexpr uint32_t kOdd = 0x0C030C01u;   // bytes 1 and 3 into 16-bit lanes
-    const int total = a.nsub * a.n_ttiles * a.n_jchunks;
-    const int tile = xcd_tile(blockIdx.x, total);
     const int jc = tile % a.n_jchunks;
     const int rest = tile / a.n_jchunks;
     const int tt = rest % a.n_ttiles;
@@ -215,13 +211,9 @@ __global__ __launch_bounds__(kThreads) void stage1_kernel(Stage1Args a) {
 // int32 accumulators.
 // ---------------------------------------------------------------------------
 template <int IW, int Q>
-__global__ __launch_bounds__(kThreads) void stage2_kernel(Stage2Args a) {
-    extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ int red[kWaves];
+__device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8_t* lds, int* red) {
     constexpr int IWP = (IW + 3) & ~3;
     constexpr int TT = 512 * Q;
-    const int total = a.ngroups * a.n_ichunks * a.n_ttiles;
-    const int tile = xcd_tile(blockIdx.x, total);
     const int ic = tile % a.n_ichunks;
     const int rest = tile / a.n_ichunks;
     const int tt = rest % a.n_ttiles;
@@ -345,6 +337,69 @@ __global__ __launch_bounds__(kThreads) void stage2_kernel(Stage2Args a) {
 }
 
 // ---------------------------------------------------------------------------
+// Kernels: one job (arguments by value, one workgroup per tile), or a batch of
+// jobs in device memory processed by a persistent grid.  In the batch form the
+// job table, its tile prefix sums and the job count are read from device
+// memory, so a captured graph can be replayed over a different set of jobs.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_job(const int* __restrict__ prefix, int njobs, int t) {
+    int lo = 0, hi = njobs;                 // prefix[lo] <= t < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int Q, int JW>
+__global__ __launch_bounds__(kThreads) void stage1_kernel(Stage1Args a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ int red[kWaves];
+    stage1_tile<Q, JW>(a, xcd_tile(blockIdx.x, a.nsub * a.n_ttiles * a.n_jchunks), lds, red);
+}
+
+template <int Q, int JW>
+__global__ __launch_bounds__(kThreads) void stage1_batch_kernel(const Stage1Args* __restrict__ jobs,
+                                                                const int* __restrict__ prefix,
+                                                                const int* __restrict__ njobs_p) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ int red[kWaves];
+    const int njobs = *njobs_p;
+    const int total = prefix[njobs];
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        const int t = xcd_tile(v, total);
+        const int jb = find_job(prefix, njobs, t);
+        const Stage1Args a = jobs[jb];
+        stage1_tile<Q, JW>(a, t - prefix[jb], lds, red);
+        __syncthreads();
+    }
+}
+
+template <int IW, int Q>
+__global__ __launch_bounds__(kThreads) void stage2_kernel(Stage2Args a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ int red[kWaves];
+    stage2_tile<IW, Q>(a, xcd_tile(blockIdx.x, a.ngroups * a.n_ichunks * a.n_ttiles), lds, red);
+}
+
+template <int IW, int Q>
+__global__ __launch_bounds__(kThreads) void stage2_batch_kernel(const Stage2Args* __restrict__ jobs,
+                                                                const int* __restrict__ prefix,
+                                                                const int* __restrict__ njobs_p) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ int red[kWaves];
+    const int njobs = *njobs_p;
+    const int total = prefix[njobs];
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        const int t = xcd_tile(v, total);
+        const int jb = find_job(prefix, njobs, t);
+        const Stage2Args a = jobs[jb];
+        stage2_tile<IW, Q>(a, t - prefix[jb], lds, red);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Variants, geometry and launches.
 // ---------------------------------------------------------------------------
 static const Stage1Variant kS1[] = {{8, 2}, {4, 4}, {4, 2}, {8, 4}, {16, 1}, {16, 2}, {8, 1}};
@@ -419,9 +474,15 @@ DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want) {
 // Raise a kernel's dynamic-LDS limit once, when a launch asks for more than
 // the runtime's default; a failure leaves the limit (and the launch then fails
 // with a reported error).
-static void allow_lds(const void* fn, int bytes, int* done) {
-    if (bytes <= 64 * 1024 || *done >= bytes) return;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess) *done = bytes;
+static void allow_lds(const void* fn, int bytes) {
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, int>> done;
+    if (bytes <= 64 * 1024) return;
+    std::lock_guard<std::mutex> lock(mu);
+    for (auto& d : done)
+        if (d.first == fn && d.second >= bytes) return;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess)
+        done.emplace_back(fn, bytes);
     (void)hipGetLastError();
 }
 
@@ -439,95 +500,128 @@ int device_max_lds() {
     return cached;
 }
 
-template <int Q, int JW>
-static hipError_t launch_s1(const Stage1Args& a, int grid, hipStream_t st) {
-    static int done = 0;
-    allow_lds(reinterpret_cast<const void*>(&stage1_kernel<Q, JW>), a.lds_bytes, &done);
-    hipLaunchKernelGGL((stage1_kernel<Q, JW>), dim3(grid), dim3(kThreads), a.lds_bytes, st, a);
-    return hipGetLastError();
+// Kernel tables: the single-job and the batch kernel of every variant.
+struct KernelPair {
+    const void* single;
+    const void* batch;
+};
+#define TX_S1(Q, JW) {reinterpret_cast<const void*>(&stage1_kernel<Q, JW>), reinterpret_cast<const void*>(&stage1_batch_kernel<Q, JW>)}
+static const KernelPair kS1Fn[kNS1] = {TX_S1(8, 2), TX_S1(4, 4), TX_S1(4, 2), TX_S1(8, 4), TX_S1(16, 1), TX_S1(16, 2), TX_S1(8, 1)};
+#undef TX_S1
+static const int kIW[] = {16, 13, 8, 4, 2, 1};
+constexpr int kNIW = 6;
+#define TX_S2(IW, Q) {reinterpret_cast<const void*>(&stage2_kernel<IW, Q>), reinterpret_cast<const void*>(&stage2_batch_kernel<IW, Q>)}
+#define TX_S2Q(IW) TX_S2(IW, 1), TX_S2(IW, 2), TX_S2(IW, 4)
+static const KernelPair kS2Fn[kNIW * kNS2] = {TX_S2Q(16), TX_S2Q(13), TX_S2Q(8), TX_S2Q(4), TX_S2Q(2), TX_S2Q(1)};
+#undef TX_S2Q
+#undef TX_S2
+
+static const KernelPair* s2_pair(int iw, int variant) {
+    for (int k = 0; k < kNIW; ++k)
+        if (kIW[k] == iw) return &kS2Fn[k * kNS2 + variant];
+    return nullptr;
 }
 
-template <int IW, int Q>
-static hipError_t launch_s2(const Stage2Args& a, int grid, hipStream_t st) {
-    static int done = 0;
-    allow_lds(reinterpret_cast<const void*>(&stage2_kernel<IW, Q>), a.lds_bytes, &done);
-    hipLaunchKernelGGL((stage2_kernel<IW, Q>), dim3(grid), dim3(kThreads), a.lds_bytes, st, a);
-    return hipGetLastError();
+static hipError_t launch(const void* fn, int grid, int lds, void** args, hipStream_t st) {
+    allow_lds(fn, lds);
+    const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, static_cast<size_t>(lds), st);
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
-template <int IW>
-static hipError_t launch_s2_q(const Stage2Args& a, int q, int grid, hipStream_t st) {
-    switch (q) {
-        case 2: return launch_s2<IW, 2>(a, grid, st);
-        case 4: return launch_s2<IW, 4>(a, grid, st);
-        default: return launch_s2<IW, 1>(a, grid, st);
-    }
+void fill_stage_args(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in, int64_t in_pitch, int64_t nt,
+                     int32_t* d_out, int64_t out_pitch, uint16_t* d_B, Stage1Args* s1, Stage2Args* s2) {
+    *s1 = Stage1Args{};
+    s1->x = d_in;
+    s1->x_pitch = in_pitch;
+    s1->x_len = nt + p->overlap;
+    s1->B = d_B;
+    s1->B_pitch = geo.B_pitch;
+    s1->dT = p->d_dT;
+    s1->gpad = p->gpad;
+    s1->nchan = p->nchan;
+    s1->nsub = p->nsub;
+    s1->m = p->m;
+    s1->ngroups = p->ngroups;
+    s1->n_jchunks = geo.n_jchunks;
+    s1->n_ttiles = geo.n_ttiles1;
+    s1->lds_bytes = geo.lds1;
+    *s2 = Stage2Args{};
+    s2->B = d_B;
+    s2->B_pitch = geo.B_pitch;
+    s2->Y = d_out;
+    s2->y_pitch = out_pitch;
+    s2->nt = nt;
+    s2->rT = p->d_rT;
+    s2->dpad = p->dpad;
+    s2->ndm = p->ndm;
+    s2->nsub = p->nsub;
+    s2->g = p->g;
+    s2->ngroups = p->ngroups;
+    s2->n_ichunks = geo.n_ichunks;
+    s2->n_ttiles = geo.n_ttiles2;
+    s2->lds_bytes = geo.lds2;
+    s2->flush = std::max(1, 65535 / (255 * p->m));
 }
+
+int64_t stage1_tiles(const Stage1Args& a) { return static_cast<int64_t>(a.nsub) * a.n_ttiles * a.n_jchunks; }
+int64_t stage2_tiles(const Stage2Args& a) { return static_cast<int64_t>(a.ngroups) * a.n_ichunks * a.n_ttiles; }
 
 hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in, int64_t in_pitch,
                              int64_t nt, int32_t* d_out, int64_t out_pitch, uint16_t* d_B, hipStream_t stream) {
     if (!geo.ok) return hipErrorInvalidValue;
-    Stage1Args s1{};
-    s1.x = d_in;
-    s1.x_pitch = in_pitch;
-    s1.x_len = nt + p->overlap;
-    s1.B = d_B;
-    s1.B_pitch = geo.B_pitch;
-    s1.dT = p->d_dT;
-    s1.gpad = p->gpad;
-    s1.nchan = p->nchan;
-    s1.nsub = p->nsub;
-    s1.m = p->m;
-    s1.ngroups = p->ngroups;
-    s1.n_jchunks = geo.n_jchunks;
-    s1.n_ttiles = geo.n_ttiles1;
-    s1.lds_bytes = geo.lds1;
-    const int grid1 = static_cast<int>(static_cast<int64_t>(s1.nsub) * s1.n_ttiles * s1.n_jchunks);
-    const Stage1Variant v1 = kS1[geo.tiles.s1];
+    Stage1Args s1;
+    Stage2Args s2;
+    fill_stage_args(p, geo, d_in, in_pitch, nt, d_out, out_pitch, d_B, &s1, &s2);
+    void* a1[] = {&s1};
     int prof = prof_begin(TX_KERNEL_STAGE1, stream);
-    hipError_t e;
-    switch (v1.q * 100 + v1.jw) {
-        case 802: e = launch_s1<8, 2>(s1, grid1, stream); break;
-        case 404: e = launch_s1<4, 4>(s1, grid1, stream); break;
-        case 402: e = launch_s1<4, 2>(s1, grid1, stream); break;
-        case 804: e = launch_s1<8, 4>(s1, grid1, stream); break;
-        case 1601: e = launch_s1<16, 1>(s1, grid1, stream); break;
-        case 1602: e = launch_s1<16, 2>(s1, grid1, stream); break;
-        case 801: e = launch_s1<8, 1>(s1, grid1, stream); break;
-        default: e = hipErrorInvalidValue; break;
-    }
+    hipError_t e = launch(kS1Fn[geo.tiles.s1].single, static_cast<int>(stage1_tiles(s1)), s1.lds_bytes, a1, stream);
     prof_end(prof, stream);
     if (e != hipSuccess) return e;
-
-    Stage2Args s2{};
-    s2.B = d_B;
-    s2.B_pitch = geo.B_pitch;
-    s2.Y = d_out;
-    s2.y_pitch = out_pitch;
-    s2.nt = nt;
-    s2.rT = p->d_rT;
-    s2.dpad = p->dpad;
-    s2.ndm = p->ndm;
-    s2.nsub = p->nsub;
-    s2.g = p->g;
-    s2.ngroups = p->ngroups;
-    s2.n_ichunks = geo.n_ichunks;
-    s2.n_ttiles = geo.n_ttiles2;
-    s2.lds_bytes = geo.lds2;
-    s2.flush = std::max(1, 65535 / (255 * p->m));
-    const int grid2 = static_cast<int>(static_cast<int64_t>(s2.ngroups) * s2.n_ichunks * s2.n_ttiles);
-    const int q2 = kS2[geo.tiles.s2].q;
+    const KernelPair* k2 = s2_pair(geo.iw, geo.tiles.s2);
+    if (!k2) return hipErrorInvalidValue;
+    void* a2[] = {&s2};
     prof = prof_begin(TX_KERNEL_STAGE2, stream);
-    switch (geo.iw) {
-        case 16: e = launch_s2_q<16>(s2, q2, grid2, stream); break;
-        case 13: e = launch_s2_q<13>(s2, q2, grid2, stream); break;
-        case 8: e = launch_s2_q<8>(s2, q2, grid2, stream); break;
-        case 4: e = launch_s2_q<4>(s2, q2, grid2, stream); break;
-        case 2: e = launch_s2_q<2>(s2, q2, grid2, stream); break;
-        default: e = launch_s2_q<1>(s2, q2, grid2, stream); break;
-    }
+    e = launch(k2->single, static_cast<int>(stage2_tiles(s2)), s2.lds_bytes, a2, stream);
     prof_end(prof, stream);
     return e;
 }
+
+// Persistent grid for a batch kernel: the resident workgroups of every CU,
+// rounded down to a multiple of the 8 XCDs.
+static int persistent_grid(const void* fn, int lds) {
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    allow_lds(fn, lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, static_cast<size_t>(lds)) != hipSuccess ||
+        per <= 0)
+        per = 1;
+    (void)hipGetLastError();
+    return std::max(8, (per * cus) / 8 * 8);
+}
+
+hipError_t launch_stage1_batch(int variant, int lds, const Stage1Args* d_jobs, const int* d_prefix, const int* d_njobs,
+                               hipStream_t stream) {
+    if (variant < 0 || variant >= kNS1) return hipErrorInvalidValue;
+    const void* fn = kS1Fn[variant].batch;
+    void* a[] = {&d_jobs, &d_prefix, &d_njobs};
+    const int prof = prof_begin(TX_KERNEL_STAGE1, stream);
+    const hipError_t e = launch(fn, persistent_grid(fn, lds), lds, a, stream);
+    prof_end(prof, stream);
+    return e;
+}
+
+hipError_t launch_stage2_batch(int iw, int variant, int lds, const Stage2Args* d_jobs, const int* d_prefix,
+                               const int* d_njobs, hipStream_t stream) {
+    const KernelPair* k = (variant >= 0 && variant < kNS2) ? s2_pair(iw, variant) : nullptr;
+    if (!k) return hipErrorInvalidValue;
+    void* a[] = {&d_jobs, &d_prefix, &d_njobs};
+    const int prof = prof_begin(TX_KERNEL_STAGE2, stream);
+    const hipError_t e = launch(k->batch, persistent_grid(k->batch, lds), lds, a, stream);
+    prof_end(prof, stream);
+    return e;
+}
+
+int stage2_iw(int32_t g) { return pick_iw(g); }
 
 }  // namespace tx

@@ -1,0 +1,160 @@
+// Streams: per-beam device history of the last `overlap` samples, so that
+// consecutive blocks dedisperse exactly as their concatenation would (the
+// paper's "write data" and "shift data" steps, Sec. 2.3).
+#include <algorithm>
+#include <new>
+
+#include "tx_internal.h"
+
+namespace tx {
+
+tx_status stream_ingest(tx_stream_s* s, const uint8_t* block, int64_t block_pitch, int64_t nt, int block_on_device,
+                        hipStream_t st, int64_t* n_out) {
+    const tx_plan_s* p = s->plan;
+    if (nt < 1 || nt > s->max_block || !block || block_pitch < nt || !n_out) return TX_EINVAL;
+    const hipMemcpyKind kind = block_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e = hipMemcpy2DAsync(s->ring[s->cur] + s->held, static_cast<size_t>(s->pitch), block,
+                                    static_cast<size_t>(block_pitch), static_cast<size_t>(nt),
+                                    static_cast<size_t>(p->nchan), kind, st);
+    if (e != hipSuccess) return status_of(e);
+    *n_out = std::max<int64_t>(0, s->held + nt - p->overlap);
+    return TX_OK;
+}
+
+tx_status stream_advance(tx_stream_s* s, int64_t nt, hipStream_t st) {
+    const int64_t O = s->plan->overlap;
+    const int64_t have = s->held + nt;
+    const int64_t n_out = std::max<int64_t>(0, have - O);
+    if (have > O && O > 0) {
+        uint8_t* src = s->ring[s->cur] + (have - O);
+        uint8_t* dst = s->ring[s->cur ^ 1];
+        hipError_t e = hipMemcpy2DAsync(dst, static_cast<size_t>(s->pitch), src, static_cast<size_t>(s->pitch),
+                                        static_cast<size_t>(O), static_cast<size_t>(s->plan->nchan),
+                                        hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return status_of(e);
+        s->cur ^= 1;
+        s->held = O;
+    } else {
+        s->held = std::min(have, O);
+    }
+    s->received += nt;
+    s->emitted += n_out;
+    return TX_OK;
+}
+
+}  // namespace tx
+
+static void free_stream(tx_stream_s* s) {
+    for (auto& r : s->ring)
+        if (r) (void)hipFree(r);
+    if (s->ws) (void)hipFree(s->ws);
+    delete s;
+}
+
+extern "C" {
+
+tx_status tx_stream_open(tx_plan_t plan, int64_t max_block, tx_stream_t* out) {
+    if (!plan || !out || max_block < 1 || max_block > (int64_t(1) << 30)) return TX_EINVAL;
+    *out = nullptr;
+    if (!plan->on_device) return TX_ESTATE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return TX_EDEVICE;
+    if (dev != plan->device) return TX_ESTATE;
+    const tx::DedispGeom geo = tx::dedisp_geometry(plan, max_block, tx::plan_tiles(plan));
+    if (!geo.ok) return TX_ENOTSUP;
+    tx_stream_s* s = new (std::nothrow) tx_stream_s();
+    if (!s) return TX_ENOMEM;
+    s->plan = plan;
+    s->device = dev;
+    s->max_block = max_block;
+    s->pitch = (plan->overlap + max_block + 255) / 256 * 256;
+    const size_t bytes = static_cast<size_t>(s->pitch) * plan->nchan;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&s->ring[0]), bytes);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->ring[1]), bytes);
+    s->ws_bytes = geo.ws_bytes;
+    if (e == hipSuccess) e = hipMalloc(&s->ws, static_cast<size_t>(std::max<int64_t>(s->ws_bytes, 256)));
+    if (e != hipSuccess) {
+        free_stream(s);
+        return tx::status_of(e);
+    }
+    *out = s;
+    return TX_OK;
+}
+
+tx_status tx_stream_push(tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt, int32_t block_on_device,
+                         int32_t* d_out, int64_t out_pitch, int64_t* nt_out, hipStream_t stream) {
+    if (!s || !nt_out) return TX_EINVAL;
+    tx_status st = tx::check_out_args(d_out, out_pitch, nt);
+    if (st != TX_OK) return st;
+    int64_t n_out = 0;
+    st = tx::stream_ingest(s, block, block_pitch, nt, block_on_device, stream, &n_out);
+    if (st != TX_OK) return st;
+    if (n_out > 0) {
+        const tx::DedispGeom geo = tx::dedisp_geometry(s->plan, n_out, tx::plan_tiles(s->plan));
+        if (!geo.ok || geo.ws_bytes > s->ws_bytes) return TX_ENOTSUP;
+        const hipError_t e = tx::launch_dedisperse(s->plan, geo, s->ring[s->cur], s->pitch, n_out, d_out, out_pitch,
+                                                   static_cast<uint16_t*>(s->ws), stream);
+        if (e != hipSuccess) return tx::status_of(e);
+    }
+    st = tx::stream_advance(s, nt, stream);
+    if (st != TX_OK) return st;
+    *nt_out = n_out;
+    return TX_OK;
+}
+
+tx_status tx_stream_position(tx_stream_t s, int64_t* received, int64_t* emitted) {
+    if (!s || !received || !emitted) return TX_EINVAL;
+    *received = s->received;
+    *emitted = s->emitted;
+    return TX_OK;
+}
+
+tx_status tx_stream_reset(tx_stream_t s) {
+    if (!s) return TX_EINVAL;
+    s->held = 0;
+    s->received = 0;
+    s->emitted = 0;
+    return TX_OK;
+}
+
+tx_status tx_stream_snapshot(tx_stream_t s, uint8_t* host_hist, int64_t* held, int64_t* received, int64_t* emitted,
+                             hipStream_t stream) {
+    if (!s || !held || !received || !emitted || (s->held > 0 && !host_hist)) return TX_EINVAL;
+    if (s->held > 0) {
+        hipError_t e = hipMemcpy2DAsync(host_hist, static_cast<size_t>(s->held), s->ring[s->cur],
+                                        static_cast<size_t>(s->pitch), static_cast<size_t>(s->held),
+                                        static_cast<size_t>(s->plan->nchan), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return tx::status_of(e);
+    }
+    *held = s->held;
+    *received = s->received;
+    *emitted = s->emitted;
+    return TX_OK;
+}
+
+tx_status tx_stream_restore(tx_stream_t s, const uint8_t* host_hist, int64_t held, int64_t received, int64_t emitted,
+                            hipStream_t stream) {
+    if (!s || held < 0 || held > s->plan->overlap || received < held || emitted < 0 || (held > 0 && !host_hist))
+        return TX_EINVAL;
+    if (received != emitted + held) return TX_EINVAL;
+    if (held > 0) {
+        hipError_t e = hipMemcpy2DAsync(s->ring[s->cur], static_cast<size_t>(s->pitch), host_hist,
+                                        static_cast<size_t>(held), static_cast<size_t>(held),
+                                        static_cast<size_t>(s->plan->nchan), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return tx::status_of(e);
+    }
+    s->held = held;
+    s->received = received;
+    s->emitted = emitted;
+    return TX_OK;
+}
+
+tx_status tx_stream_close(tx_stream_t s) {
+    if (!s) return TX_OK;
+    free_stream(s);
+    return TX_OK;
+}
+
+}  // extern "C"
