@@ -29,9 +29,13 @@ PEAK_ADD16 = 256 * 4 * 16 * 2 * 2.4e9   # 16-bit integer adds/s: 256 CUs x 64 la
 PAPER_DM_SAMPLES_PER_S = 4096 / 153e-6  # real time on one CPU core, 4096 channels and trials, 153 us
 
 
-def kernel_source_hash():
+KERNEL_SOURCES = {"stage1": "tx_kernels_dedisp.hip", "stage2": "tx_kernels_dedisp.hip",
+                  "boxcar": "tx_kernels_boxcar.hip"}
+
+
+def kernel_source_hash(kernel):
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2401_13834_amd", "csrc", "tx_kernels.hip"), "rb") as f:
+    with open(os.path.join(ROOT, "paper_2401_13834_amd", "csrc", KERNEL_SOURCES[kernel]), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -46,27 +50,14 @@ def load_traffic(kernel, workload):
     except (OSError, ValueError):
         return None
     ent = data.get(f"{kernel}:{workload}")
-    if not ent or ent.get("source_hash") != kernel_source_hash():
+    if not ent or ent.get("source_hash") != kernel_source_hash(kernel):
         return None
     return ent.get("hbm_bytes_per_launch")
 
 
 def make_input(tx, plan, wl, synth):
-    """Seeded noise (pooled rows) with the workload's pulses, placed with the
-    plan's own brute-force delays."""
-    nchan = len(wl.freqs)
-    n = wl.nt + plan.overlap
-    pulses = []
-    for spec in wl.pulses:
-        kind, dm, t0, w = spec[0], spec[1], spec[2], spec[3]
-        start = t0 + plan.delays(dm).astype(np.int64)
-        if kind == "snr-index":
-            amp = synth.spectral_amplitudes(wl.freqs, 816.0, -1.5, 1.0)
-            amp = amp * (16.0 * spec[4] / np.sqrt(w) / amp.sum())
-        else:
-            amp = synth.pulse_amplitude(spec, w, nchan)
-        pulses.append((start, w, amp))
-    return synth.pooled_normal_u8(nchan, n, wl.seed, pulses=pulses)
+    """Seeded noise (pooled rows) with the workload's pulses."""
+    return synth.pooled_normal_u8(len(wl.freqs), wl.nt + plan.overlap, wl.seed, pulses=place_pulses(plan, wl, synth))
 
 
 def cpu_baseline(wl, x, g, seconds):
@@ -93,6 +84,132 @@ def cpu_baseline(wl, x, g, seconds):
                       f"dedispersion + peaks + candidates, NumPy single-threaded, {dt:.1f} s"}
 
 
+def place_pulses(plan, wl, synth):
+    """(start[nchan], width, amplitude) of the workload's pulses, placed with
+    the plan's own brute-force delays."""
+    nchan = len(wl.freqs)
+    out = []
+    for spec in wl.pulses:
+        kind, dm, t0, w = spec[0], spec[1], spec[2], spec[3]
+        start = t0 + plan.delays(dm).astype(np.int64)
+        if kind == "snr-index":
+            amp = synth.spectral_amplitudes(wl.freqs, 816.0, -1.5, 1.0)
+            amp = amp * (16.0 * spec[4] / np.sqrt(w) / amp.sum())
+        else:
+            amp = synth.pulse_amplitude(spec, w, nchan)
+        out.append((start, w, amp))
+    return out
+
+
+def batched_leg(torch, tx, synth, steps):
+    """64 beams of uneven shape (channels 1024-4096, blocks 16384-65536, 512-4096
+    DM trials up to DM 3000, sub-band count chosen by each plan) dedispersed
+    with peaks and candidates in one batch launch replayed as a HIP graph;
+    against the same jobs run one beam per launch."""
+    beams = synth.batched_beams()
+    jobs = []
+    for wl in beams:
+        plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, 0)
+        nchan, ndm, nt = len(wl.freqs), plan.ndm, wl.nt
+        pitch = (nt + plan.overlap + 255) // 256 * 256
+        d_in = synth.device_normal_u8(torch, nchan, pitch, wl.seed, pulses=place_pulses(plan, wl, synth))
+        y = torch.empty((ndm, nt), dtype=torch.int32, device="cuda")
+        peaks = (torch.empty(ndm, dtype=torch.float64, device="cuda"),
+                 torch.empty(ndm, dtype=torch.int32, device="cuda"),
+                 torch.empty(ndm, dtype=torch.int64, device="cuda"))
+        cands = torch.empty((1 << 16, 3), dtype=torch.int64, device="cuda")
+        count = torch.zeros(1, dtype=torch.int64, device="cuda")
+        jobs.append(dict(wl=wl, plan=plan, d_in=d_in, y=y, peaks=peaks, cands=cands, count=count))
+    dm_samples = sum(j["plan"].ndm * j["wl"].nt for j in jobs)
+    stream = torch.cuda.Stream()
+    batch = tx.Batch(len(jobs), graph=True)
+    for j in jobs:
+        batch.add(j["plan"], j["d_in"], j["wl"].nt, j["y"], widths=j["wl"].widths, gamma=j["wl"].gamma,
+                  peaks=j["peaks"], cands=j["cands"], count=j["count"])
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        batch.launch(stream)                       # captures the graph
+        stream.synchronize()
+        ev0.record(stream)
+        for _ in range(steps):
+            batch.launch(stream)
+        ev1.record(stream)
+        stream.synchronize()
+        t_batch = ev0.elapsed_time(ev1) * 1e-3 / steps
+        ncand = sum(int(j["count"].item()) for j in jobs)
+
+        def plain_round():
+            for j in jobs:
+                tx.tx_dedisperse(j["plan"], j["d_in"], j["wl"].nt, j["y"], stream=stream)
+                tx.tx_candidates(j["y"], j["wl"].nt, j["wl"].widths, j["wl"].gamma, j["cands"], j["count"],
+                                 peaks=j["peaks"], stream=stream)
+        plain_round()
+        stream.synchronize()
+        ev0.record(stream)
+        plain_round()
+        ev1.record(stream)
+        stream.synchronize()
+        t_plain = ev0.elapsed_time(ev1) * 1e-3
+    nsubs = {}
+    for j in jobs:
+        nsubs[str(j["plan"].nsub)] = nsubs.get(str(j["plan"].nsub), 0) + 1
+    batch.close()
+    del jobs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    tx.tx_pool_trim()
+    return {"workload": "batched-64", "beams": len(beams), "value": dm_samples / t_batch,
+            "unit": "DM-trial samples/s", "ms_per_launch": t_batch * 1e3, "launches": steps, "graph": True,
+            "plain_value": dm_samples / t_plain, "plain_ms": t_plain * 1e3,
+            "speedup_vs_plain": t_plain / t_batch, "dm_samples_per_launch": dm_samples, "nsub_chosen": nsubs,
+            "candidates": ncand}
+
+
+def served_leg(torch, tx, synth, serve, speeds, source, lanes, max_slots):
+    """256 beams stream consecutive 4096-channel, 32768-sample blocks at
+    Poisson arrivals (mean gap = block duration / speed) through the
+    continuous-batching loop; p50/p99 latency from arrival to host-visible
+    candidates."""
+    wl = synth.workload("served-4096")
+    plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    nchan, nt = len(wl.freqs), wl.nt
+    t_blk = nt * wl.tsamp
+    pool = []
+    for i in range(4):
+        d = synth.device_normal_u8(torch, nchan, nt, 4000 + i)
+        pool.append(d if source == "device" else d.cpu().pin_memory())
+    nbeams = 256
+    srv = serve.Server([plan] * nbeams, nt, wl.widths, gamma=wl.gamma, cap=4096, lanes=lanes, max_slots=max_slots,
+                       graph=True, source=source, keep=())
+
+    def data(b, k):
+        return pool[(b * 7 + k) % len(pool)]
+
+    runs = []
+    for speed, nblocks in speeds:
+        for st in srv.streams:
+            st.reset()
+        arr = synth.poisson_arrivals(nbeams, nblocks, t_blk, speed, 4 + speed)
+        _, stats = srv.run(arr, data)
+        runs.append({"speed": speed, "blocks": stats.blocks, "batches": stats.batches,
+                     "mean_batch": round(stats.mean_batch, 2), "p50_ms": stats.p50_s * 1e3,
+                     "p99_ms": stats.p99_s * 1e3, "max_ms": stats.max_s * 1e3, "value": stats.throughput,
+                     "gpu_busy": stats.gpu_s / stats.wall_s if stats.wall_s > 0 else None,
+                     "p99_below_block": stats.p99_s < t_blk})
+        print(f"served speed {speed}: {json.dumps(runs[-1])}", file=sys.stderr, flush=True)
+    slots = srv.slots
+    srv.close()
+    del pool
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    tx.tx_pool_trim()
+    ok = [r["speed"] for r in runs if r["p99_below_block"]]
+    return {"workload": "served-4096", "beams": nbeams, "source": source, "lanes": lanes, "slots": slots,
+            "block_duration_ms": t_blk * 1e3, "unit": "DM-trial samples/s", "runs": runs,
+            "max_speed_p99_below_block": max(ok) if ok else None,
+            "value": max(r["value"] for r in runs)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +218,14 @@ def main():
     ap.add_argument("--workload", default="paper-4096")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-beam batched launch")
+    ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--no-served", action="store_true", help="skip the served-stream runs")
+    ap.add_argument("--served-speeds", default="1:2,8:9,24:13",
+                    help="speed:blocks-per-beam pairs of the served runs")
+    ap.add_argument("--served-source", choices=("host", "device"), default="host")
+    ap.add_argument("--served-lanes", type=int, default=2)
+    ap.add_argument("--served-slots", type=int, default=32)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy the DM x time array once (a plain copy of known size "
                          "whose HBM counters scale the kernels' counters)")
@@ -195,6 +320,18 @@ def main():
         "candidates_last_step": ncand,
         "roofline": roofline,
     }
+    del d_in, y, cands
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    tx.tx_pool_trim()
+    if not args.no_batched:
+        out["batched"] = batched_leg(torch, tx, synth, args.batched_steps)
+        print(f"batched: {json.dumps(out['batched'])}", file=sys.stderr, flush=True)
+    if not args.no_served:
+        from paper_2401_13834_amd import serve
+        speeds = [tuple(int(v) for v in p.split(":")) for p in args.served_speeds.split(",") if p]
+        out["served"] = served_leg(torch, tx, synth, serve, speeds, args.served_source, args.served_lanes,
+                                   args.served_slots)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, x, plan.g, args.cpu_seconds)
     print(json.dumps(out), flush=True)

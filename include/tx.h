@@ -50,6 +50,11 @@ typedef enum tx_status {
 /* Human-readable name of a status code.  Never NULL. */
 const char* tx_status_str(tx_status s);
 
+/* Return the stream-ordered scratch that libtx calls have freed on the
+ * current device to the system (libtx keeps it pooled for reuse otherwise).
+ * Synchronises the device.  Errors: TX_EDEVICE. */
+tx_status tx_pool_trim(void);
+
 /* Version string of the library build. */
 const char* tx_version(void);
 
@@ -200,7 +205,7 @@ tx_status tx_dedisperse_ws(tx_plan_t plan, const uint8_t* d_in, int64_t in_pitch
 /* ------------------------------------------------------------------------ */
 
 typedef struct tx_tiles {
-    int32_t stage1;      /* first-stage variant, 0..count-1, or -1 for the default */
+    int32_t stage1;      /* first-stage variant, 0..count-1, or -1 for the library's default */
     int32_t stage1_lds;  /* LDS bytes per first-stage workgroup, 0 = default (raised
                             to what the plan's longest staged row needs) */
     int32_t stage2;      /* second-stage variant, or -1 */
@@ -221,6 +226,20 @@ tx_status tx_tile_variant_info(int32_t stage, int32_t variant, int32_t* outputs_
  * queued from another thread. */
 tx_status tx_plan_get_tiles(tx_plan_t plan, tx_tiles* tiles);
 tx_status tx_plan_set_tiles(tx_plan_t plan, const tx_tiles* tiles);
+
+/*
+ * Autotuner: time every first-stage variant with the default second stage,
+ * then every second-stage variant with the fastest first stage, dedispersing
+ * a scratch block of nt outputs of the plan's shape on `stream` (effort 0:
+ * default LDS sizes; 1: also 16, 24, 32 and 48 KB per workgroup), and store
+ * the fastest pair in the plan as tx_plan_set_tiles would.  Scratch comes
+ * from the device's stream-ordered pool; the call synchronises `stream`
+ * (not for use under graph capture).  *best_ms (may be NULL) receives the
+ * measured time of one dedispersion with the chosen tiles.  Errors:
+ * TX_EINVAL, TX_ESTATE (host-only plan or another device), TX_ENOMEM,
+ * TX_EDEVICE, TX_ENOTSUP (no variant fits the device's LDS).
+ */
+tx_status tx_plan_autotune(tx_plan_t plan, int64_t nt, int32_t effort, double* best_ms, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Matched filter (Sec. 2.4) and DM-time candidates (Sec. 2.5)               */
@@ -298,10 +317,13 @@ tx_status tx_candidates(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64_t p
  */
 typedef struct tx_stream_s* tx_stream_t;
 
-/* Open a stream for blocks of at most max_block samples.  Allocates two
- * device buffers of nchan x (overlap + max_block) bytes and the dedispersion
- * scratch on the plan's device.  Errors: TX_EINVAL, TX_ESTATE (host-only
- * plan), TX_ENOMEM, TX_EDEVICE. */
+/* Open a stream for blocks of at most max_block samples.  Allocates one
+ * device buffer of nchan x (overlap + max_block) bytes (rows rounded up to
+ * 256 bytes) on the plan's device; the first-stage scratch of standalone
+ * pushes (tx_dedisperse_ws_size(max_block)) comes from the device's
+ * stream-ordered pool on the first push that emits output, and stream jobs of
+ * a batch use the batch's scratch instead.  Errors: TX_EINVAL, TX_ESTATE
+ * (host-only plan), TX_ENOMEM, TX_EDEVICE. */
 tx_status tx_stream_open(tx_plan_t plan, int64_t max_block, tx_stream_t* out);
 
 /*
@@ -353,7 +375,8 @@ tx_status tx_stream_close(tx_stream_t s);
  * are captured into a HIP graph on the first launch and replayed afterwards;
  * the job table lives in device memory and is refreshed before every replay,
  * so later launches may carry other jobs as long as every job's plan uses the
- * same tile variant and fits the captured LDS sizes (else TX_ESTATE).
+ * same tile variant and fits the captured LDS sizes and grids (else
+ * TX_ESTATE; tx_batch_reserve sizes a graph for the largest launch).
  */
 typedef struct tx_batch_s* tx_batch_t;
 
@@ -390,8 +413,22 @@ tx_status tx_batch_add_stream(tx_batch_t b, tx_stream_t s, const uint8_t* block,
                               const tx_batch_boxcar* box);
 tx_status tx_batch_stream_output(tx_batch_t b, int32_t job, int64_t* nt_out);
 
-/* Queue all jobs on `stream`.  Errors: TX_EINVAL (no jobs), TX_ESTATE (a job
- * does not fit a captured graph), TX_ENOMEM, TX_EDEVICE. */
+/* Declare, before the first launch, that up to `count` jobs of one launch
+ * may use `plan` with at most max_nt output samples and at most nw boxcar
+ * widths (0: no boxcar).  A graph captured later is sized for the sum of all
+ * reservations (LDS, kernels and grids), so any later mix within them replays
+ * without TX_ESTATE.  All reserved plans must use the same tile variants
+ * (else TX_EINVAL); the first reserved plan's variants then apply to every
+ * job.  Errors: TX_EINVAL, TX_ESTATE (plan on another device), TX_ENOTSUP
+ * (capacity beyond 2^31 - 1 tiles). */
+tx_status tx_batch_reserve(tx_batch_t b, tx_plan_t plan, int32_t nw, int64_t max_nt, int32_t count);
+
+/* Queue all jobs on `stream`.  The job table is uploaded on `stream` and the
+ * host call waits until the previous launch of this batch has consumed its
+ * table, so consecutive launches of one batch (and the pushes of one stream)
+ * must be queued on the same HIP stream or ordered by the caller.  Errors:
+ * TX_EINVAL (no jobs), TX_ESTATE (a job does not fit a captured graph),
+ * TX_ENOMEM, TX_EDEVICE. */
 tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream);
 
 tx_status tx_batch_destroy(tx_batch_t b);

@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtx.so")
 
-TX_OK = 0
+TX_OK, TX_EINVAL, TX_ENOMEM, TX_EDEVICE, TX_ESTATE, TX_EOVERFLOW, TX_ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 STATUS = {0: "TX_OK", -1: "TX_EINVAL", -2: "TX_ENOMEM", -3: "TX_EDEVICE", -4: "TX_ESTATE",
           -5: "TX_EOVERFLOW", -6: "TX_ENOTSUP"}
 TX_PLAN_HOST_ONLY = 1
@@ -190,6 +190,14 @@ class Plan:
         t = Tiles(stage1, stage1_lds, stage2, stage2_lds)
         _check(lib().tx_plan_set_tiles(self._h, ctypes.byref(t)), "tx_plan_set_tiles")
 
+    def autotune(self, nt, effort=1, stream=None):
+        """Measure the tile variants for blocks of ``nt`` outputs on the current
+        device and keep the fastest; returns its time in milliseconds."""
+        ms = ctypes.c_double()
+        _check(_setup_more().tx_plan_autotune(self._h, int(nt), int(effort), ctypes.byref(ms), _stream(stream)),
+               "tx_plan_autotune")
+        return ms.value
+
     def ws_size(self, nt):
         b = ctypes.c_int64()
         _check(lib().tx_dedisperse_ws_size(self._h, int(nt), ctypes.byref(b)), "tx_dedisperse_ws_size")
@@ -322,6 +330,11 @@ _SIGS2 = {
                                            ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                            ctypes.POINTER(BatchBoxcar)]),
     "tx_batch_stream_output": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "tx_batch_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                        ctypes.c_int32]),
+    "tx_plan_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "tx_pool_trim": (ctypes.c_int, []),
     "tx_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "tx_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
@@ -335,6 +348,11 @@ def _setup_more():
         fn.restype = res
         fn.argtypes = args
     return L
+
+
+def tx_pool_trim():
+    """Give pooled scratch of the current device back to the system."""
+    _check(_setup_more().tx_pool_trim(), "tx_pool_trim")
 
 
 class Stream:
@@ -432,6 +450,11 @@ class Batch:
                                          block.stride(0) * block.element_size(), int(nt),
                                          1 if block.is_cuda else 0, _ptr(d_out), d_out.stride(0),
                                          None if bx is None else ctypes.byref(bx)), "tx_batch_add_stream")
+
+    def reserve(self, plan, nw, max_nt, count=1):
+        """Size a graph captured later for ``count`` jobs of ``plan`` with up to
+        ``max_nt`` outputs and ``nw`` boxcar widths per launch."""
+        _check(lib().tx_batch_reserve(self._h, plan.handle, int(nw), int(max_nt), int(count)), "tx_batch_reserve")
 
     def stream_output(self, job):
         n = ctypes.c_int64()

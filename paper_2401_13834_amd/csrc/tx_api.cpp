@@ -17,20 +17,6 @@ tx_status from_hip(hipError_t e) { return tx::status_of(e); }
 
 // Keep freed stream-ordered scratch in the device pool instead of handing it
 // back to the driver at every synchronisation.
-tx_status retain_pool(int dev) {
-    static std::mutex mu;
-    static bool done[64] = {};
-    std::lock_guard<std::mutex> lock(mu);
-    if (dev < 0 || dev >= 64) return TX_EDEVICE;
-    if (done[dev]) return TX_OK;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return TX_EDEVICE;
-    uint64_t thr = UINT64_MAX;
-    if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr) != hipSuccess) return TX_EDEVICE;
-    done[dev] = true;
-    return TX_OK;
-}
-
 void release_device(tx_plan_s* p) {
     if (p->d_dT) (void)hipFree(p->d_dT);
     if (p->d_rT) (void)hipFree(p->d_rT);
@@ -107,6 +93,20 @@ tx_status tx::status_of(hipError_t e) {
 tx::Tiles tx::plan_tiles(const tx_plan_s* p) {
     std::lock_guard<std::mutex> lock(p->mu);
     return p->tiles;
+}
+
+tx_status tx::retain_pool(int dev) {
+    static std::mutex mu;
+    static bool done[64] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    if (dev < 0 || dev >= 64) return TX_EDEVICE;
+    if (done[dev]) return TX_OK;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return TX_EDEVICE;
+    uint64_t thr = UINT64_MAX;
+    if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr) != hipSuccess) return TX_EDEVICE;
+    done[dev] = true;
+    return TX_OK;
 }
 
 tx_status tx::boxcar_widths(const int32_t* widths, int32_t nw, int64_t nt, tx::BoxcarArgs* a) {
@@ -226,6 +226,16 @@ tx_status tx_plan_delays(tx_plan_t p, double dm, int32_t* host_delay) {
     return TX_OK;
 }
 
+tx_status tx_pool_trim(void) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return TX_EDEVICE;
+    hipMemPool_t pool;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipDeviceGetDefaultMemPool(&pool, dev);
+    if (e == hipSuccess) e = hipMemPoolTrimTo(pool, 0);
+    return from_hip(e);
+}
+
 tx_status tx_plan_destroy(tx_plan_t p) {
     if (!p) return TX_OK;
     release_device(p);
@@ -258,7 +268,7 @@ tx_status tx_dedisperse(tx_plan_t p, const uint8_t* d_in, int64_t in_pitch, int6
     if (st != TX_OK) return st;
     st = check_dedisp_args(p, d_in, in_pitch, nt, d_out, out_pitch);
     if (st != TX_OK || nt == 0) return st;
-    st = retain_pool(p->device);
+    st = tx::retain_pool(p->device);
     if (st != TX_OK) return st;
     const tx::DedispGeom geo = tx::dedisp_geometry(p, nt, current_tiles(p));
     if (!geo.ok) return TX_ENOTSUP;

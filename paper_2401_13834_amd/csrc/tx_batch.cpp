@@ -51,13 +51,8 @@ struct Signature {            // what a captured graph bakes in
     bool groups[kNIW] = {};
     int nwt = 0;
     bool any_box = false;
-    bool operator==(const Signature& o) const {
-        if (s1 != o.s1 || lds1 != o.lds1 || s2 != o.s2 || lds2 != o.lds2 || nwt != o.nwt || any_box != o.any_box)
-            return false;
-        for (int k = 0; k < kNIW; ++k)
-            if (groups[k] != o.groups[k]) return false;
-        return true;
-    }
+    // grids: first-stage tiles, second-stage tiles per group, boxcar rows
+    int64_t g1 = 0, g2[kNIW] = {}, gb = 0;
 };
 
 }  // namespace
@@ -74,13 +69,17 @@ struct tx_batch_s {
     uint8_t* h_tab = nullptr;
     hipEvent_t uploaded = nullptr;     // the last upload from h_tab has been consumed
     bool upload_pending = false;
-    // scratch for device-block jobs (first-stage series)
+    // first-stage series of every job of a launch
     void* scratch = nullptr;
     int64_t scratch_bytes = 0;
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     Signature sig;
+    // plans declared ahead of the first launch (tx_batch_reserve)
+    bool reserved = false;
+    Signature floor;
+    tx::Tiles tiles{};
 };
 
 namespace {
@@ -123,15 +122,17 @@ hipError_t run_kernels(tx_batch_s* b, const Signature& sig, hipStream_t st) {
         e = tx::launch_zero_counts(bx, ints + b->L.nb(), b->max_jobs, st);
         if (e != hipSuccess) return e;
     }
-    e = tx::launch_stage1_batch(sig.s1, sig.lds1, s1, ints + b->L.p1(), ints + b->L.n1(), st);
+    e = tx::launch_stage1_batch(sig.s1, sig.lds1, s1, ints + b->L.p1(), ints + b->L.n1(), static_cast<int>(sig.g1),
+                                st);
     if (e != hipSuccess) return e;
     for (int g = 0; g < kNIW; ++g) {
         if (!sig.groups[g]) continue;
         e = tx::launch_stage2_batch(kIWs[g], sig.s2, sig.lds2, s2 + static_cast<size_t>(g) * b->max_jobs,
-                                    ints + b->L.p2(g), ints + b->L.n2(g), st);
+                                    ints + b->L.p2(g), ints + b->L.n2(g), static_cast<int>(sig.g2[g]), st);
         if (e != hipSuccess) return e;
     }
-    if (sig.any_box) e = tx::launch_boxcar_batch(sig.nwt, bx, ints + b->L.pb(), ints + b->L.nb(), st);
+    if (sig.any_box)
+        e = tx::launch_boxcar_batch(sig.nwt, bx, ints + b->L.pb(), ints + b->L.nb(), static_cast<int>(sig.gb), st);
     return e;
 }
 
@@ -232,6 +233,39 @@ tx_status tx_batch_add_stream(tx_batch_t b, tx_stream_t s, const uint8_t* block,
     return TX_OK;
 }
 
+tx_status tx_batch_reserve(tx_batch_t b, tx_plan_t plan, int32_t nw, int64_t max_nt, int32_t count) {
+    if (!b || !plan || nw < 0 || nw > TX_MAX_WIDTHS || max_nt < 1 || max_nt > (int64_t(1) << 30) || count < 1 ||
+        count > b->max_jobs)
+        return TX_EINVAL;
+    if (!plan->on_device || plan->device != b->device) return TX_ESTATE;
+    const tx::Tiles t = tx::plan_tiles(plan);
+    if (b->reserved && (t.s1 != b->tiles.s1 || t.s2 != b->tiles.s2)) return TX_EINVAL;
+    const tx::DedispGeom g = tx::dedisp_geometry(plan, max_nt, t);
+    if (!g.ok) return TX_ENOTSUP;
+    tx::Stage1Args a1;
+    tx::Stage2Args a2;
+    tx::fill_stage_args(plan, g, nullptr, max_nt + plan->overlap, max_nt, nullptr, max_nt + 1, nullptr, &a1, &a2);
+    Signature f = b->floor;
+    f.s1 = g.tiles.s1;
+    f.s2 = g.tiles.s2;
+    f.lds1 = std::max(f.lds1, g.lds1);
+    f.lds2 = std::max(f.lds2, g.lds2);
+    const int gi = iw_index(g.iw);
+    f.groups[gi] = true;
+    f.g1 += count * tx::stage1_tiles(a1);
+    f.g2[gi] += count * tx::stage2_tiles(a2);
+    if (nw > 0) {
+        f.any_box = true;
+        f.nwt = std::max(f.nwt, nw <= 8 ? 8 : (nw <= 16 ? 16 : 32));
+        f.gb += static_cast<int64_t>(count) * plan->ndm;
+    }
+    if (f.g1 > INT32_MAX || f.g2[gi] > INT32_MAX || f.gb > INT32_MAX) return TX_ENOTSUP;
+    b->floor = f;
+    b->tiles = t;
+    b->reserved = true;
+    return TX_OK;
+}
+
 tx_status tx_batch_stream_output(tx_batch_t b, int32_t job, int64_t* nt_out) {
     if (!b || !nt_out || job < 0 || job >= static_cast<int32_t>(b->jobs.size())) return TX_EINVAL;
     *nt_out = b->jobs[job].nt_out;
@@ -245,10 +279,11 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
     if (dev != b->device) return TX_ESTATE;
     const int n = static_cast<int>(b->jobs.size());
 
-    // Tile choice: the first job's plan decides the first-stage variant; every
-    // job's LDS need raises the batch's LDS sizes.
-    const tx::Tiles t0 = tx::plan_tiles(b->jobs[0].plan);
-    Signature sig;
+    // Tile choice: the reserved plans, else the first job's plan, decide the
+    // variants; every job's LDS need (and every reserved plan's) raises the
+    // batch's LDS sizes.
+    const tx::Tiles t0 = b->reserved ? b->tiles : tx::plan_tiles(b->jobs[0].plan);
+    Signature sig = b->reserved ? b->floor : Signature{};
     std::vector<tx::DedispGeom> geo(static_cast<size_t>(n));
     // Stream jobs: copy the blocks behind the held histories first.
     for (Job& j : b->jobs) {
@@ -276,27 +311,71 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
             sig.any_box = true;
             sig.nwt = std::max(sig.nwt, j.box.nw <= 8 ? 8 : (j.box.nw <= 16 ? 16 : 32));
         }
-        if (!j.stream && j.nt_out > 0) {
+        if (j.nt_out > 0) {
             scratch_off[static_cast<size_t>(k)] = scratch_need;
             scratch_need += g.ws_bytes;
         }
+    }
+    // Grids: the tiles and rows of this launch.
+    int64_t tot1 = 0, tot2[kNIW] = {}, totb = 0;
+    for (int k = 0; k < n; ++k) {
+        const Job& j = b->jobs[static_cast<size_t>(k)];
+        if (j.nt_out <= 0) continue;
+        tx::Stage1Args a1;
+        tx::Stage2Args a2;
+        tx::fill_stage_args(j.plan, geo[static_cast<size_t>(k)], nullptr, 0, j.nt_out, nullptr, 0, nullptr, &a1, &a2);
+        tot1 += tx::stage1_tiles(a1);
+        tot2[iw_index(geo[static_cast<size_t>(k)].iw)] += tx::stage2_tiles(a2);
+        if (j.has_box) totb += j.plan->ndm;
     }
     const bool use_graph = (b->flags & TX_BATCH_GRAPH) && stream != nullptr;
     if (use_graph && b->exec) {
         // A captured graph fixes the kernels, grids and LDS sizes.
         Signature want = b->sig;
         bool fits = sig.s1 == want.s1 && sig.s2 == want.s2 && sig.lds1 <= want.lds1 && sig.lds2 <= want.lds2 &&
-                    sig.nwt <= want.nwt && (!sig.any_box || want.any_box);
+                    sig.nwt <= want.nwt && (!sig.any_box || want.any_box) && tot1 <= want.g1 && totb <= want.gb;
         for (int g = 0; g < kNIW; ++g)
-            if (sig.groups[g] && !want.groups[g]) fits = false;
+            if ((sig.groups[g] && !want.groups[g]) || tot2[g] > want.g2[g]) fits = false;
         if (!fits) return TX_ESTATE;
         sig = want;
+    } else {
+        // Direct launches use the exact grids.  A graph captured now is sized
+        // for the larger of the reserved capacity and this launch, with every
+        // stream job counted at its largest block.
+        const Signature& f = b->floor;
+        if (use_graph) {
+            int64_t c1 = 0, c2[kNIW] = {}, cb = 0;
+            for (int k = 0; k < n; ++k) {
+                const Job& j = b->jobs[static_cast<size_t>(k)];
+                const int64_t nt_cap = j.stream ? std::max(j.stream->max_block, j.nt_out) : j.nt_out;
+                if (nt_cap <= 0) continue;
+                const tx::DedispGeom gc = tx::dedisp_geometry(j.plan, nt_cap, t0);
+                if (!gc.ok) return TX_ENOTSUP;
+                tx::Stage1Args a1;
+                tx::Stage2Args a2;
+                tx::fill_stage_args(j.plan, gc, nullptr, 0, nt_cap, nullptr, 0, nullptr, &a1, &a2);
+                c1 += tx::stage1_tiles(a1);
+                c2[iw_index(gc.iw)] += tx::stage2_tiles(a2);
+                if (j.has_box) cb += j.plan->ndm;
+            }
+            tot1 = std::max(tot1, c1);
+            totb = std::max(totb, cb);
+            for (int g = 0; g < kNIW; ++g) tot2[g] = std::max(tot2[g], c2[g]);
+        }
+        sig.g1 = std::max(tot1, use_graph ? f.g1 : 0);
+        sig.gb = std::max(totb, use_graph ? f.gb : 0);
+        for (int g = 0; g < kNIW; ++g) sig.g2[g] = std::max(tot2[g], use_graph ? f.g2[g] : 0);
+        if (sig.g1 > INT32_MAX || sig.gb > INT32_MAX) return TX_ENOTSUP;
+        for (int g = 0; g < kNIW; ++g)
+            if (sig.g2[g] > INT32_MAX) return TX_ENOTSUP;
     }
-    // Scratch for device-block jobs (stream-ordered, so in-flight work keeps
-    // the old buffer until it is done).
+    // First-stage scratch of every job (stream-ordered, so in-flight work
+    // keeps the old buffer until it is done).
     if (scratch_need > b->scratch_bytes) {
         if (b->scratch) (void)hipFreeAsync(b->scratch, stream);
         b->scratch = nullptr;
+        const tx_status rp = tx::retain_pool(b->device);
+        if (rp != TX_OK) return rp;
         const hipError_t e = hipMallocAsync(&b->scratch, static_cast<size_t>(scratch_need), stream);
         if (e != hipSuccess) {
             b->scratch_bytes = 0;
@@ -325,11 +404,9 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
         const tx::DedispGeom& g = geo[static_cast<size_t>(k)];
         tx::Stage1Args a1;
         tx::Stage2Args a2;
-        const uint8_t* in = j.stream ? j.stream->ring[j.stream->cur] : j.in;
+        const uint8_t* in = j.stream ? j.stream->ring : j.in;
         const int64_t in_pitch = j.stream ? j.stream->pitch : j.in_pitch;
-        uint16_t* ws = j.stream ? static_cast<uint16_t*>(j.stream->ws)
-                                : reinterpret_cast<uint16_t*>(static_cast<uint8_t*>(b->scratch) + scratch_off[static_cast<size_t>(k)]);
-        if (j.stream && g.ws_bytes > j.stream->ws_bytes) return TX_ENOTSUP;
+        uint16_t* ws = reinterpret_cast<uint16_t*>(static_cast<uint8_t*>(b->scratch) + scratch_off[static_cast<size_t>(k)]);
         tx::fill_stage_args(j.plan, g, in, in_pitch, j.nt_out, j.out, j.out_pitch, ws, &a1, &a2);
         a1.lds_bytes = sig.lds1;
         a2.lds_bytes = sig.lds2;
@@ -402,7 +479,11 @@ tx_status tx_batch_destroy(tx_batch_t b) {
     if (!b) return TX_OK;
     if (b->upload_pending) (void)hipEventSynchronize(b->uploaded);
     destroy_graph(b);
-    if (b->scratch) (void)hipFree(b->scratch);
+    if (b->scratch) {
+        (void)hipDeviceSynchronize();
+        (void)hipFreeAsync(b->scratch, nullptr);
+        (void)hipStreamSynchronize(nullptr);
+    }
     if (b->d_tab) (void)hipFree(b->d_tab);
     if (b->h_tab) (void)hipHostFree(b->h_tab);
     if (b->uploaded) (void)hipEventDestroy(b->uploaded);

@@ -10,6 +10,23 @@
 
 #include "../../include/tx.h"
 
+#if defined(__HIP__)
+// Global address space.  Pointers read from device memory (the job tables of
+// a batch) are generic to the compiler, which then emits flat loads and stores
+// that also count against the LDS wait counter; casting them to this address
+// space keeps the kernels on global_load / global_store.  (The host pass of a
+// HIP source sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TX_GLOBAL __attribute__((address_space(1)))
+#else
+#define TX_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ TX_GLOBAL T* to_global(T* p) {
+    return (TX_GLOBAL T*)(p);
+}
+#endif
+
 namespace tx {
 
 constexpr double kDispersion = 4.148808e3;  // s MHz^2 pc^-1 cm^3 (Sec. 2.3, Eq. 1)
@@ -126,11 +143,10 @@ struct tx_stream_s {
     int device = -1;
     int64_t max_block = 0;
     int64_t pitch = 0;                 // bytes per ring row (multiple of 256)
-    uint8_t* ring[2] = {nullptr, nullptr};
-    int cur = 0;
-    int64_t held = 0;                  // valid samples at the front of ring[cur]
+    uint8_t* ring = nullptr;           // nchan rows: held history, then the new block
+    int64_t held = 0;                  // valid samples at the front of every row
     int64_t received = 0, emitted = 0;
-    void* ws = nullptr;                // dedispersion scratch for max_block outputs
+    void* ws = nullptr;                // dedispersion scratch of standalone pushes (allocated on first use)
     int64_t ws_bytes = 0;
 };
 
@@ -146,6 +162,8 @@ tx_status check_out_args(const int32_t* d_out, int64_t out_pitch, int64_t nt);
 // Validate a width list and fill widths, 1/sqrt(w), nw and the longest width <= nt.
 tx_status boxcar_widths(const int32_t* widths, int32_t nw, int64_t nt, BoxcarArgs* a);
 tx_status status_of(hipError_t e);
+// Keep freed stream-ordered scratch in the device's pool (idempotent per device).
+tx_status retain_pool(int dev);
 tx::Tiles plan_tiles(const tx_plan_s* p);
 
 // Host plan construction (tx_plan.cpp).
@@ -177,12 +195,14 @@ void fill_stage_args(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d
 int64_t stage1_tiles(const Stage1Args& a);
 int64_t stage2_tiles(const Stage2Args& a);
 int stage2_iw(int32_t g);
+// Batch launches: `grid` workgroups (at least the batch's tiles / rows; 0
+// skips the launch).
 hipError_t launch_stage1_batch(int variant, int lds, const Stage1Args* d_jobs, const int* d_prefix,
-                               const int* d_njobs, hipStream_t stream);
+                               const int* d_njobs, int grid, hipStream_t stream);
 hipError_t launch_stage2_batch(int iw, int variant, int lds, const Stage2Args* d_jobs, const int* d_prefix,
-                               const int* d_njobs, hipStream_t stream);
+                               const int* d_njobs, int grid, hipStream_t stream);
 // Boxcar over many row sets: rows of all jobs, job of a row by prefix sums.
-hipError_t launch_boxcar_batch(int nwt, const BoxcarArgs* d_jobs, const int* d_prefix, const int* d_njobs,
+hipError_t launch_boxcar_batch(int nwt, const BoxcarArgs* d_jobs, const int* d_prefix, const int* d_njobs, int grid,
                                hipStream_t stream);
 hipError_t launch_zero_counts(const BoxcarArgs* d_jobs, const int* d_njobs, int max_jobs, hipStream_t stream);
 

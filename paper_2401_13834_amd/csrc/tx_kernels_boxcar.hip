@@ -56,7 +56,7 @@ __device__ __forceinline__ V wave_sum(V v) {
 // Exclusive running sums of y[t0 + e], e in [e0, e0 + 4096) (zeros past the
 // row), written to P[e]; returns the round total.  Thread tid owns 16
 // consecutive samples.
-__device__ __forceinline__ uint32_t scan_round(const int32_t* __restrict__ y, int T, int t0, int e0, int L,
+__device__ __forceinline__ uint32_t scan_round(const TX_GLOBAL int32_t* __restrict__ y, int T, int t0, int e0, int L,
                                                uint32_t base, uint32_t* P, uint32_t* wtot, bool vec) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int e = e0 + 16 * tid;
@@ -65,7 +65,7 @@ __device__ __forceinline__ uint32_t scan_round(const int32_t* __restrict__ y, in
     if (vec && e + 16 <= L && t + 16 <= T) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const uint4 q = *reinterpret_cast<const uint4*>(y + t + 4 * k);
+            const uint4 q = *reinterpret_cast<const TX_GLOBAL uint4*>(y + t + 4 * k);
             v[4 * k] = q.x;
             v[4 * k + 1] = q.y;
             v[4 * k + 2] = q.z;
@@ -190,7 +190,7 @@ __device__ __forceinline__ void boxcar_tile(const BoxcarArgs& a, BoxShared<NWT>&
                     c.width = bw;
                     c.time = t;
                     c.snr = bs;
-                    a.cands[slot] = c;
+                    to_global(a.cands)[slot] = c;
                 }
             }
     }
@@ -202,15 +202,15 @@ __device__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int T = a.nt;
-    const int32_t* __restrict__ y = a.y + static_cast<size_t>(row) * a.pitch;
-    const bool vec = (reinterpret_cast<uintptr_t>(y) & 15) == 0;
+    const TX_GLOBAL int32_t* __restrict__ y = to_global(a.y) + static_cast<size_t>(row) * a.pitch;
+    const bool vec = ((reinterpret_cast<uintptr_t>(a.y) + static_cast<uintptr_t>(row) * a.pitch * 4) & 15) == 0;
 
     // ---- moments ----------------------------------------------------------
     unsigned long long s1 = 0, s2 = 0;
     int bad = 0;
     const int nvec = vec ? T / 4 : 0;
     for (int v = tid; v < nvec; v += kThreads) {
-        const int4 q = *reinterpret_cast<const int4*>(y + 4 * v);
+        const int4 q = *reinterpret_cast<const TX_GLOBAL int4*>(y + 4 * v);
         const int32_t e[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -273,9 +273,9 @@ __device__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
     const long long sum = sh.sum;
     if (state != 0) {
         if (tid == 0 && a.want_peaks) {
-            a.snr[row] = state == 1 ? 0.0 : __builtin_nan("");
-            a.width[row] = state == 1 ? a.widths[0] : -1;
-            a.time[row] = state == 1 ? 0 : -1;
+            to_global(a.snr)[row] = state == 1 ? 0.0 : __builtin_nan("");
+            to_global(a.width)[row] = state == 1 ? a.widths[0] : -1;
+            to_global(a.time)[row] = state == 1 ? 0 : -1;
         }
         __syncthreads();
         return;
@@ -371,9 +371,9 @@ __device__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
                 bw = a.widths[0];
                 bt = 0;
             }
-            a.snr[row] = bs;
-            a.width[row] = bw;
-            a.time[row] = bt;
+            to_global(a.snr)[row] = bs;
+            to_global(a.width)[row] = bw;
+            to_global(a.time)[row] = bt;
         }
     }
     __syncthreads();
@@ -394,6 +394,9 @@ __device__ __forceinline__ int find_row_job(const int* __restrict__ prefix, int 
     return lo;
 }
 
+// Batch form: one workgroup per row of all jobs (job of a row by prefix sums);
+// the grid may exceed the batch's rows (a captured graph is sized for the
+// largest batch) and workgroups past the last row exit at once.
 template <int NWT>
 __global__ __launch_bounds__(kThreads) void boxcar_batch_kernel(const BoxcarArgs* __restrict__ jobs,
                                                                 const int* __restrict__ prefix,
@@ -401,11 +404,11 @@ __global__ __launch_bounds__(kThreads) void boxcar_batch_kernel(const BoxcarArgs
     __shared__ BoxShared<NWT> sh;
     const int njobs = *njobs_p;
     const int total = prefix[njobs];
-    for (int v = blockIdx.x; v < total; v += gridDim.x) {
-        const int jb = find_row_job(prefix, njobs, v);
-        const BoxcarArgs a = jobs[jb];
-        boxcar_row<NWT>(a, v - prefix[jb], sh);
-    }
+    const int v = static_cast<int>(blockIdx.x);
+    if (v >= total) return;
+    const int jb = find_row_job(prefix, njobs, v);
+    const BoxcarArgs a = jobs[jb];
+    boxcar_row<NWT>(a, v - prefix[jb], sh);
 }
 
 __global__ void zero_u64_kernel(unsigned long long* p) {
@@ -440,31 +443,17 @@ hipError_t launch_boxcar(const BoxcarArgs& a, hipStream_t stream) {
     return e;
 }
 
-template <int NWT>
-static int boxcar_grid() {
-    int dev = 0, cus = 0, per = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&boxcar_batch_kernel<NWT>),
-                                                     kThreads, 0) != hipSuccess ||
-        per <= 0)
-        per = 1;
-    (void)hipGetLastError();
-    return std::max(8, per * cus);
-}
 
-hipError_t launch_boxcar_batch(int nwt, const BoxcarArgs* d_jobs, const int* d_prefix, const int* d_njobs,
+hipError_t launch_boxcar_batch(int nwt, const BoxcarArgs* d_jobs, const int* d_prefix, const int* d_njobs, int grid,
                                hipStream_t stream) {
+    if (grid <= 0) return hipSuccess;
     const int prof = prof_begin(TX_KERNEL_BOXCAR, stream);
     if (nwt <= 8)
-        hipLaunchKernelGGL(boxcar_batch_kernel<8>, dim3(boxcar_grid<8>()), dim3(kThreads), 0, stream, d_jobs, d_prefix,
-                           d_njobs);
+        hipLaunchKernelGGL(boxcar_batch_kernel<8>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs);
     else if (nwt <= 16)
-        hipLaunchKernelGGL(boxcar_batch_kernel<16>, dim3(boxcar_grid<16>()), dim3(kThreads), 0, stream, d_jobs,
-                           d_prefix, d_njobs);
+        hipLaunchKernelGGL(boxcar_batch_kernel<16>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs);
     else
-        hipLaunchKernelGGL(boxcar_batch_kernel<32>, dim3(boxcar_grid<32>()), dim3(kThreads), 0, stream, d_jobs,
-                           d_prefix, d_njobs);
+        hipLaunchKernelGGL(boxcar_batch_kernel<32>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs);
     const hipError_t e = hipGetLastError();
     prof_end(prof, stream);
     return e;

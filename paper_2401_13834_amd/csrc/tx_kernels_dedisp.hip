@@ -46,14 +46,14 @@ __device__ __forceinline__ int block_max(int v, int* red) {
 }
 
 // Bytes [b, b + 20) of a row with `avail` valid bytes (zeros past the end).
-__device__ __forceinline__ void load20(const uint8_t* row, int b, int64_t avail, uint32_t d[5]) {
+__device__ __forceinline__ void load20(const TX_GLOBAL uint8_t* row, int b, int64_t avail, uint32_t d[5]) {
     if (b + 20 <= avail) {
-        const uint4 v = *reinterpret_cast<const uint4*>(row + b);
+        const uint4 v = *reinterpret_cast<const TX_GLOBAL uint4*>(row + b);
         d[0] = v.x;
         d[1] = v.y;
         d[2] = v.z;
         d[3] = v.w;
-        d[4] = *reinterpret_cast<const uint32_t*>(row + b + 16);
+        d[4] = *reinterpret_cast<const TX_GLOBAL uint32_t*>(row + b + 16);
     } else {
 #pragma unroll
         for (int k = 0; k < 5; ++k) d[k] = 0u;
@@ -96,13 +96,13 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
     const int lane = tid & 63;
     const int wave = uniform(tid >> 6);
     const int ch0 = s * a.m;
-    const int32_t* __restrict__ dT = a.dT;
+    const TX_GLOBAL int32_t* __restrict__ dT = to_global(a.dT);
     const size_t gp = static_cast<size_t>(a.gpad);
 
     // Largest shift (from the 16-byte aligned row start) in this workgroup.
     int sp = 0;
     for (int c = tid; c < a.m; c += kThreads) {
-        const int32_t* r = dT + static_cast<size_t>(ch0 + c) * gp;
+        const TX_GLOBAL int32_t* r = dT + static_cast<size_t>(ch0 + c) * gp;
         sp = max(sp, r[jl] - (r[j0] & ~15));
     }
     sp = block_max(sp, red);
@@ -123,7 +123,7 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
         const int nc = min(nch, a.m - cb);
         for (int t = tid; t < nc * J; t += kThreads) {
             const int c = t / J, k = t - c * J;
-            const int32_t* r = dT + static_cast<size_t>(ch0 + cb + c) * gp;
+            const TX_GLOBAL int32_t* r = dT + static_cast<size_t>(ch0 + cb + c) * gp;
             const int sh = r[min(j0 + k, jl)] - (r[j0] & ~15);
             tab[t] = c * rowbytes + sh;          // word offset (sh & ~3) plus byte shift (sh & 3)
         }
@@ -131,7 +131,7 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
         for (int c = wave; c < nc; c += kWaves) {
             const int ch = ch0 + cb + c;
             const int64_t start = static_cast<int64_t>(u0) + (dT[static_cast<size_t>(ch) * gp + j0] & ~15);
-            const uint8_t* row = a.x + static_cast<size_t>(ch) * a.x_pitch + start;
+            const TX_GLOBAL uint8_t* row = to_global(a.x) + static_cast<size_t>(ch) * a.x_pitch + start;
             const int64_t avail_b = a.x_len - start;
             uint32_t* dst = reinterpret_cast<uint32_t*>(dat + c * rowbytes);
             for (int i = lane; 4 * i < W; i += 64) {
@@ -183,13 +183,13 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
     for (int jj = 0; jj < JW; ++jj) {
         const int j = j0 + wave * JW + jj;
         if (j <= jl) {
-            uint16_t* out = a.B + (static_cast<size_t>(j) * a.nsub + s) * a.B_pitch + u0;
+            TX_GLOBAL uint16_t* out = to_global(a.B) + (static_cast<size_t>(j) * a.nsub + s) * a.B_pitch + u0;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const uint32_t even = full[jj][q] - (odd[jj][q] << 8);
                 const uint32_t w01 = perm_b32(odd[jj][q], even, 0x05040100u);
                 const uint32_t w23 = perm_b32(odd[jj][q], even, 0x07060302u);
-                *reinterpret_cast<uint2*>(out + 4 * (lane + 64 * q)) = make_uint2(w01, w23);
+                *reinterpret_cast<TX_GLOBAL uint2*>(out + 4 * (lane + 64 * q)) = make_uint2(w01, w23);
             }
         }
     }
@@ -227,12 +227,12 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = uniform(tid >> 6);
-    const int32_t* __restrict__ rT = a.rT;
+    const TX_GLOBAL int32_t* __restrict__ rT = to_global(a.rT);
     const size_t dp = static_cast<size_t>(a.dpad);
 
     int sp = 0;
     for (int s = tid; s < a.nsub; s += kThreads) {
-        const int32_t* r = rT + static_cast<size_t>(s) * dp;
+        const TX_GLOBAL int32_t* r = rT + static_cast<size_t>(s) * dp;
         sp = max(sp, r[il] - (r[i0] & ~7));
     }
     sp = block_max(sp, red);
@@ -251,23 +251,23 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
     int pending = 0;
     const bool pairs = a.flush >= 2;
     const int step_max = pairs ? 2 : 1;
-    const uint16_t* Bj = a.B + static_cast<size_t>(j) * a.nsub * a.B_pitch;
+    const TX_GLOBAL uint16_t* Bj = to_global(a.B) + static_cast<size_t>(j) * a.nsub * a.B_pitch;
     const int wbase = wave * 64 * Q + lane;
 
     for (int sb = 0; sb < a.nsub; sb += nsb) {
         const int ns = min(nsb, a.nsub - sb);
         for (int t = tid; t < ns * IWP; t += kThreads) {
             const int r = t / IWP, k = t - r * IWP;
-            const int32_t* rr = rT + static_cast<size_t>(sb + r) * dp;
+            const TX_GLOBAL int32_t* rr = rT + static_cast<size_t>(sb + r) * dp;
             const int e = rr[i0 + min(k, ni - 1)] - (rr[i0] & ~7);
             tab[t] = r * rowbytes + 2 * e;       // word offset plus a 2-byte shift for odd e
         }
         for (int r = wave; r < ns; r += kWaves) {
             const int s = sb + r;
-            const uint16_t* src = Bj + static_cast<size_t>(s) * a.B_pitch + t0 + (rT[static_cast<size_t>(s) * dp + i0] & ~7);
+            const TX_GLOBAL uint16_t* src = Bj + static_cast<size_t>(s) * a.B_pitch + t0 + (rT[static_cast<size_t>(s) * dp + i0] & ~7);
             uint32_t* dst = reinterpret_cast<uint32_t*>(dat + r * rowbytes);
             for (int i = lane; 4 * i < W; i += 64)
-                *reinterpret_cast<uint4*>(dst + 4 * i) = *reinterpret_cast<const uint4*>(src + 8 * i);
+                *reinterpret_cast<uint4*>(dst + 4 * i) = *reinterpret_cast<const TX_GLOBAL uint4*>(src + 8 * i);
         }
         __syncthreads();
         int r = 0;
@@ -321,12 +321,12 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
 #pragma unroll
     for (int ii = 0; ii < IW; ++ii) {
         if (ii < ni) {
-            int32_t* out = a.Y + static_cast<size_t>(i0 + ii) * a.y_pitch;
+            TX_GLOBAL int32_t* out = to_global(a.Y) + static_cast<size_t>(i0 + ii) * a.y_pitch;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int64_t t = t0 + 2 * static_cast<int64_t>(wbase + 64 * q);
                 if (t + 1 < a.nt) {
-                    *reinterpret_cast<int2*>(out + t) =
+                    *reinterpret_cast<TX_GLOBAL int2*>(out + t) =
                         make_int2(static_cast<int32_t>(lo[ii][q]), static_cast<int32_t>(hi[ii][q]));
                 } else if (t < a.nt) {
                     out[t] = static_cast<int32_t>(lo[ii][q]);
@@ -337,10 +337,12 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
 }
 
 // ---------------------------------------------------------------------------
-// Kernels: one job (arguments by value, one workgroup per tile), or a batch of
-// jobs in device memory processed by a persistent grid.  In the batch form the
-// job table, its tile prefix sums and the job count are read from device
-// memory, so a captured graph can be replayed over a different set of jobs.
+// Kernels: one job (arguments by value), or a batch of jobs whose argument
+// table, tile prefix sums and job count are read from device memory, so that a
+// captured graph can be replayed over another set of jobs.  Both forms run one
+// workgroup per tile; a batch grid may be larger than the batch (a captured
+// graph is sized for the largest batch it will see) and workgroups past the
+// last tile exit at once.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int find_job(const int* __restrict__ prefix, int njobs, int t) {
     int lo = 0, hi = njobs;                 // prefix[lo] <= t < prefix[hi]
@@ -349,6 +351,16 @@ __device__ __forceinline__ int find_job(const int* __restrict__ prefix, int njob
         if (prefix[mid] <= t) lo = mid; else hi = mid;
     }
     return lo;
+}
+
+// Tile of this workgroup in a batch of `total` tiles, or -1.  Tiles are dealt
+// to the XCDs in contiguous ranges, as in the single-job form.
+__device__ __forceinline__ int batch_tile(int total) {
+    const int total8 = (total + 7) & ~7;
+    const int bid = static_cast<int>(blockIdx.x);
+    if (bid >= total8) return -1;
+    const int t = xcd_tile(bid, total8);
+    return t < total ? t : -1;
 }
 
 template <int Q, int JW>
@@ -365,14 +377,11 @@ __global__ __launch_bounds__(kThreads) void stage1_batch_kernel(const Stage1Args
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ int red[kWaves];
     const int njobs = *njobs_p;
-    const int total = prefix[njobs];
-    for (int v = blockIdx.x; v < total; v += gridDim.x) {
-        const int t = xcd_tile(v, total);
-        const int jb = find_job(prefix, njobs, t);
-        const Stage1Args a = jobs[jb];
-        stage1_tile<Q, JW>(a, t - prefix[jb], lds, red);
-        __syncthreads();
-    }
+    const int t = batch_tile(prefix[njobs]);
+    if (t < 0) return;
+    const int jb = find_job(prefix, njobs, t);
+    const Stage1Args a = jobs[jb];
+    stage1_tile<Q, JW>(a, t - prefix[jb], lds, red);
 }
 
 template <int IW, int Q>
@@ -389,14 +398,11 @@ __global__ __launch_bounds__(kThreads) void stage2_batch_kernel(const Stage2Args
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ int red[kWaves];
     const int njobs = *njobs_p;
-    const int total = prefix[njobs];
-    for (int v = blockIdx.x; v < total; v += gridDim.x) {
-        const int t = xcd_tile(v, total);
-        const int jb = find_job(prefix, njobs, t);
-        const Stage2Args a = jobs[jb];
-        stage2_tile<IW, Q>(a, t - prefix[jb], lds, red);
-        __syncthreads();
-    }
+    const int t = batch_tile(prefix[njobs]);
+    if (t < 0) return;
+    const int jb = find_job(prefix, njobs, t);
+    const Stage2Args a = jobs[jb];
+    stage2_tile<IW, Q>(a, t - prefix[jb], lds, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -407,6 +413,11 @@ static const Stage2Variant kS2[] = {{1}, {2}, {4}};
 constexpr int kNS1 = sizeof(kS1) / sizeof(kS1[0]);
 constexpr int kNS2 = sizeof(kS2) / sizeof(kS2[0]);
 constexpr int kDefaultLds = 32 * 1024;
+// Defaults: the fastest pair at 32 KB on the 4096-channel paper-scale block
+// (first stage 8 output dwords x 4 trials per wavefront, second stage 1024
+// outputs per workgroup); tx_plan_autotune measures per plan.
+constexpr int kDefaultS1 = 3;
+constexpr int kDefaultS2 = 1;
 
 int stage1_variant_count() { return kNS1; }
 int stage2_variant_count() { return kNS2; }
@@ -416,12 +427,15 @@ Stage2Variant stage2_variant(int v) { return kS2[v]; }
 static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 int device_max_lds();
 
+// Trials per second-stage workgroup.  A workgroup computes all IW trials
+// (padding repeats the last) and stages its sub-band rows once, which costs
+// about as much as two trials: minimise chunks * (IW + 2).
 static int pick_iw(int32_t g) {
     static const int cands[] = {16, 13, 8, 4, 2, 1};
     int best = 1;
     int64_t best_cost = INT64_MAX;
     for (int iw : cands) {
-        const int64_t cost = (g + iw - 1) / iw * static_cast<int64_t>(iw);
+        const int64_t cost = (g + iw - 1) / iw * static_cast<int64_t>(iw + 2);
         if (cost < best_cost) {
             best_cost = cost;
             best = iw;
@@ -433,8 +447,8 @@ static int pick_iw(int32_t g) {
 DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want) {
     DedispGeom g{};
     g.tiles = want;
-    if (g.tiles.s1 < 0 || g.tiles.s1 >= kNS1) g.tiles.s1 = 0;
-    if (g.tiles.s2 < 0 || g.tiles.s2 >= kNS2) g.tiles.s2 = 0;
+    if (g.tiles.s1 < 0 || g.tiles.s1 >= kNS1) g.tiles.s1 = kDefaultS1;
+    if (g.tiles.s2 < 0 || g.tiles.s2 >= kNS2) g.tiles.s2 = kDefaultS2;
     const Stage1Variant v1 = kS1[g.tiles.s1];
     const Stage2Variant v2 = kS2[g.tiles.s2];
     g.tt1 = 256 * v1.q;
@@ -586,38 +600,30 @@ hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const ui
     return e;
 }
 
-// Persistent grid for a batch kernel: the resident workgroups of every CU,
-// rounded down to a multiple of the 8 XCDs.
-static int persistent_grid(const void* fn, int lds) {
-    int dev = 0, cus = 0, per = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    allow_lds(fn, lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, static_cast<size_t>(lds)) != hipSuccess ||
-        per <= 0)
-        per = 1;
-    (void)hipGetLastError();
-    return std::max(8, (per * cus) / 8 * 8);
-}
+// batch_tile deals tiles over round_up(total, 8) workgroup ids, so the grid
+// must cover every id below that: round it up to the 8 XCDs.
+static int batch_grid(int tiles) { return (tiles + 7) / 8 * 8; }
 
 hipError_t launch_stage1_batch(int variant, int lds, const Stage1Args* d_jobs, const int* d_prefix, const int* d_njobs,
-                               hipStream_t stream) {
+                               int grid, hipStream_t stream) {
     if (variant < 0 || variant >= kNS1) return hipErrorInvalidValue;
+    if (grid <= 0) return hipSuccess;
     const void* fn = kS1Fn[variant].batch;
     void* a[] = {&d_jobs, &d_prefix, &d_njobs};
     const int prof = prof_begin(TX_KERNEL_STAGE1, stream);
-    const hipError_t e = launch(fn, persistent_grid(fn, lds), lds, a, stream);
+    const hipError_t e = launch(fn, batch_grid(grid), lds, a, stream);
     prof_end(prof, stream);
     return e;
 }
 
 hipError_t launch_stage2_batch(int iw, int variant, int lds, const Stage2Args* d_jobs, const int* d_prefix,
-                               const int* d_njobs, hipStream_t stream) {
+                               const int* d_njobs, int grid, hipStream_t stream) {
     const KernelPair* k = (variant >= 0 && variant < kNS2) ? s2_pair(iw, variant) : nullptr;
     if (!k) return hipErrorInvalidValue;
+    if (grid <= 0) return hipSuccess;
     void* a[] = {&d_jobs, &d_prefix, &d_njobs};
     const int prof = prof_begin(TX_KERNEL_STAGE2, stream);
-    const hipError_t e = launch(k->batch, persistent_grid(k->batch, lds), lds, a, stream);
+    const hipError_t e = launch(k->batch, batch_grid(grid), lds, a, stream);
     prof_end(prof, stream);
     return e;
 }

@@ -13,7 +13,7 @@ tx_status stream_ingest(tx_stream_s* s, const uint8_t* block, int64_t block_pitc
     const tx_plan_s* p = s->plan;
     if (nt < 1 || nt > s->max_block || !block || block_pitch < nt || !n_out) return TX_EINVAL;
     const hipMemcpyKind kind = block_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    hipError_t e = hipMemcpy2DAsync(s->ring[s->cur] + s->held, static_cast<size_t>(s->pitch), block,
+    hipError_t e = hipMemcpy2DAsync(s->ring + s->held, static_cast<size_t>(s->pitch), block,
                                     static_cast<size_t>(block_pitch), static_cast<size_t>(nt),
                                     static_cast<size_t>(p->nchan), kind, st);
     if (e != hipSuccess) return status_of(e);
@@ -26,13 +26,36 @@ tx_status stream_advance(tx_stream_s* s, int64_t nt, hipStream_t st) {
     const int64_t have = s->held + nt;
     const int64_t n_out = std::max<int64_t>(0, have - O);
     if (have > O && O > 0) {
-        uint8_t* src = s->ring[s->cur] + (have - O);
-        uint8_t* dst = s->ring[s->cur ^ 1];
-        hipError_t e = hipMemcpy2DAsync(dst, static_cast<size_t>(s->pitch), src, static_cast<size_t>(s->pitch),
-                                        static_cast<size_t>(O), static_cast<size_t>(s->plan->nchan),
-                                        hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return status_of(e);
-        s->cur ^= 1;
+        // Move the last O samples of every row to the front (the paper's
+        // "shift data").  Source and destination overlap when the shift d is
+        // below O: then copy forward in pieces no wider than d, so no piece
+        // overwrites a source byte that a later piece still has to read, or,
+        // for many pieces, through a transient buffer from the stream-ordered
+        // pool.
+        const int64_t d = have - O;
+        const size_t rows = static_cast<size_t>(s->plan->nchan);
+        const size_t pitch = static_cast<size_t>(s->pitch);
+        if ((O + d - 1) / d <= 8) {
+            for (int64_t x = 0; x < O; x += d) {
+                const int64_t w = std::min(d, O - x);
+                hipError_t e = hipMemcpy2DAsync(s->ring + x, pitch, s->ring + d + x, pitch, static_cast<size_t>(w),
+                                                rows, hipMemcpyDeviceToDevice, st);
+                if (e != hipSuccess) return status_of(e);
+            }
+        } else {
+            void* tmp = nullptr;
+            hipError_t e = hipMallocAsync(&tmp, static_cast<size_t>(O) * rows, st);
+            if (e != hipSuccess) return status_of(e);
+            uint8_t* t = static_cast<uint8_t*>(tmp);
+            e = hipMemcpy2DAsync(t, static_cast<size_t>(O), s->ring + d, pitch, static_cast<size_t>(O), rows,
+                                 hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpy2DAsync(s->ring, pitch, t, static_cast<size_t>(O), static_cast<size_t>(O), rows,
+                                     hipMemcpyDeviceToDevice, st);
+            const hipError_t ef = hipFreeAsync(tmp, st);
+            if (e == hipSuccess) e = ef;
+            if (e != hipSuccess) return status_of(e);
+        }
         s->held = O;
     } else {
         s->held = std::min(have, O);
@@ -45,9 +68,12 @@ tx_status stream_advance(tx_stream_s* s, int64_t nt, hipStream_t st) {
 }  // namespace tx
 
 static void free_stream(tx_stream_s* s) {
-    for (auto& r : s->ring)
-        if (r) (void)hipFree(r);
-    if (s->ws) (void)hipFree(s->ws);
+    if (s->ring || s->ws) (void)hipDeviceSynchronize();
+    if (s->ring) (void)hipFree(s->ring);
+    if (s->ws) {
+        (void)hipFreeAsync(s->ws, nullptr);
+        (void)hipStreamSynchronize(nullptr);
+    }
     delete s;
 }
 
@@ -69,10 +95,7 @@ tx_status tx_stream_open(tx_plan_t plan, int64_t max_block, tx_stream_t* out) {
     s->max_block = max_block;
     s->pitch = (plan->overlap + max_block + 255) / 256 * 256;
     const size_t bytes = static_cast<size_t>(s->pitch) * plan->nchan;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&s->ring[0]), bytes);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->ring[1]), bytes);
-    s->ws_bytes = geo.ws_bytes;
-    if (e == hipSuccess) e = hipMalloc(&s->ws, static_cast<size_t>(std::max<int64_t>(s->ws_bytes, 256)));
+    const hipError_t e = hipMalloc(reinterpret_cast<void**>(&s->ring), bytes);
     if (e != hipSuccess) {
         free_stream(s);
         return tx::status_of(e);
@@ -91,8 +114,21 @@ tx_status tx_stream_push(tx_stream_t s, const uint8_t* block, int64_t block_pitc
     if (st != TX_OK) return st;
     if (n_out > 0) {
         const tx::DedispGeom geo = tx::dedisp_geometry(s->plan, n_out, tx::plan_tiles(s->plan));
-        if (!geo.ok || geo.ws_bytes > s->ws_bytes) return TX_ENOTSUP;
-        const hipError_t e = tx::launch_dedisperse(s->plan, geo, s->ring[s->cur], s->pitch, n_out, d_out, out_pitch,
+        if (!geo.ok) return TX_ENOTSUP;
+        if (geo.ws_bytes > s->ws_bytes) {
+            // Sized for the largest block this stream accepts; kept until close.
+            const tx::DedispGeom big = tx::dedisp_geometry(s->plan, s->max_block, tx::plan_tiles(s->plan));
+            const int64_t want = std::max(big.ws_bytes, geo.ws_bytes);
+            if (s->ws) (void)hipFreeAsync(s->ws, stream);
+            s->ws = nullptr;
+            s->ws_bytes = 0;
+            const tx_status rp = tx::retain_pool(s->device);
+            if (rp != TX_OK) return rp;
+            const hipError_t e = hipMallocAsync(&s->ws, static_cast<size_t>(want), stream);
+            if (e != hipSuccess) return tx::status_of(e);
+            s->ws_bytes = want;
+        }
+        const hipError_t e = tx::launch_dedisperse(s->plan, geo, s->ring, s->pitch, n_out, d_out, out_pitch,
                                                    static_cast<uint16_t*>(s->ws), stream);
         if (e != hipSuccess) return tx::status_of(e);
     }
@@ -121,7 +157,7 @@ tx_status tx_stream_snapshot(tx_stream_t s, uint8_t* host_hist, int64_t* held, i
                              hipStream_t stream) {
     if (!s || !held || !received || !emitted || (s->held > 0 && !host_hist)) return TX_EINVAL;
     if (s->held > 0) {
-        hipError_t e = hipMemcpy2DAsync(host_hist, static_cast<size_t>(s->held), s->ring[s->cur],
+        hipError_t e = hipMemcpy2DAsync(host_hist, static_cast<size_t>(s->held), s->ring,
                                         static_cast<size_t>(s->pitch), static_cast<size_t>(s->held),
                                         static_cast<size_t>(s->plan->nchan), hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -139,7 +175,7 @@ tx_status tx_stream_restore(tx_stream_t s, const uint8_t* host_hist, int64_t hel
         return TX_EINVAL;
     if (received != emitted + held) return TX_EINVAL;
     if (held > 0) {
-        hipError_t e = hipMemcpy2DAsync(s->ring[s->cur], static_cast<size_t>(s->pitch), host_hist,
+        hipError_t e = hipMemcpy2DAsync(s->ring, static_cast<size_t>(s->pitch), host_hist,
                                         static_cast<size_t>(held), static_cast<size_t>(held),
                                         static_cast<size_t>(s->plan->nchan), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);

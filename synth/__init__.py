@@ -177,6 +177,60 @@ def spectral_amplitudes(freqs, f0, index, scale):
     return scale * (np.asarray(freqs, dtype=np.float64) / f0) ** index
 
 
+def device_normal_u8(torch, nchan, nsamp, seed, *, device="cuda", mean=128.0, std=16.0, pulses=(), rows=256):
+    """Same recipe as ``normal_u8`` drawn on the device with torch's generator
+    (a different sequence of numbers than ``normal_u8`` for the same seed),
+    for blocks too large to draw on the host.  ``pulses`` as in ``normal_u8``;
+    ``torch.round`` rounds half to even like ``np.rint``."""
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    out = torch.empty((nchan, nsamp), dtype=torch.uint8, device=device)
+    for r0 in range(0, nchan, rows):
+        r1 = min(nchan, r0 + rows)
+        z = torch.randn((r1 - r0, nsamp), generator=gen, device=device, dtype=torch.float32)
+        z.mul_(float(std)).add_(float(mean))
+        for start, width, amp in pulses:
+            st = np.asarray(start, dtype=np.int64)[r0:r1]
+            a = np.broadcast_to(np.asarray(amp, dtype=np.float64), (nchan,))[r0:r1]
+            cols = st[:, None] + np.arange(int(width), dtype=np.int64)[None, :]
+            rr = np.broadcast_to(np.arange(r1 - r0, dtype=np.int64)[:, None], cols.shape)
+            ok = (cols >= 0) & (cols < nsamp)
+            vals = np.broadcast_to(a.astype(np.float32)[:, None], cols.shape)[ok]
+            z.index_put_((torch.from_numpy(rr[ok]).to(device), torch.from_numpy(cols[ok]).to(device)),
+                         torch.from_numpy(np.ascontiguousarray(vals)).to(device), accumulate=True)
+        out[r0:r1] = z.round_().clamp_(0, 255).to(torch.uint8)
+    return out
+
+
+BATCHED_NCHAN = (1024, 2048, 4096)
+BATCHED_NT = (16384, 32768, 49152, 65536)
+BATCHED_NDM = (512, 1024, 1536, 2048, 3072, 4096)
+BATCHED_DMMAX = (1000.0, 2000.0, 3000.0)
+
+
+def batched_beams(n=64, seed=3):
+    """The uneven batch: ``n`` beams over 856-1712 MHz at 153.12 us, each with
+    a channel count, block length, DM grid (``ndm`` trials evenly over
+    0..dm_max) and 0-5 pulses (DM uniform on the grid's range, width 1..32,
+    integrated S/N 3..10, start uniform in the block) drawn from ``seed``.
+    ``nsub`` is 0: the plan picks it."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for b in range(n):
+        nchan = int(rng.choice(BATCHED_NCHAN))
+        nt = int(rng.choice(BATCHED_NT))
+        ndm = int(rng.choice(BATCHED_NDM))
+        dmmax = float(rng.choice(BATCHED_DMMAX))
+        pulses = []
+        for _ in range(int(rng.integers(0, 6))):
+            w = int(rng.integers(1, 33))
+            pulses.append(("snr", float(rng.uniform(0.0, dmmax)), int(rng.integers(0, nt - w)), w,
+                           float(rng.uniform(3.0, 10.0))))
+        out.append(Workload(f"batched-{b}", band_centres(1712.0, 856.0, nchan), 153.12e-6,
+                            np.linspace(0.0, dmmax, ndm), 0, nt, pow2_widths(512), 1000 * seed + b, pulses=pulses))
+    return out
+
+
 def poisson_arrivals(nbeams, nblocks, period_s, speed, seed):
     """Arrival times [nbeams, nblocks] in seconds: each beam starts at a
     uniform time in [0, period) and then waits exponential gaps of mean

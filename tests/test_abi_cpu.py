@@ -118,3 +118,19 @@ def test_device_calls_on_host_only_plan_are_refused():
     assert st == -4
     with pytest.raises(tx.TxError):
         p.delays(-1.0)
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    from paper_2401_13834_amd import tune
+    f = synth.band_centres(1712.0, 856.0, 64)
+    d = np.linspace(0.0, 300.0, 40)
+    k1 = tune.shape_key(f, 306.24e-6, d, 8, 3000, "dev")
+    assert k1 == tune.shape_key(f.copy(), 306.24e-6, d.copy(), 8, 3000, "dev")
+    assert k1 != tune.shape_key(f, 306.24e-6, d, 8, 3001, "dev")
+    assert k1 != tune.shape_key(f, 306.24e-6, d * 1.0000001, 8, 3000, "dev")
+    path = str(tmp_path / "c" / "tiles.json")
+    assert tune.load(path) == {}
+    tune.save({k1: {"tiles": [3, 32768, 1, 32768], "ms": 1.5}}, path)
+    assert tune.load(path)[k1]["tiles"] == [3, 32768, 1, 32768]
+    assert tune.nsub_candidates(4096) == [16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
+    assert all(4096 % n == 0 and 4096 // n <= 256 for n in tune.nsub_candidates(4096))
