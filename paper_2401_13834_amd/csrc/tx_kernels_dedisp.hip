@@ -274,16 +274,35 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
         while (r < ns) {
             const int step = (pairs && r + 1 < ns) ? 2 : 1;
             if (step == 2) {
+                // Reads of trial ii + 1 are issued before the arithmetic of
+                // trial ii (see the first stage).
+                uint32_t ra[2][Q][2], rb[2][Q][2];
+                int e0[IW], e1[IW];
 #pragma unroll
                 for (int ii = 0; ii < IW; ++ii) {
-                    const int e0 = uniform(tab[r * IWP + ii]);
-                    const int e1 = uniform(tab[(r + 1) * IWP + ii]);
-                    const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3)) + wbase;
-                    const uint32_t* p1 = reinterpret_cast<const uint32_t*>(dat + (e1 & ~3)) + wbase;
+                    e0[ii] = uniform(tab[r * IWP + ii]);
+                    e1[ii] = uniform(tab[(r + 1) * IWP + ii]);
+                }
+                auto fetch = [&](int ii, int buf) {
+                    const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0[ii] & ~3)) + wbase;
+                    const uint32_t* p1 = reinterpret_cast<const uint32_t*>(dat + (e1[ii] & ~3)) + wbase;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        ra[buf][q][0] = p0[64 * q];
+                        ra[buf][q][1] = p0[64 * q + 1];
+                        rb[buf][q][0] = p1[64 * q];
+                        rb[buf][q][1] = p1[64 * q + 1];
+                    }
+                };
+                fetch(0, 0);
+#pragma unroll
+                for (int ii = 0; ii < IW; ++ii) {
+                    if (ii + 1 < IW) fetch(ii + 1, (ii + 1) & 1);
+                    const int buf = ii & 1;
 #pragma unroll
                     for (int q = 0; q < Q; ++q)
-                        acc[ii][q] += align_b32(p0[64 * q + 1], p0[64 * q], e0 & 3) +
-                                      align_b32(p1[64 * q + 1], p1[64 * q], e1 & 3);
+                        acc[ii][q] += align_b32(ra[buf][q][1], ra[buf][q][0], e0[ii] & 3) +
+                                      align_b32(rb[buf][q][1], rb[buf][q][0], e1[ii] & 3);
                 }
             } else {
 #pragma unroll
