@@ -111,18 +111,33 @@ tx_status tx::retain_pool(int dev) {
 
 tx_status tx::boxcar_widths(const int32_t* widths, int32_t nw, int64_t nt, tx::BoxcarArgs* a) {
     if (!widths || nw < 1 || nw > TX_MAX_WIDTHS) return TX_EINVAL;
-    int32_t wmax = 0;
     for (int32_t k = 0; k < nw; ++k) {
         if (widths[k] < 1 || widths[k] > TX_MAX_WIDTH) return TX_EINVAL;
         if (k > 0 && widths[k] <= widths[k - 1]) return TX_EINVAL;
-        a->widths[k] = widths[k];
-        a->rsw[k] = 1.0 / std::sqrt(static_cast<double>(widths[k]));
-        if (widths[k] <= nt) wmax = widths[k];
     }
-    a->nw = nw;
-    a->wmax = wmax;
+    int32_t copy[TX_MAX_WIDTHS];
+    for (int32_t k = 0; k < nw; ++k) copy[k] = widths[k];
+    tx::boxcar_fit(a, copy, nw, nt);
     return TX_OK;
 }
+
+void tx::boxcar_fit(tx::BoxcarArgs* a, const int32_t* widths, int32_t nw, int64_t nt) {
+    int32_t ne = 0;
+    while (ne < nw && widths[ne] <= nt) ++ne;
+    const int32_t w_first = widths[0];
+    int32_t src[TX_MAX_WIDTHS];
+    for (int32_t k = 0; k < TX_MAX_WIDTHS; ++k) src[k] = ne > 0 ? widths[std::min(k, ne - 1)] : w_first;
+    a->nw = nw;
+    a->ne = ne;
+    a->w_first = w_first;
+    a->wmax = ne > 0 ? widths[ne - 1] : 0;
+    for (int32_t k = 0; k < TX_MAX_WIDTHS; ++k) {
+        a->widths[k] = src[k];
+        a->rsw[k] = 1.0 / std::sqrt(static_cast<double>(src[k]));
+    }
+}
+
+int tx::boxcar_nwt(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 12 ? 12 : n <= 16 ? 16 : 32; }
 
 tx_status tx::check_out_args(const int32_t* d_out, int64_t out_pitch, int64_t nt) {
     if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 7) || (out_pitch & 1) || out_pitch < nt) return TX_EINVAL;

@@ -256,7 +256,7 @@ tx_status tx_batch_reserve(tx_batch_t b, tx_plan_t plan, int32_t nw, int64_t max
     f.g2[gi] += count * tx::stage2_tiles(a2);
     if (nw > 0) {
         f.any_box = true;
-        f.nwt = std::max(f.nwt, nw <= 8 ? 8 : (nw <= 16 ? 16 : 32));
+        f.nwt = std::max(f.nwt, tx::boxcar_nwt(nw));
         f.gb += static_cast<int64_t>(count) * plan->ndm;
     }
     if (f.g1 > INT32_MAX || f.g2[gi] > INT32_MAX || f.gb > INT32_MAX) return TX_ENOTSUP;
@@ -309,7 +309,7 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
         sig.groups[iw_index(g.iw)] = true;   // by plan, so a graph captured while priming still fits
         if (j.has_box) {
             sig.any_box = true;
-            sig.nwt = std::max(sig.nwt, j.box.nw <= 8 ? 8 : (j.box.nw <= 16 ? 16 : 32));
+            sig.nwt = std::max(sig.nwt, tx::boxcar_nwt(j.box.nw));
         }
         if (j.nt_out > 0) {
             scratch_off[static_cast<size_t>(k)] = scratch_need;
@@ -423,9 +423,7 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
             bx.pitch = j.out_pitch;
             bx.ndm = j.plan->ndm;
             bx.nt = static_cast<int32_t>(j.nt_out);
-            bx.wmax = 0;
-            for (int w = 0; w < bx.nw; ++w)
-                if (bx.widths[w] <= bx.nt) bx.wmax = bx.widths[w];
+            tx::boxcar_fit(&bx, j.box.widths, j.box.nw, j.nt_out);
             hb[nb] = bx;
             hi[b->L.pb() + nb + 1] = hi[b->L.pb() + nb] + bx.ndm;
             ++nb;

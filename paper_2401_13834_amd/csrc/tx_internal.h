@@ -79,10 +79,15 @@ struct BoxcarArgs {
     int64_t pitch;
     int32_t ndm;
     int32_t nt;
-    int32_t nw;
+    int32_t nw;             // widths given
+    int32_t ne;             // widths <= nt (a prefix: widths increase)
     int32_t wmax;           // largest width <= nt (0 if none)
+    int32_t w_first;        // widths[0] as given (reported when ne == 0)
+    // widths[0..ne) and their 1/sqrt(w) (computed on the host), padded to
+    // TX_MAX_WIDTHS with the last entry so that kernels sized for more widths
+    // than ne repeat a width instead of branching
     int32_t widths[TX_MAX_WIDTHS];
-    double rsw[TX_MAX_WIDTHS];   // 1 / sqrt(w), computed on the host
+    double rsw[TX_MAX_WIDTHS];
     double gamma;
     int32_t want_peaks;
     int32_t want_cands;
@@ -161,6 +166,11 @@ tx_status stream_advance(tx_stream_s* s, int64_t nt, hipStream_t st);
 tx_status check_out_args(const int32_t* d_out, int64_t out_pitch, int64_t nt);
 // Validate a width list and fill widths, 1/sqrt(w), nw and the longest width <= nt.
 tx_status boxcar_widths(const int32_t* widths, int32_t nw, int64_t nt, BoxcarArgs* a);
+// Effective widths of a row of nt samples (ne, wmax and padding, from the
+// widths given); call after boxcar_widths and whenever nt changes.
+void boxcar_fit(BoxcarArgs* a, const int32_t* widths, int32_t nw, int64_t nt);
+// Widths a boxcar kernel instance handles (4, 8, 12, 16 or 32) for n widths.
+int boxcar_nwt(int n);
 tx_status status_of(hipError_t e);
 // Keep freed stream-ordered scratch in the device's pool (idempotent per device).
 tx_status retain_pool(int dev);

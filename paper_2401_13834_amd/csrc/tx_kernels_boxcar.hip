@@ -34,6 +34,8 @@ struct BoxShared {
     int redbad[kWaves];
     uint32_t wtot[kWaves];
     int32_t sthr[TX_MAX_WIDTHS];
+    int32_t wd[TX_MAX_WIDTHS];     // widths and 1/sqrt(width) of the row's job, for
+    double rs[TX_MAX_WIDTHS];      // run-time indexing (no private copy of the arguments)
     double inv_d;
     long long sum;
     int state;
@@ -57,8 +59,8 @@ __device__ __forceinline__ V wave_sum(V v) {
 // row), written to P[e]; returns the round total.  Thread tid owns 16
 // consecutive samples.
 __device__ __forceinline__ uint32_t scan_round(const TX_GLOBAL int32_t* __restrict__ y, int T, int t0, int e0, int L,
-                                               uint32_t base, uint32_t* P, uint32_t* wtot, bool vec) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+                                               uint32_t base, uint32_t* P, uint32_t* wtot, bool vec, int tid) {
+    const int lane = tid & 63, wave = tid >> 6;
     const int e = e0 + 16 * tid;
     uint32_t v[16];
     const int64_t t = static_cast<int64_t>(t0) + e;
@@ -72,8 +74,11 @@ __device__ __forceinline__ uint32_t scan_round(const TX_GLOBAL int32_t* __restri
             v[4 * k + 3] = q.w;
         }
     } else {
+        // Valid samples of this lane in this round (the count changes with the
+        // tile, so no per-element condition is hoisted out of the tile loop).
+        const int64_t lim = min(static_cast<int64_t>(L - e), static_cast<int64_t>(T) - t);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = (e + k < L && t + k < T) ? static_cast<uint32_t>(y[t + k]) : 0u;
+        for (int k = 0; k < 16; ++k) v[k] = k < lim ? static_cast<uint32_t>(y[t + k]) : 0u;
     }
     uint32_t ex[16];
     uint32_t run = 0;
@@ -105,16 +110,47 @@ __device__ __forceinline__ uint32_t scan_round(const TX_GLOBAL int32_t* __restri
 }
 
 // One tile of 4096 window starts.  TAIL: some windows reach past the row end.
+// Wavefront max / min of an int32 with DPP moves (quad, half-row and row
+// permutes, then the row broadcasts of 15 and 31); the result is read from
+// lane 63.
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // row_mirror
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast15
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// One tile of 4096 window starts.  TAIL: some windows reach past the row end.
+// Per width slot, each lane keeps only the largest sum of its 16 starts; the
+// wavefront's largest sum is compared with the wavefront's best so far
+// (kept in LDS per wavefront) and only when it beats it (a few tiles per
+// row) does the wavefront look up the earliest start reaching it.  Candidate
+// flags take max(S - S*) over pairs of width slots with one 3-input max.
+// Width slots past the row's widths repeat its last width, so the loop has no
+// per-width branches.
 template <int NWT, bool TAIL, bool CANDS>
 __device__ __forceinline__ void boxcar_tile(const BoxcarArgs& a, BoxShared<NWT>& sh, int row, int t0, long long sum,
-                                            double inv_d, int32_t (&bS)[NWT], int32_t (&bT)[NWT]) {
-    const int tid = threadIdx.x;
+                                            double inv_d, int tid) {
+    const int wave = tid >> 6;
     const int T = a.nt;
+    const int lb = 4 * tid;     // this lane's first start in the tile
     uint32_t Pt[4][4];
     int32_t mx[4][4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const uint4 q = *reinterpret_cast<const uint4*>(sh.P + 1024 * k + 4 * tid);
+        const uint4 q = *reinterpret_cast<const uint4*>(sh.P + lb + 1024 * k);
         Pt[k][0] = q.x;
         Pt[k][1] = q.y;
         Pt[k][2] = q.z;
@@ -122,67 +158,94 @@ __device__ __forceinline__ void boxcar_tile(const BoxcarArgs& a, BoxShared<NWT>&
 #pragma unroll
         for (int r = 0; r < 4; ++r) mx[k][r] = INT32_MIN;
     }
+#pragma unroll 1
+    for (int i = 0; i < NWT; i += 2) {
+        // Per-width values come from LDS, which keeps the registers free.
+        const int w0 = sh.wd[i], w1 = sh.wd[i + 1];
+        const int32_t thr0 = CANDS ? max(sh.sthr[i], 0) : 0;
+        const int32_t thr1 = CANDS ? max(sh.sthr[i + 1], 0) : 0;
+        int32_t tm0 = INT32_MIN, tm1 = INT32_MIN;
+        const uint32_t* p0 = sh.P + lb + w0;
+        const uint32_t* p1 = sh.P + lb + w1;
 #pragma unroll
-    for (int i = 0; i < NWT; ++i) {
-        if (i < a.nw) {
-            const int w = a.widths[i];
-            if (w <= T) {
-                const int32_t thr = CANDS ? max(sh.sthr[i], 0) : 0;
+        for (int k = 0; k < 4; ++k) {
+            const int base = 1024 * k + 4 * tid;
+            const uint2 u0 = *reinterpret_cast<const uint2*>(p0 + 1024 * k);
+            const uint2 u1 = *reinterpret_cast<const uint2*>(p0 + 1024 * k + 2);
+            const uint2 v0 = *reinterpret_cast<const uint2*>(p1 + 1024 * k);
+            const uint2 v1 = *reinterpret_cast<const uint2*>(p1 + 1024 * k + 2);
+            const uint32_t A[4] = {u0.x, u0.y, u1.x, u1.y};
+            const uint32_t B[4] = {v0.x, v0.y, v1.x, v1.y};
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int idx = 1024 * k + 4 * tid + w;
-                    uint32_t Pw[4];
-                    if ((w & 3) == 0) {
-                        const uint4 q = *reinterpret_cast<const uint4*>(sh.P + idx);
-                        Pw[0] = q.x;
-                        Pw[1] = q.y;
-                        Pw[2] = q.z;
-                        Pw[3] = q.w;
-                    } else if ((w & 1) == 0) {
-                        const uint2 q0 = *reinterpret_cast<const uint2*>(sh.P + idx);
-                        const uint2 q1 = *reinterpret_cast<const uint2*>(sh.P + idx + 2);
-                        Pw[0] = q0.x;
-                        Pw[1] = q0.y;
-                        Pw[2] = q1.x;
-                        Pw[3] = q1.y;
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) Pw[r] = sh.P[idx + r];
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int t = t0 + 1024 * k + 4 * tid + r;
-                        const int32_t S = static_cast<int32_t>(Pw[r] - Pt[k][r]);
-                        const bool ok = !TAIL || t + w <= T;
-                        if (ok && S > bS[i]) {
-                            bS[i] = S;
-                            bT[i] = t;
-                        }
-                        if (CANDS && ok) mx[k][r] = max(mx[k][r], S - thr);
-                    }
+            for (int r = 0; r < 4; ++r) {
+                const int32_t S0 = static_cast<int32_t>(A[r] - Pt[k][r]);
+                const int32_t S1 = static_cast<int32_t>(B[r] - Pt[k][r]);
+                const int t = t0 + base + r;
+                const bool ok0 = !TAIL || t + w0 <= T;   // no window past the row end
+                const bool ok1 = !TAIL || t + w1 <= T;
+                tm0 = max(tm0, ok0 ? S0 : INT32_MIN);
+                tm1 = max(tm1, ok1 ? S1 : INT32_MIN);
+                if (CANDS) {
+                    // valid sums are >= 0 and thresholds in [0, 2^31), so S - thr cannot wrap
+                    const int32_t d0 = ok0 ? S0 - thr0 : -1;
+                    const int32_t d1 = ok1 ? S1 - thr1 : -1;
+                    mx[k][r] = max(max(mx[k][r], d0), d1);
                 }
             }
         }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ii = i + h;
+            const int w = h ? w1 : w0;
+            const int32_t wm = wave_max_i32(h ? tm1 : tm0);
+            if (wm > sh.wS[wave][ii]) {                 // wavefront-uniform, a few tiles per row
+                int32_t first = INT32_MAX;
+#pragma unroll 1
+                for (int kr = 15; kr >= 0; --kr) {      // rolled: this path is rare
+                    const int e = 1024 * (kr >> 2) + 4 * tid + (kr & 3);
+                    const int t = t0 + e;
+                    const int32_t S = static_cast<int32_t>(sh.P[e + w] - sh.P[e]);
+                    const bool ok = !TAIL || t + w <= T;
+                    first = (ok && S == wm) ? t : first;
+                }
+                const int32_t ft = wave_min_i32(first);
+                if ((tid & 63) == 0) {
+                    sh.wS[wave][ii] = wm;
+                    sh.wT[wave][ii] = ft;
+                }
+            }
+        }
+        // Keep each width pair's LDS reads next to their arithmetic (the
+        // scheduler would otherwise hoist every width's reads and run out of
+        // registers).
+        __builtin_amdgcn_sched_barrier(0);
     }
     if (CANDS) {
+        // Flagged starts (rare) as a bit mask, then one start at a time.
+        uint32_t flags = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 3; k >= 0; --k)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (mx[k][r] < 0) continue;
-                const int t = t0 + 1024 * k + 4 * tid + r;
-                double bs = 0.0;
-                int bw = -1;
-                for (int i = 0; i < a.nw; ++i) {
-                    const int w = a.widths[i];
-                    if (w > T || t + w > T) continue;
-                    const int32_t S = static_cast<int32_t>(sh.P[1024 * k + 4 * tid + r + w] - Pt[k][r]);
-                    const double sn = snr_of(T, S, w, sum, inv_d, a.rsw[i]);
-                    if (bw < 0 || sn > bs) {
-                        bs = sn;
-                        bw = w;
-                    }
+            for (int r = 3; r >= 0; --r) flags = (flags << 1) | (mx[k][r] >= 0 ? 1u : 0u);   // bit 4k + r
+        while (flags) {
+            const int kr = __builtin_ctz(flags);
+            flags &= flags - 1;
+            const int e = 1024 * (kr >> 2) + 4 * tid + (kr & 3);
+            const int t = t0 + e;
+            const uint32_t pt = sh.P[e];
+            double bs = 0.0;
+            int bw = -1;
+            for (int i = 0; i < a.ne; ++i) {
+                const int w = sh.wd[i];
+                if (t + w > T) continue;
+                const int32_t S = static_cast<int32_t>(sh.P[e + w] - pt);
+                const double sn = snr_of(T, S, w, sum, inv_d, sh.rs[i]);
+                if (bw < 0 || sn > bs) {
+                    bs = sn;
+                    bw = w;
                 }
+            }
+            {
                 const unsigned long long slot = atomicAdd(a.count, 1ull);
                 if (static_cast<long long>(slot) < a.cap) {
                     tx_cand c;
@@ -193,17 +256,30 @@ __device__ __forceinline__ void boxcar_tile(const BoxcarArgs& a, BoxShared<NWT>&
                     to_global(a.cands)[slot] = c;
                 }
             }
+        }
     }
 }
 
 template <int NWT>
-__device__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
+__device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int T = a.nt;
     const TX_GLOBAL int32_t* __restrict__ y = to_global(a.y) + static_cast<size_t>(row) * a.pitch;
     const bool vec = ((reinterpret_cast<uintptr_t>(a.y) + static_cast<uintptr_t>(row) * a.pitch * 4) & 15) == 0;
+    if (tid < NWT) {
+        int32_t w = 0;
+        double r = 0.0;
+#pragma unroll
+        for (int k = 0; k < NWT; ++k)          // compile-time indices only
+            if (k == tid) {
+                w = a.widths[k];
+                r = a.rsw[k];
+            }
+        sh.wd[tid] = w;
+        sh.rs[tid] = r;
+    }
 
     // ---- moments ----------------------------------------------------------
     unsigned long long s1 = 0, s2 = 0;
@@ -274,16 +350,16 @@ __device__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
     if (state != 0) {
         if (tid == 0 && a.want_peaks) {
             to_global(a.snr)[row] = state == 1 ? 0.0 : __builtin_nan("");
-            to_global(a.width)[row] = state == 1 ? a.widths[0] : -1;
+            to_global(a.width)[row] = state == 1 ? a.w_first : -1;
             to_global(a.time)[row] = state == 1 ? 0 : -1;
         }
         __syncthreads();
         return;
     }
     // ---- per-width thresholds ------------------------------------------------
-    if (a.want_cands && tid < a.nw) {
-        const int64_t w = a.widths[tid];
-        const double rsw = a.rsw[tid];
+    if (a.want_cands && tid < NWT) {
+        const int64_t w = sh.wd[tid];
+        const double rsw = sh.rs[tid];
         int64_t lo = INT32_MIN, hi = INT32_MAX;
         int32_t res;
         if (snr_of(T, lo, w, sum, inv_d, rsw) >= a.gamma) {
@@ -302,64 +378,51 @@ __device__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
     __syncthreads();
 
     // ---- tiles ------------------------------------------------------------------
-    int32_t bS[NWT], bT[NWT];
+    if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < NWT; ++i) {
-        bS[i] = INT32_MIN;
-        bT[i] = 0;
+        for (int i = 0; i < NWT; ++i) {
+            sh.wS[wave][i] = INT32_MIN;   // this wavefront's best sum per width so far
+            sh.wT[wave][i] = 0;
+        }
     }
     const int L = kBoxTile + a.wmax;
-    for (int t0 = 0; t0 < T; t0 += kBoxTile) {
-        const uint32_t tot = scan_round(y, T, t0, 0, L, 0u, sh.P, sh.wtot, vec);
+    for (int t0 = 0; a.ne > 0 && t0 < T; t0 += kBoxTile) {
+        // The thread index, made opaque to the compiler in every tile: else it
+        // hoists dozens of lane-dependent masks and addresses out of this loop
+        // and spills them.
+        int tv = tid;
+        asm volatile("" : "+v"(tv));
+        const uint32_t tot = scan_round(y, T, t0, 0, L, 0u, sh.P, sh.wtot, vec, tv);
         uint32_t tot2 = 0;
-        if (L > kBoxTile) tot2 = scan_round(y, T, t0, kBoxTile, L, tot, sh.P, sh.wtot, vec);
+        if (L > kBoxTile) tot2 = scan_round(y, T, t0, kBoxTile, L, tot, sh.P, sh.wtot, vec, tv);
         if (tid == 0) sh.P[L] = tot + tot2;
         __syncthreads();
         const bool tail = t0 + kBoxTile + a.wmax > T;
         if (a.want_cands) {
-            if (tail) boxcar_tile<NWT, true, true>(a, sh, row, t0, sum, inv_d, bS, bT);
-            else boxcar_tile<NWT, false, true>(a, sh, row, t0, sum, inv_d, bS, bT);
+            if (tail) boxcar_tile<NWT, true, true>(a, sh, row, t0, sum, inv_d, tv);
+            else boxcar_tile<NWT, false, true>(a, sh, row, t0, sum, inv_d, tv);
         } else {
-            if (tail) boxcar_tile<NWT, true, false>(a, sh, row, t0, sum, inv_d, bS, bT);
-            else boxcar_tile<NWT, false, false>(a, sh, row, t0, sum, inv_d, bS, bT);
+            if (tail) boxcar_tile<NWT, true, false>(a, sh, row, t0, sum, inv_d, tv);
+            else boxcar_tile<NWT, false, false>(a, sh, row, t0, sum, inv_d, tv);
         }
         __syncthreads();
     }
     // ---- peak: reduce (largest S, earliest t) per width ---------------------------
     if (a.want_peaks) {
-#pragma unroll
-        for (int i = 0; i < NWT; ++i) {
-            int32_t S = bS[i];
-            int32_t t = bT[i];
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const int32_t S2 = __shfl_xor(S, o);
-                const int32_t t2 = __shfl_xor(t, o);
-                if (S2 > S || (S2 == S && t2 < t)) {
-                    S = S2;
-                    t = t2;
-                }
-            }
-            if (lane == 0) {
-                sh.wS[wave][i] = S;
-                sh.wT[wave][i] = t;
-            }
-        }
         __syncthreads();
         if (tid == 0) {
             double bs = 0.0;
             int bw = -1;
             long long bt = 0;
-            for (int i = 0; i < a.nw; ++i) {
-                const int w = a.widths[i];
-                if (w > T) continue;
+            for (int i = 0; i < a.ne; ++i) {
+                const int w = sh.wd[i];
                 int32_t S = sh.wS[0][i], t = sh.wT[0][i];
                 for (int v = 1; v < kWaves; ++v)
                     if (sh.wS[v][i] > S || (sh.wS[v][i] == S && sh.wT[v][i] < t)) {
                         S = sh.wS[v][i];
                         t = sh.wT[v][i];
                     }
-                const double sn = snr_of(T, S, w, sum, inv_d, a.rsw[i]);
+                const double sn = snr_of(T, S, w, sum, inv_d, sh.rs[i]);
                 if (bw < 0 || sn > bs) {
                     bs = sn;
                     bw = w;
@@ -368,7 +431,7 @@ __device__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
             }
             if (bw < 0) {
                 bs = 0.0;
-                bw = a.widths[0];
+                bw = a.w_first;
                 bt = 0;
             }
             to_global(a.snr)[row] = bs;
@@ -382,7 +445,8 @@ __device__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
 template <int NWT>
 __global__ __launch_bounds__(kThreads) void boxcar_kernel(BoxcarArgs a) {
     __shared__ BoxShared<NWT> sh;
-    for (int row = blockIdx.x; row < a.ndm; row += gridDim.x) boxcar_row<NWT>(a, row, sh);
+    const int row = static_cast<int>(blockIdx.x);        // grid = rows
+    if (row < a.ndm) boxcar_row<NWT>(a, row, sh);
 }
 
 __device__ __forceinline__ int find_row_job(const int* __restrict__ prefix, int njobs, int v) {
@@ -407,8 +471,7 @@ __global__ __launch_bounds__(kThreads) void boxcar_batch_kernel(const BoxcarArgs
     const int v = static_cast<int>(blockIdx.x);
     if (v >= total) return;
     const int jb = find_row_job(prefix, njobs, v);
-    const BoxcarArgs a = jobs[jb];
-    boxcar_row<NWT>(a, v - prefix[jb], sh);
+    boxcar_row<NWT>(jobs[jb], v - prefix[jb], sh);
 }
 
 __global__ void zero_u64_kernel(unsigned long long* p) {
@@ -432,12 +495,13 @@ hipError_t launch_boxcar(const BoxcarArgs& a, hipStream_t stream) {
     if (a.ndm <= 0) return hipSuccess;
     const int grid = a.ndm;
     const int prof = prof_begin(TX_KERNEL_BOXCAR, stream);
-    if (a.nw <= 8)
-        hipLaunchKernelGGL(boxcar_kernel<8>, dim3(grid), dim3(kThreads), 0, stream, a);
-    else if (a.nw <= 16)
-        hipLaunchKernelGGL(boxcar_kernel<16>, dim3(grid), dim3(kThreads), 0, stream, a);
-    else
-        hipLaunchKernelGGL(boxcar_kernel<32>, dim3(grid), dim3(kThreads), 0, stream, a);
+    switch (boxcar_nwt(a.ne)) {
+        case 4: hipLaunchKernelGGL(boxcar_kernel<4>, dim3(grid), dim3(kThreads), 0, stream, a); break;
+        case 8: hipLaunchKernelGGL(boxcar_kernel<8>, dim3(grid), dim3(kThreads), 0, stream, a); break;
+        case 12: hipLaunchKernelGGL(boxcar_kernel<12>, dim3(grid), dim3(kThreads), 0, stream, a); break;
+        case 16: hipLaunchKernelGGL(boxcar_kernel<16>, dim3(grid), dim3(kThreads), 0, stream, a); break;
+        default: hipLaunchKernelGGL(boxcar_kernel<32>, dim3(grid), dim3(kThreads), 0, stream, a); break;
+    }
     const hipError_t e = hipGetLastError();
     prof_end(prof, stream);
     return e;
@@ -448,12 +512,13 @@ hipError_t launch_boxcar_batch(int nwt, const BoxcarArgs* d_jobs, const int* d_p
                                hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
     const int prof = prof_begin(TX_KERNEL_BOXCAR, stream);
-    if (nwt <= 8)
-        hipLaunchKernelGGL(boxcar_batch_kernel<8>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs);
-    else if (nwt <= 16)
-        hipLaunchKernelGGL(boxcar_batch_kernel<16>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs);
-    else
-        hipLaunchKernelGGL(boxcar_batch_kernel<32>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs);
+    switch (boxcar_nwt(nwt)) {
+        case 4: hipLaunchKernelGGL(boxcar_batch_kernel<4>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs); break;
+        case 8: hipLaunchKernelGGL(boxcar_batch_kernel<8>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs); break;
+        case 12: hipLaunchKernelGGL(boxcar_batch_kernel<12>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs); break;
+        case 16: hipLaunchKernelGGL(boxcar_batch_kernel<16>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs); break;
+        default: hipLaunchKernelGGL(boxcar_batch_kernel<32>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs); break;
+    }
     const hipError_t e = hipGetLastError();
     prof_end(prof, stream);
     return e;
