@@ -50,6 +50,7 @@ struct Signature {            // what a captured graph bakes in
     int s1 = -1, lds1 = 0, s2 = -1, lds2 = 0;
     bool groups[kNIW] = {};
     int nwt = 0;
+    int ldsb = 0;             // boxcar dynamic LDS (per-(tile, width) maxima)
     bool any_box = false;
     // grids: first-stage tiles, second-stage tiles per group, boxcar rows
     int64_t g1 = 0, g2[kNIW] = {}, gb = 0;
@@ -132,7 +133,8 @@ hipError_t run_kernels(tx_batch_s* b, const Signature& sig, hipStream_t st) {
         if (e != hipSuccess) return e;
     }
     if (sig.any_box)
-        e = tx::launch_boxcar_batch(sig.nwt, bx, ints + b->L.pb(), ints + b->L.nb(), static_cast<int>(sig.gb), st);
+        e = tx::launch_boxcar_batch(sig.nwt, sig.ldsb, bx, ints + b->L.pb(), ints + b->L.nb(), static_cast<int>(sig.gb),
+                                    st);
     return e;
 }
 
@@ -257,6 +259,7 @@ tx_status tx_batch_reserve(tx_batch_t b, tx_plan_t plan, int32_t nw, int64_t max
     if (nw > 0) {
         f.any_box = true;
         f.nwt = std::max(f.nwt, tx::boxcar_nwt(nw));
+        f.ldsb = std::max(f.ldsb, tx::boxcar_tmax_bytes(f.nwt, max_nt));
         f.gb += static_cast<int64_t>(count) * plan->ndm;
     }
     if (f.g1 > INT32_MAX || f.g2[gi] > INT32_MAX || f.gb > INT32_MAX) return TX_ENOTSUP;
@@ -328,6 +331,11 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
         tot2[iw_index(geo[static_cast<size_t>(k)].iw)] += tx::stage2_tiles(a2);
         if (j.has_box) totb += j.plan->ndm;
     }
+    // Boxcar dynamic LDS: the per-(tile, width) maxima of the longest row that
+    // fits (longer rows rescan their tiles instead).
+    int ldsb = 0;
+    for (const Job& j : b->jobs)
+        if (j.has_box && j.nt_out > 0) ldsb = std::max(ldsb, tx::boxcar_tmax_bytes(sig.nwt, j.nt_out));
     const bool use_graph = (b->flags & TX_BATCH_GRAPH) && stream != nullptr;
     if (use_graph && b->exec) {
         // A captured graph fixes the kernels, grids and LDS sizes.
@@ -356,7 +364,10 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
                 tx::fill_stage_args(j.plan, gc, nullptr, 0, nt_cap, nullptr, 0, nullptr, &a1, &a2);
                 c1 += tx::stage1_tiles(a1);
                 c2[iw_index(gc.iw)] += tx::stage2_tiles(a2);
-                if (j.has_box) cb += j.plan->ndm;
+                if (j.has_box) {
+                    cb += j.plan->ndm;
+                    ldsb = std::max(ldsb, tx::boxcar_tmax_bytes(sig.nwt, nt_cap));
+                }
             }
             tot1 = std::max(tot1, c1);
             totb = std::max(totb, cb);
@@ -364,6 +375,7 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
         }
         sig.g1 = std::max(tot1, use_graph ? f.g1 : 0);
         sig.gb = std::max(totb, use_graph ? f.gb : 0);
+        sig.ldsb = std::max(ldsb, use_graph ? f.ldsb : 0);
         for (int g = 0; g < kNIW; ++g) sig.g2[g] = std::max(tot2[g], use_graph ? f.g2[g] : 0);
         if (sig.g1 > INT32_MAX || sig.gb > INT32_MAX) return TX_ENOTSUP;
         for (int g = 0; g < kNIW; ++g)
@@ -424,6 +436,8 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
             bx.ndm = j.plan->ndm;
             bx.nt = static_cast<int32_t>(j.nt_out);
             tx::boxcar_fit(&bx, j.box.widths, j.box.nw, j.nt_out);
+            const int need = tx::boxcar_tmax_bytes(sig.nwt, j.nt_out);
+            bx.tmax_ok = (need > 0 && need <= sig.ldsb) ? 1 : 0;
             hb[nb] = bx;
             hi[b->L.pb() + nb + 1] = hi[b->L.pb() + nb] + bx.ndm;
             ++nb;

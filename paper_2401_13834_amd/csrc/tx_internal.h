@@ -91,6 +91,7 @@ struct BoxcarArgs {
     double gamma;
     int32_t want_peaks;
     int32_t want_cands;
+    int32_t tmax_ok;        // the launch's dynamic LDS holds this row's per-(tile, width) maxima
     double* snr;
     int32_t* width;
     int64_t* time;
@@ -212,8 +213,12 @@ hipError_t launch_stage1_batch(int variant, int lds, const Stage1Args* d_jobs, c
 hipError_t launch_stage2_batch(int iw, int variant, int lds, const Stage2Args* d_jobs, const int* d_prefix,
                                const int* d_njobs, int grid, hipStream_t stream);
 // Boxcar over many row sets: rows of all jobs, job of a row by prefix sums.
-hipError_t launch_boxcar_batch(int nwt, const BoxcarArgs* d_jobs, const int* d_prefix, const int* d_njobs, int grid,
-                               hipStream_t stream);
+hipError_t launch_boxcar_batch(int nwt, int lds, const BoxcarArgs* d_jobs, const int* d_prefix, const int* d_njobs,
+                               int grid, hipStream_t stream);
+// Dynamic LDS bytes for the per-(tile, width) maxima of a row of nt samples
+// with nwt widths, or 0 when they do not fit (the kernel then rescans every
+// tile for candidates).
+int boxcar_tmax_bytes(int nwt, int64_t nt);
 hipError_t launch_zero_counts(const BoxcarArgs* d_jobs, const int* d_njobs, int max_jobs, hipStream_t stream);
 
 // Largest dynamic LDS per workgroup the current device allows (capped at kMaxLds).

@@ -1,24 +1,24 @@
 // Boxcar matched filter for gfx950 (MI355X): per-DM noise statistics, peak
-// S/N over the boxcar widths, and the thresholded DM-time candidates.
+// S/N over the boxcar widths, and the thresholded DM-time candidates
+// (Sec. 2.4, Eq. 5; Sec. 2.5).
 //
-// One workgroup per DM row (the batch form walks the rows of many jobs with a
-// persistent grid).  Per row:
-//  1. exact sums of y and y^2 (uint64; exact for values < 2^21 and rows
-//     <= 2^20), then c = floor(sum/T), Q = sum y^2 - 2 c sum + T c^2
-//     (= sum (y - c)^2, evaluated mod 2^64), var = Q/T - (r/T)^2, sigma and
-//     1/(sigma T) in float64;
-//  2. per width, the least window sum S* whose S/N reaches gamma, by bisection
-//     with the same float64 expression, so the per-window test is an integer
-//     compare;
-//  3. per tile of 4096 window starts: the tile's running sums (exclusive
-//     prefix, uint32; window sums are exact as differences) of 4096 + the
-//     longest width samples in LDS; every (start, width) updates the largest
-//     sum per width (earliest start) and a per-start flag max(S - S*); flagged
-//     starts compute the S/N of every width and append (row, t, best width,
-//     snr) to the candidate list.
-// Thread tid owns the starts t0 + 1024 k + 4 tid + r (k, r < 4), so its own
-// running sums and those a window of width 4m needs are aligned 16-byte LDS
-// reads.
+// One workgroup per DM row (the batch form takes the rows of many jobs).  The
+// row is read from HBM once, in tiles of 4096 window starts:
+//  * each tile's running sums (exclusive prefix, uint32: window sums are exact
+//    as differences) of its 4096 + longest-width samples go to LDS; the same
+//    loads accumulate the exact moments sum y and sum y^2 (uint64);
+//  * per width, every lane keeps the largest window sum of its 16 starts; the
+//    wavefront's largest is compared with the wavefront's best so far, and
+//    only when it beats it (a few tiles per row) does the wavefront look up
+//    the earliest start reaching it; the workgroup's largest sum per (tile,
+//    width) is kept in LDS.
+// Then c = floor(sum/T), Q = sum y^2 - 2 c sum + T c^2 (= sum (y - c)^2, mod
+// 2^64), var = Q/T - (r/T)^2, sigma and 1/(sigma T) in float64 give the peak
+// S/N, and per width the least window sum S* whose S/N reaches gamma
+// (bisection with the same float64 expression).  Only tiles where some width's
+// largest sum reaches its S* are read again to list candidates: a start is a
+// candidate when some width passes, and is reported with the width of highest
+// S/N.  Thread tid owns the starts t0 + tid + 256 j (j < 16).
 #include <algorithm>
 
 #include "tx_internal.h"
@@ -26,6 +26,10 @@
 #pragma clang fp contract(off)
 
 namespace tx {
+
+// Largest dynamic LDS for the per-(tile, width) maxima; rows needing more
+// read every tile again for candidates.
+constexpr int kTileMaxLds = 16 * 1024;
 
 template <int NWT>
 struct BoxShared {
@@ -39,9 +43,11 @@ struct BoxShared {
     double inv_d;
     long long sum;
     int state;
-    int32_t wS[kWaves][NWT];
-    int32_t wT[kWaves][NWT];
+    int32_t wS[kWaves][NWT];       // per wavefront: best sum per width so far, and
+    int32_t wT[kWaves][NWT];       // its earliest start
 };
+
+extern __shared__ int32_t tx_box_tmax[];   // [tiles][NWT]: workgroup's largest sum per tile and width
 
 __device__ __forceinline__ double snr_of(int64_t T, int64_t S, int64_t w, int64_t sum, double inv_d, double rsw) {
     const int64_t N = T * S - w * sum;
@@ -55,61 +61,6 @@ __device__ __forceinline__ V wave_sum(V v) {
     return v;
 }
 
-// Exclusive running sums of y[t0 + e], e in [e0, e0 + 4096) (zeros past the
-// row), written to P[e]; returns the round total.  Thread tid owns 16
-// consecutive samples.
-__device__ __forceinline__ uint32_t scan_round(const TX_GLOBAL int32_t* __restrict__ y, int T, int t0, int e0, int L,
-                                               uint32_t base, uint32_t* P, uint32_t* wtot, bool vec, int tid) {
-    const int lane = tid & 63, wave = tid >> 6;
-    const int e = e0 + 16 * tid;
-    uint32_t v[16];
-    const int64_t t = static_cast<int64_t>(t0) + e;
-    if (vec && e + 16 <= L && t + 16 <= T) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint4 q = *reinterpret_cast<const TX_GLOBAL uint4*>(y + t + 4 * k);
-            v[4 * k] = q.x;
-            v[4 * k + 1] = q.y;
-            v[4 * k + 2] = q.z;
-            v[4 * k + 3] = q.w;
-        }
-    } else {
-        // Valid samples of this lane in this round (the count changes with the
-        // tile, so no per-element condition is hoisted out of the tile loop).
-        const int64_t lim = min(static_cast<int64_t>(L - e), static_cast<int64_t>(T) - t);
-#pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = k < lim ? static_cast<uint32_t>(y[t + k]) : 0u;
-    }
-    uint32_t ex[16];
-    uint32_t run = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        ex[k] = run;
-        run += v[k];
-    }
-    uint32_t incl = run;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t n = __shfl_up(incl, o);
-        if (lane >= o) incl += n;
-    }
-    if (lane == 63) wtot[wave] = incl;
-    __syncthreads();
-    uint32_t before = base;
-    for (int w = 0; w < wave; ++w) before += wtot[w];
-    before += incl - run;
-    if (e < L) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            *reinterpret_cast<uint4*>(P + e + 4 * k) =
-                make_uint4(before + ex[4 * k], before + ex[4 * k + 1], before + ex[4 * k + 2], before + ex[4 * k + 3]);
-    }
-    const uint32_t total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
-    __syncthreads();
-    return total;
-}
-
-// One tile of 4096 window starts.  TAIL: some windows reach past the row end.
 // Wavefront max / min of an int32 with DPP moves (quad, half-row and row
 // permutes, then the row broadcasts of 15 and 31); the result is read from
 // lane 63.
@@ -132,130 +83,179 @@ __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
     return __builtin_amdgcn_readlane(v, 63);
 }
 
-// One tile of 4096 window starts.  TAIL: some windows reach past the row end.
-// Per width slot, each lane keeps only the largest sum of its 16 starts; the
-// wavefront's largest sum is compared with the wavefront's best so far
-// (kept in LDS per wavefront) and only when it beats it (a few tiles per
-// row) does the wavefront look up the earliest start reaching it.  Candidate
-// flags take max(S - S*) over pairs of width slots with one 3-input max.
-// Width slots past the row's widths repeat its last width, so the loop has no
-// per-width branches.
-template <int NWT, bool TAIL, bool CANDS>
-__device__ __forceinline__ void boxcar_tile(const BoxcarArgs& a, BoxShared<NWT>& sh, int row, int t0, long long sum,
-                                            double inv_d, int tid) {
+// Moments of the samples a thread loaded (exact; a value >= 2^21 or < 0 flags
+// the row).
+struct Moments {
+    unsigned long long s1 = 0, s2 = 0;
+    uint32_t bad = 0;
+};
+
+// Exclusive running sums of y[t0 + e] for e < L = 4096 + longest width
+// (<= 5120; zeros past the row) into P[e], and P[L] = their total.  Thread
+// tid owns the 20 consecutive samples from e = 20 tid.  COUNT: add the
+// samples with e < 4096 (the tile's own) to the moments.
+template <bool COUNT>
+__device__ __forceinline__ void scan_tile(const TX_GLOBAL int32_t* __restrict__ y, int T, int t0, int L, uint32_t* P,
+                                          uint32_t* wtot, bool vec, int tid, Moments& m) {
+    constexpr int kPer = 20;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int e = kPer * tid;
+    uint32_t v[kPer];
+    const int64_t t = static_cast<int64_t>(t0) + e;
+    if (vec && e + kPer <= L && t + kPer <= T) {
+#pragma unroll
+        for (int k = 0; k < kPer / 4; ++k) {
+            const uint4 q = *reinterpret_cast<const TX_GLOBAL uint4*>(y + t + 4 * k);
+            v[4 * k] = q.x;
+            v[4 * k + 1] = q.y;
+            v[4 * k + 2] = q.z;
+            v[4 * k + 3] = q.w;
+        }
+    } else {
+        // Valid samples of this lane (the count changes with the tile, so no
+        // per-element condition is hoisted out of the tile loop).
+        const int64_t lim = min(static_cast<int64_t>(L - e), static_cast<int64_t>(T) - t);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) v[k] = k < lim ? static_cast<uint32_t>(y[t + k]) : 0u;
+    }
+    if (COUNT) {
+        constexpr uint32_t kMask = static_cast<uint32_t>(TX_MAX_VALUE) - 1u;
+        const int own = min(kPer, kBoxTile - e);       // samples of this tile (the rest belong to the next)
+        uint32_t ps = 0;                               // < 20 * 2^21: no wrap
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t x = k < own ? v[k] : 0u;
+            m.bad |= x > kMask ? 1u : 0u;
+            const uint32_t u = x & kMask;
+            ps += u;
+            m.s2 += static_cast<unsigned long long>(u) * u;
+        }
+        m.s1 += ps;
+    }
+    uint32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) run += v[k];
+    uint32_t incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t n = __shfl_up(incl, o);
+        if (lane >= o) incl += n;
+    }
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wtot[w];
+    before += incl - run;
+    if (e < L) {
+#pragma unroll
+        for (int k = 0; k < kPer / 4; ++k) {
+            const uint32_t p0 = before, p1 = p0 + v[4 * k], p2 = p1 + v[4 * k + 1], p3 = p2 + v[4 * k + 2];
+            before = p3 + v[4 * k + 3];
+            *reinterpret_cast<uint4*>(P + e + 4 * k) = make_uint4(p0, p1, p2, p3);
+        }
+    }
+    if (tid == 0) P[L] = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+    __syncthreads();
+}
+
+// Peak search over one tile.  Lane tid owns the starts t0 + tid + 256 j
+// (j < 16), so a wavefront reads 64 consecutive LDS words per load (no bank
+// conflicts for any width).  TAIL: some windows reach past the row end.  Width
+// slots past the row's widths repeat its last width.
+template <int NWT, bool TAIL>
+__device__ __forceinline__ void peak_tile(const BoxcarArgs& a, BoxShared<NWT>& sh, int tile, int t0, int tid,
+                                          bool keep_tmax) {
     const int wave = tid >> 6;
     const int T = a.nt;
-    const int lb = 4 * tid;     // this lane's first start in the tile
-    uint32_t Pt[4][4];
-    int32_t mx[4][4];
+    uint32_t Pt[16];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint4 q = *reinterpret_cast<const uint4*>(sh.P + lb + 1024 * k);
-        Pt[k][0] = q.x;
-        Pt[k][1] = q.y;
-        Pt[k][2] = q.z;
-        Pt[k][3] = q.w;
+    for (int j = 0; j < 16; ++j) Pt[j] = sh.P[tid + 256 * j];
+    int32_t tm[NWT];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) mx[k][r] = INT32_MIN;
-    }
-#pragma unroll 1
     for (int i = 0; i < NWT; i += 2) {
         // Per-width values come from LDS, which keeps the registers free.
         const int w0 = sh.wd[i], w1 = sh.wd[i + 1];
-        const int32_t thr0 = CANDS ? max(sh.sthr[i], 0) : 0;
-        const int32_t thr1 = CANDS ? max(sh.sthr[i + 1], 0) : 0;
+        const uint32_t* p0 = sh.P + tid + w0;
+        const uint32_t* p1 = sh.P + tid + w1;
         int32_t tm0 = INT32_MIN, tm1 = INT32_MIN;
-        const uint32_t* p0 = sh.P + lb + w0;
-        const uint32_t* p1 = sh.P + lb + w1;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int base = 1024 * k + 4 * tid;
-            const uint2 u0 = *reinterpret_cast<const uint2*>(p0 + 1024 * k);
-            const uint2 u1 = *reinterpret_cast<const uint2*>(p0 + 1024 * k + 2);
-            const uint2 v0 = *reinterpret_cast<const uint2*>(p1 + 1024 * k);
-            const uint2 v1 = *reinterpret_cast<const uint2*>(p1 + 1024 * k + 2);
-            const uint32_t A[4] = {u0.x, u0.y, u1.x, u1.y};
-            const uint32_t B[4] = {v0.x, v0.y, v1.x, v1.y};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int32_t S0 = static_cast<int32_t>(A[r] - Pt[k][r]);
-                const int32_t S1 = static_cast<int32_t>(B[r] - Pt[k][r]);
-                const int t = t0 + base + r;
-                const bool ok0 = !TAIL || t + w0 <= T;   // no window past the row end
-                const bool ok1 = !TAIL || t + w1 <= T;
-                tm0 = max(tm0, ok0 ? S0 : INT32_MIN);
-                tm1 = max(tm1, ok1 ? S1 : INT32_MIN);
-                if (CANDS) {
-                    // valid sums are >= 0 and thresholds in [0, 2^31), so S - thr cannot wrap
-                    const int32_t d0 = ok0 ? S0 - thr0 : -1;
-                    const int32_t d1 = ok1 ? S1 - thr1 : -1;
-                    mx[k][r] = max(max(mx[k][r], d0), d1);
-                }
-            }
+        for (int j = 0; j < 16; ++j) {
+            const int32_t S0 = static_cast<int32_t>(p0[256 * j] - Pt[j]);
+            const int32_t S1 = static_cast<int32_t>(p1[256 * j] - Pt[j]);
+            const int t = t0 + tid + 256 * j;
+            tm0 = max(tm0, (!TAIL || t + w0 <= T) ? S0 : INT32_MIN);   // no window past the row end
+            tm1 = max(tm1, (!TAIL || t + w1 <= T) ? S1 : INT32_MIN);
         }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int ii = i + h;
-            const int w = h ? w1 : w0;
-            const int32_t wm = wave_max_i32(h ? tm1 : tm0);
-            if (wm > sh.wS[wave][ii]) {                 // wavefront-uniform, a few tiles per row
-                int32_t first = INT32_MAX;
-#pragma unroll 1
-                for (int kr = 15; kr >= 0; --kr) {      // rolled: this path is rare
-                    const int e = 1024 * (kr >> 2) + 4 * tid + (kr & 3);
-                    const int t = t0 + e;
-                    const int32_t S = static_cast<int32_t>(sh.P[e + w] - sh.P[e]);
-                    const bool ok = !TAIL || t + w <= T;
-                    first = (ok && S == wm) ? t : first;
-                }
-                const int32_t ft = wave_min_i32(first);
-                if ((tid & 63) == 0) {
-                    sh.wS[wave][ii] = wm;
-                    sh.wT[wave][ii] = ft;
-                }
-            }
-        }
-        // Keep each width pair's LDS reads next to their arithmetic (the
-        // scheduler would otherwise hoist every width's reads and run out of
-        // registers).
+        tm[i] = tm0;
+        tm[i + 1] = tm1;
+        // Keep each width pair's LDS reads next to their arithmetic.
         __builtin_amdgcn_sched_barrier(0);
     }
-    if (CANDS) {
-        // Flagged starts (rare) as a bit mask, then one start at a time.
-        uint32_t flags = 0;
+    // Wavefront maxima of all widths (independent reductions, interleaved).
+    int32_t wm[NWT];
 #pragma unroll
-        for (int k = 3; k >= 0; --k)
+    for (int i = 0; i < NWT; ++i) wm[i] = wave_max_i32(tm[i]);
+#pragma unroll 1
+    for (int ii = 0; ii < NWT; ++ii) {
+        // wm[ii] with a run-time ii: select among the (uniform) values.
+        int32_t m = wm[0];
 #pragma unroll
-            for (int r = 3; r >= 0; --r) flags = (flags << 1) | (mx[k][r] >= 0 ? 1u : 0u);   // bit 4k + r
-        while (flags) {
-            const int kr = __builtin_ctz(flags);
-            flags &= flags - 1;
-            const int e = 1024 * (kr >> 2) + 4 * tid + (kr & 3);
-            const int t = t0 + e;
-            const uint32_t pt = sh.P[e];
-            double bs = 0.0;
-            int bw = -1;
-            for (int i = 0; i < a.ne; ++i) {
-                const int w = sh.wd[i];
-                if (t + w > T) continue;
-                const int32_t S = static_cast<int32_t>(sh.P[e + w] - pt);
-                const double sn = snr_of(T, S, w, sum, inv_d, sh.rs[i]);
-                if (bw < 0 || sn > bs) {
-                    bs = sn;
-                    bw = w;
-                }
+        for (int k = 1; k < NWT; ++k) m = (k == ii) ? wm[k] : m;
+        if (keep_tmax && (tid & 63) == 0) atomicMax(&tx_box_tmax[tile * NWT + ii], m);
+        if (m > sh.wS[wave][ii]) {                      // wavefront-uniform, a few tiles per row
+            const int w = sh.wd[ii];
+            int32_t first = INT32_MAX;
+#pragma unroll 1
+            for (int j = 15; j >= 0; --j) {             // rolled: this path is rare
+                const int e = tid + 256 * j;
+                const int t = t0 + e;
+                const int32_t S = static_cast<int32_t>(sh.P[e + w] - sh.P[e]);
+                first = ((!TAIL || t + w <= T) && S == m) ? t : first;
             }
-            {
-                const unsigned long long slot = atomicAdd(a.count, 1ull);
-                if (static_cast<long long>(slot) < a.cap) {
-                    tx_cand c;
-                    c.dm_index = row;
-                    c.width = bw;
-                    c.time = t;
-                    c.snr = bs;
-                    to_global(a.cands)[slot] = c;
-                }
+            const int32_t ft = wave_min_i32(first);
+            if ((tid & 63) == 0) {
+                sh.wS[wave][ii] = m;
+                sh.wT[wave][ii] = ft;
             }
+        }
+    }
+}
+
+// Candidates of one tile (rare: only tiles where some width's largest sum
+// reaches its threshold S*).  Widths increase, so a strict ">" keeps the
+// smaller width on equal S/N.
+template <int NWT>
+__device__ __forceinline__ void cand_tile(const BoxcarArgs& a, BoxShared<NWT>& sh, int row, int t0, long long sum,
+                                          double inv_d, int tid) {
+    const int T = a.nt;
+#pragma unroll 1
+    for (int j = 0; j < 16; ++j) {
+        const int e = tid + 256 * j;
+        const int t = t0 + e;
+        const uint32_t pt = sh.P[e];
+        bool pass = false;
+        double bs = 0.0;
+        int bw = -1;
+        for (int i = 0; i < a.ne; ++i) {
+            const int w = sh.wd[i];
+            if (t + w > T) continue;
+            const int32_t S = static_cast<int32_t>(sh.P[e + w] - pt);
+            pass = pass || S >= max(sh.sthr[i], 0);       // window sums are >= 0
+            const double sn = snr_of(T, S, w, sum, inv_d, sh.rs[i]);
+            if (bw < 0 || sn > bs) {
+                bs = sn;
+                bw = w;
+            }
+        }
+        if (!pass) continue;
+        const unsigned long long slot = atomicAdd(a.count, 1ull);
+        if (static_cast<long long>(slot) < a.cap) {
+            tx_cand c;
+            c.dm_index = row;
+            c.width = bw;
+            c.time = t;
+            c.snr = bs;
+            to_global(a.cands)[slot] = c;
         }
     }
 }
@@ -268,6 +268,8 @@ __device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShar
     const int T = a.nt;
     const TX_GLOBAL int32_t* __restrict__ y = to_global(a.y) + static_cast<size_t>(row) * a.pitch;
     const bool vec = ((reinterpret_cast<uintptr_t>(a.y) + static_cast<uintptr_t>(row) * a.pitch * 4) & 15) == 0;
+    const int ntiles = (T + kBoxTile - 1) / kBoxTile;
+    const bool keep_tmax = a.tmax_ok != 0;
     if (tid < NWT) {
         int32_t w = 0;
         double r = 0.0;
@@ -280,36 +282,45 @@ __device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShar
         sh.wd[tid] = w;
         sh.rs[tid] = r;
     }
-
-    // ---- moments ----------------------------------------------------------
-    unsigned long long s1 = 0, s2 = 0;
-    int bad = 0;
-    const int nvec = vec ? T / 4 : 0;
-    for (int v = tid; v < nvec; v += kThreads) {
-        const int4 q = *reinterpret_cast<const TX_GLOBAL int4*>(y + 4 * v);
-        const int32_t e[4] = {q.x, q.y, q.z, q.w};
+    if (lane == 0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            bad |= (e[k] < 0) | (e[k] >= TX_MAX_VALUE);
-            const uint32_t u = static_cast<uint32_t>(e[k]);
-            s1 += u;
-            s2 += static_cast<unsigned long long>(u) * u;
+        for (int i = 0; i < NWT; ++i) {
+            sh.wS[wave][i] = INT32_MIN;
+            sh.wT[wave][i] = 0;
         }
     }
-    for (int t = 4 * nvec + tid; t < T; t += kThreads) {
-        const int32_t e = y[t];
-        bad |= (e < 0) | (e >= TX_MAX_VALUE);
-        const uint32_t u = static_cast<uint32_t>(e);
-        s1 += u;
-        s2 += static_cast<unsigned long long>(u) * u;
+    if (keep_tmax)
+        for (int k = tid; k < ntiles * NWT; k += kThreads) tx_box_tmax[k] = INT32_MIN;
+    __syncthreads();
+
+    // ---- one pass over the row: running sums, moments, peaks ------------------
+    const int L = kBoxTile + a.wmax;
+    Moments m;
+    for (int tile = 0; tile < ntiles; ++tile) {
+        const int t0 = tile * kBoxTile;
+        // The thread index, made opaque to the compiler in every tile: else it
+        // hoists dozens of lane-dependent masks and addresses out of this loop
+        // and spills them.
+        int tv = tid;
+        asm volatile("" : "+v"(tv));
+        scan_tile<true>(y, T, t0, L, sh.P, sh.wtot, vec, tv, m);
+        if (a.ne > 0) {
+            if (t0 + kBoxTile + a.wmax > T) peak_tile<NWT, true>(a, sh, tile, t0, tv, keep_tmax);
+            else peak_tile<NWT, false>(a, sh, tile, t0, tv, keep_tmax);
+        }
+        __syncthreads();
     }
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    bad = __any(bad) ? 1 : 0;
-    if (lane == 0) {
-        sh.red1[wave] = s1;
-        sh.red2[wave] = s2;
-        sh.redbad[wave] = bad;
+
+    // ---- statistics ----------------------------------------------------------------
+    {
+        const unsigned long long s1 = wave_sum(m.s1);
+        const unsigned long long s2 = wave_sum(m.s2);
+        const int bad = __any(m.bad != 0) ? 1 : 0;
+        if (lane == 0) {
+            sh.red1[wave] = s1;
+            sh.red2[wave] = s2;
+            sh.redbad[wave] = bad;
+        }
     }
     __syncthreads();
     if (tid == 0) {
@@ -356,92 +367,73 @@ __device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShar
         __syncthreads();
         return;
     }
-    // ---- per-width thresholds ------------------------------------------------
-    if (a.want_cands && tid < NWT) {
-        const int64_t w = sh.wd[tid];
-        const double rsw = sh.rs[tid];
-        int64_t lo = INT32_MIN, hi = INT32_MAX;
-        int32_t res;
-        if (snr_of(T, lo, w, sum, inv_d, rsw) >= a.gamma) {
-            res = INT32_MIN;
-        } else if (!(snr_of(T, hi, w, sum, inv_d, rsw) >= a.gamma)) {
-            res = INT32_MAX;                          // never reached: window sums are < 2^31 - 1
-        } else {
-            while (hi - lo > 1) {                     // snr(lo) < gamma <= snr(hi)
-                const int64_t mid = lo + (hi - lo) / 2;
-                if (snr_of(T, mid, w, sum, inv_d, rsw) >= a.gamma) hi = mid; else lo = mid;
-            }
-            res = static_cast<int32_t>(hi);
-        }
-        sh.sthr[tid] = res;
-    }
-    __syncthreads();
 
-    // ---- tiles ------------------------------------------------------------------
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NWT; ++i) {
-            sh.wS[wave][i] = INT32_MIN;   // this wavefront's best sum per width so far
-            sh.wT[wave][i] = 0;
-        }
-    }
-    const int L = kBoxTile + a.wmax;
-    for (int t0 = 0; a.ne > 0 && t0 < T; t0 += kBoxTile) {
-        // The thread index, made opaque to the compiler in every tile: else it
-        // hoists dozens of lane-dependent masks and addresses out of this loop
-        // and spills them.
-        int tv = tid;
-        asm volatile("" : "+v"(tv));
-        const uint32_t tot = scan_round(y, T, t0, 0, L, 0u, sh.P, sh.wtot, vec, tv);
-        uint32_t tot2 = 0;
-        if (L > kBoxTile) tot2 = scan_round(y, T, t0, kBoxTile, L, tot, sh.P, sh.wtot, vec, tv);
-        if (tid == 0) sh.P[L] = tot + tot2;
-        __syncthreads();
-        const bool tail = t0 + kBoxTile + a.wmax > T;
-        if (a.want_cands) {
-            if (tail) boxcar_tile<NWT, true, true>(a, sh, row, t0, sum, inv_d, tv);
-            else boxcar_tile<NWT, false, true>(a, sh, row, t0, sum, inv_d, tv);
-        } else {
-            if (tail) boxcar_tile<NWT, true, false>(a, sh, row, t0, sum, inv_d, tv);
-            else boxcar_tile<NWT, false, false>(a, sh, row, t0, sum, inv_d, tv);
-        }
-        __syncthreads();
-    }
-    // ---- peak: reduce (largest S, earliest t) per width ---------------------------
-    if (a.want_peaks) {
-        __syncthreads();
-        if (tid == 0) {
-            double bs = 0.0;
-            int bw = -1;
-            long long bt = 0;
-            for (int i = 0; i < a.ne; ++i) {
-                const int w = sh.wd[i];
-                int32_t S = sh.wS[0][i], t = sh.wT[0][i];
-                for (int v = 1; v < kWaves; ++v)
-                    if (sh.wS[v][i] > S || (sh.wS[v][i] == S && sh.wT[v][i] < t)) {
-                        S = sh.wS[v][i];
-                        t = sh.wT[v][i];
-                    }
-                const double sn = snr_of(T, S, w, sum, inv_d, sh.rs[i]);
-                if (bw < 0 || sn > bs) {
-                    bs = sn;
-                    bw = w;
-                    bt = t;
+    // ---- peak: (largest S, earliest t) per width, then the best width -------------
+    if (a.want_peaks && tid == 0) {
+        double bs = 0.0;
+        int bw = -1;
+        long long bt = 0;
+        for (int i = 0; i < a.ne; ++i) {
+            const int w = sh.wd[i];
+            int32_t S = sh.wS[0][i], t = sh.wT[0][i];
+            for (int v = 1; v < kWaves; ++v)
+                if (sh.wS[v][i] > S || (sh.wS[v][i] == S && sh.wT[v][i] < t)) {
+                    S = sh.wS[v][i];
+                    t = sh.wT[v][i];
                 }
+            const double sn = snr_of(T, S, w, sum, inv_d, sh.rs[i]);
+            if (bw < 0 || sn > bs) {
+                bs = sn;
+                bw = w;
+                bt = t;
             }
-            if (bw < 0) {
-                bs = 0.0;
-                bw = a.w_first;
-                bt = 0;
+        }
+        if (bw < 0) {
+            bs = 0.0;
+            bw = a.w_first;
+            bt = 0;
+        }
+        to_global(a.snr)[row] = bs;
+        to_global(a.width)[row] = bw;
+        to_global(a.time)[row] = bt;
+    }
+
+    // ---- candidates ------------------------------------------------------------------
+    if (a.want_cands && a.ne > 0) {
+        if (tid < a.ne) {
+            const int64_t w = sh.wd[tid];
+            const double rsw = sh.rs[tid];
+            int64_t lo = INT32_MIN, hi = INT32_MAX;
+            int32_t res;
+            if (snr_of(T, lo, w, sum, inv_d, rsw) >= a.gamma) {
+                res = INT32_MIN;
+            } else if (!(snr_of(T, hi, w, sum, inv_d, rsw) >= a.gamma)) {
+                res = INT32_MAX;                          // never reached: window sums are < 2^31 - 1
+            } else {
+                while (hi - lo > 1) {                     // snr(lo) < gamma <= snr(hi)
+                    const int64_t mid = lo + (hi - lo) / 2;
+                    if (snr_of(T, mid, w, sum, inv_d, rsw) >= a.gamma) hi = mid; else lo = mid;
+                }
+                res = static_cast<int32_t>(hi);
             }
-            to_global(a.snr)[row] = bs;
-            to_global(a.width)[row] = bw;
-            to_global(a.time)[row] = bt;
+            sh.sthr[tid] = res;
+        }
+        __syncthreads();
+        for (int tile = 0; tile < ntiles; ++tile) {
+            bool hit = !keep_tmax;
+            if (keep_tmax)
+                for (int i = 0; i < a.ne; ++i) hit = hit || tx_box_tmax[tile * NWT + i] >= max(sh.sthr[i], 0);
+            if (!hit) continue;                           // workgroup-uniform
+            Moments unused;
+            scan_tile<false>(y, T, tile * kBoxTile, L, sh.P, sh.wtot, vec, tid, unused);
+            cand_tile<NWT>(a, sh, row, tile * kBoxTile, sum, inv_d, tid);
+            __syncthreads();
         }
     }
     __syncthreads();
 }
 
+// Single job: one workgroup per row.
 template <int NWT>
 __global__ __launch_bounds__(kThreads) void boxcar_kernel(BoxcarArgs a) {
     __shared__ BoxShared<NWT> sh;
@@ -484,9 +476,14 @@ __global__ void zero_counts_kernel(const BoxcarArgs* __restrict__ jobs, const in
 }
 
 // ---------------------------------------------------------------------------
-// Launches.
-// ---------------------------------------------------------------------------
-hipError_t launch_boxcar(const BoxcarArgs& a, hipStream_t stream) {
+
+int boxcar_tmax_bytes(int nwt, int64_t nt) {
+    const int64_t b = (nt + kBoxTile - 1) / kBoxTile * boxcar_nwt(nwt) * 4;
+    return b <= kTileMaxLds ? static_cast<int>(b) : 0;
+}
+
+hipError_t launch_boxcar(const BoxcarArgs& a_in, hipStream_t stream) {
+    BoxcarArgs a = a_in;
     if (a.want_cands) {
         hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, stream, a.count);
         const hipError_t e = hipGetLastError();
@@ -494,30 +491,32 @@ hipError_t launch_boxcar(const BoxcarArgs& a, hipStream_t stream) {
     }
     if (a.ndm <= 0) return hipSuccess;
     const int grid = a.ndm;
+    const int nwt = boxcar_nwt(a.ne);
+    const int lds = boxcar_tmax_bytes(a.ne, a.nt);
+    a.tmax_ok = lds > 0 ? 1 : 0;
     const int prof = prof_begin(TX_KERNEL_BOXCAR, stream);
-    switch (boxcar_nwt(a.ne)) {
-        case 4: hipLaunchKernelGGL(boxcar_kernel<4>, dim3(grid), dim3(kThreads), 0, stream, a); break;
-        case 8: hipLaunchKernelGGL(boxcar_kernel<8>, dim3(grid), dim3(kThreads), 0, stream, a); break;
-        case 12: hipLaunchKernelGGL(boxcar_kernel<12>, dim3(grid), dim3(kThreads), 0, stream, a); break;
-        case 16: hipLaunchKernelGGL(boxcar_kernel<16>, dim3(grid), dim3(kThreads), 0, stream, a); break;
-        default: hipLaunchKernelGGL(boxcar_kernel<32>, dim3(grid), dim3(kThreads), 0, stream, a); break;
+    switch (nwt) {
+        case 4: hipLaunchKernelGGL(boxcar_kernel<4>, dim3(grid), dim3(kThreads), lds, stream, a); break;
+        case 8: hipLaunchKernelGGL(boxcar_kernel<8>, dim3(grid), dim3(kThreads), lds, stream, a); break;
+        case 12: hipLaunchKernelGGL(boxcar_kernel<12>, dim3(grid), dim3(kThreads), lds, stream, a); break;
+        case 16: hipLaunchKernelGGL(boxcar_kernel<16>, dim3(grid), dim3(kThreads), lds, stream, a); break;
+        default: hipLaunchKernelGGL(boxcar_kernel<32>, dim3(grid), dim3(kThreads), lds, stream, a); break;
     }
     const hipError_t e = hipGetLastError();
     prof_end(prof, stream);
     return e;
 }
 
-
-hipError_t launch_boxcar_batch(int nwt, const BoxcarArgs* d_jobs, const int* d_prefix, const int* d_njobs, int grid,
-                               hipStream_t stream) {
+hipError_t launch_boxcar_batch(int nwt, int lds, const BoxcarArgs* d_jobs, const int* d_prefix, const int* d_njobs,
+                               int grid, hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
     const int prof = prof_begin(TX_KERNEL_BOXCAR, stream);
     switch (boxcar_nwt(nwt)) {
-        case 4: hipLaunchKernelGGL(boxcar_batch_kernel<4>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs); break;
-        case 8: hipLaunchKernelGGL(boxcar_batch_kernel<8>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs); break;
-        case 12: hipLaunchKernelGGL(boxcar_batch_kernel<12>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs); break;
-        case 16: hipLaunchKernelGGL(boxcar_batch_kernel<16>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs); break;
-        default: hipLaunchKernelGGL(boxcar_batch_kernel<32>, dim3(grid), dim3(kThreads), 0, stream, d_jobs, d_prefix, d_njobs); break;
+        case 4: hipLaunchKernelGGL(boxcar_batch_kernel<4>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
+        case 8: hipLaunchKernelGGL(boxcar_batch_kernel<8>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
+        case 12: hipLaunchKernelGGL(boxcar_batch_kernel<12>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
+        case 16: hipLaunchKernelGGL(boxcar_batch_kernel<16>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
+        default: hipLaunchKernelGGL(boxcar_batch_kernel<32>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
     }
     const hipError_t e = hipGetLastError();
     prof_end(prof, stream);
