@@ -142,6 +142,11 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
         }
         __syncthreads();
         const int32_t* tw = tab + wave * JW;
+        // For Q > 4: 1, hidden from the compiler, which would otherwise merge
+        // words w and w + 1 into one read and pay an address add for every
+        // q >= 4 (the paired-read offsets reach 255 words).
+        int one = 1;
+        if (Q > 4) asm volatile("" : "+v"(one));
         int c = 0;
         for (; c + 1 < nc; c += 2) {
 #pragma unroll
@@ -150,12 +155,17 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
                 const int e1 = uniform(tw[(c + 1) * J + jj]);
                 const uint32_t k0 = static_cast<uint32_t>(e0 & 3), k1 = static_cast<uint32_t>(e1 & 3);
                 const uint32_t sel0 = kOdd + k0 * 0x00010001u, sel1 = kOdd + k1 * 0x00010001u;
+                // Words w and w + 1 through two bases, so that every read is a
+                // multiple of 64 words from its base (one read per two q, with
+                // no per-q address arithmetic).
                 const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3)) + lane;
                 const uint32_t* p1 = reinterpret_cast<const uint32_t*>(dat + (e1 & ~3)) + lane;
+                const uint32_t* p0n = p0 + one;
+                const uint32_t* p1n = p1 + one;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    const uint32_t a0 = p0[64 * q], a1 = p0[64 * q + 1];
-                    const uint32_t b0 = p1[64 * q], b1 = p1[64 * q + 1];
+                    const uint32_t a0 = p0[64 * q], a1 = p0n[64 * q];
+                    const uint32_t b0 = p1[64 * q], b1 = p1n[64 * q];
                     full[jj][q] += align_b32(a1, a0, k0) + align_b32(b1, b0, k1);
                     odd[jj][q] += perm_b32(a1, a0, sel0) + perm_b32(b1, b0, sel1);
                 }
@@ -168,9 +178,10 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
                 const uint32_t k0 = static_cast<uint32_t>(e0 & 3);
                 const uint32_t sel0 = kOdd + k0 * 0x00010001u;
                 const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3)) + lane;
+                const uint32_t* p0n = p0 + one;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    const uint32_t a0 = p0[64 * q], a1 = p0[64 * q + 1];
+                    const uint32_t a0 = p0[64 * q], a1 = p0n[64 * q];
                     full[jj][q] += align_b32(a1, a0, k0);
                     odd[jj][q] += perm_b32(a1, a0, sel0);
                 }
