@@ -61,27 +61,41 @@ def make_input(tx, plan, wl, synth):
 
 
 def cpu_baseline(wl, x, g, seconds):
-    """The oracle, as it is, on a bounded sample of the same block: the first
-    K coarse groups (K*g DM trials) over the full block length, through
-    dedispersion, peaks and candidates."""
+    """The C oracle (OpenMP over the host's cores), as it is, on a bounded
+    sample of the same block: the first K coarse groups (K*g DM trials) over
+    the full block length, through dedispersion, peaks and candidates.  The
+    NumPy oracle's single-threaded rate on one group is reported beside it."""
     import oracle
+    from oracle import c_oracle as co
     nt = wl.nt
+    threads = co.max_threads()
 
     def run(k):
-        ref = oracle.make_plan(wl.freqs, wl.tsamp, wl.dms[:k * g], wl.nsub, g=g)
-        xs = x[:, :nt + ref.overlap]
         t = time.perf_counter()
-        y = oracle.dedisperse_subband(xs, ref, nt)
-        oracle.boxcar_peaks(y, wl.widths)
-        oracle.boxcar_candidates(y, wl.widths, wl.gamma)
+        y = co.dedisperse_subband(x, wl.freqs, wl.tsamp, wl.dms[:k * g], wl.nsub, g, nt, threads=threads)
+        co.boxcar_peaks(y, wl.widths, threads=threads)
+        co.boxcar_candidates(y, wl.widths, wl.gamma, threads=threads)
         return time.perf_counter() - t, k * g
 
+    run(1)                                         # warm-up (builds the library if needed)
     dt1, _ = run(1)
     k = max(1, min(len(wl.dms) // g, int(seconds / max(dt1, 1e-3))))
     dt, ntrials = run(k)
-    return {"value": ntrials * nt / dt, "unit": "DM-trial samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{ntrials} of {len(wl.dms)} DM trials ({k} coarse groups) x {nt} samples, "
-                      f"dedispersion + peaks + candidates, NumPy single-threaded, {dt:.1f} s"}
+    kmax = len(wl.dms) // g
+    if dt < 0.5 * seconds and k < kmax:           # fixed costs made the first estimate short
+        k = max(k + 1, min(kmax, int(k * seconds / max(dt, 1e-3))))
+        dt, ntrials = run(k)
+    ref = oracle.make_plan(wl.freqs, wl.tsamp, wl.dms[:g], wl.nsub, g=g)
+    t = time.perf_counter()
+    yn = oracle.dedisperse_subband(x[:, :nt + ref.overlap], ref, nt)
+    oracle.boxcar_peaks(yn, wl.widths)
+    oracle.boxcar_candidates(yn, wl.widths, wl.gamma)
+    dtn = time.perf_counter() - t
+    return {"value": ntrials * nt / dt, "unit": "DM-trial samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{ntrials} of {len(wl.dms)} DM trials ({k} coarse groups of {g}) x {nt} samples, "
+                      f"two-stage dedispersion + peaks + candidates, C oracle with {threads} OpenMP threads, "
+                      f"{dt:.1f} s",
+            "numpy_oracle_1core": g * nt / dtn}
 
 
 def place_pulses(plan, wl, synth):
