@@ -318,8 +318,13 @@ tx_status tx_candidates(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64_t p
 typedef struct tx_stream_s* tx_stream_t;
 
 /* Open a stream for blocks of at most max_block samples.  Allocates one
- * device buffer of nchan x (overlap + max_block) bytes (rows rounded up to
- * 256 bytes) on the plan's device; the first-stage scratch of standalone
+ * device buffer of nchan rows of overlap + max_block bytes (plus up to 15
+ * bytes so that the history always ends, and every block is written, at a
+ * 16-byte aligned byte; rows rounded up to 256 bytes) on the plan's device.
+ * Each push moves the kept history back by the block length (16-byte aligned
+ * destination; the source is aligned when the block length is a multiple of
+ * 16, which makes the device-to-device copies several times faster).  The
+ * first-stage scratch of standalone
  * pushes (tx_dedisperse_ws_size(max_block)) comes from the device's
  * stream-ordered pool on the first push that emits output, and stream jobs of
  * a batch use the batch's scratch instead.  Errors: TX_EINVAL, TX_ESTATE
@@ -413,14 +418,20 @@ tx_status tx_batch_add_stream(tx_batch_t b, tx_stream_t s, const uint8_t* block,
                               const tx_batch_boxcar* box);
 tx_status tx_batch_stream_output(tx_batch_t b, int32_t job, int64_t* nt_out);
 
-/* Declare, before the first launch, that up to `count` jobs of one launch
- * may use `plan` with at most max_nt output samples and at most nw boxcar
- * widths (0: no boxcar).  A graph captured later is sized for the sum of all
- * reservations (LDS, kernels and grids), so any later mix within them replays
- * without TX_ESTATE.  All reserved plans must use the same tile variants
- * (else TX_EINVAL); the first reserved plan's variants then apply to every
- * job.  Errors: TX_EINVAL, TX_ESTATE (plan on another device), TX_ENOTSUP
- * (capacity beyond 2^31 - 1 tiles). */
+/* Declare, before the first launch, that jobs may use `plan` with at most
+ * max_nt output samples and at most nw boxcar widths (0: no boxcar).  Once a
+ * plan is reserved, graphs are kept per size class: a launch of n jobs
+ * replays (capturing on first use) the graph of the class c = the next power
+ * of two >= n (at most max_jobs), whose kernels and LDS sizes are the union
+ * over all reservations and whose grids are c times the largest grid of one
+ * reserved job.  So every later launch whose jobs stay within the
+ * reservations replays without TX_ESTATE, and small launches replay small
+ * grids.  count (1..max_jobs) is checked but does not change the sizing,
+ * which already covers max_jobs jobs of the largest reservation.  All
+ * reserved plans must use the same tile variants (else TX_EINVAL); the first
+ * reserved plan's variants then apply to every job.  Errors: TX_EINVAL,
+ * TX_ESTATE (plan on another device), TX_ENOTSUP (capacity beyond 2^31 - 1
+ * tiles). */
 tx_status tx_batch_reserve(tx_batch_t b, tx_plan_t plan, int32_t nw, int64_t max_nt, int32_t count);
 
 /* Queue all jobs on `stream`.  The job table is uploaded on `stream` and the

@@ -56,6 +56,13 @@ struct Signature {            // what a captured graph bakes in
     int64_t g1 = 0, g2[kNIW] = {}, gb = 0;
 };
 
+struct GraphSlot {
+    int cap_jobs = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Signature sig;
+};
+
 }  // namespace
 
 struct tx_batch_s {
@@ -73,11 +80,11 @@ struct tx_batch_s {
     // first-stage series of every job of a launch
     void* scratch = nullptr;
     int64_t scratch_bytes = 0;
-    // graph
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    Signature sig;
-    // plans declared ahead of the first launch (tx_batch_reserve)
+    // captured graphs, one per size class (jobs per launch, a power of two,
+    // when plans were reserved; a single class otherwise)
+    std::vector<GraphSlot> graphs;
+    // plans declared ahead of the first launch (tx_batch_reserve): the union
+    // of their kernels and LDS sizes, and the largest grids of one job
     bool reserved = false;
     Signature floor;
     tx::Tiles tiles{};
@@ -85,11 +92,21 @@ struct tx_batch_s {
 
 namespace {
 
-void destroy_graph(tx_batch_s* b) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
+void destroy_graphs(tx_batch_s* b) {
+    for (GraphSlot& g : b->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    b->graphs.clear();
+}
+
+// Size class of a launch of n jobs: the next power of two (at most max_jobs)
+// when plans were reserved, so that small launches replay small grids.
+int size_class(const tx_batch_s* b, int n) {
+    if (!b->reserved) return b->max_jobs;
+    int c = 1;
+    while (c < n) c <<= 1;
+    return std::min(c, b->max_jobs);
 }
 
 tx_status fill_box(const tx_batch_boxcar* box, tx::BoxcarArgs* a) {
@@ -254,15 +271,18 @@ tx_status tx_batch_reserve(tx_batch_t b, tx_plan_t plan, int32_t nw, int64_t max
     f.lds2 = std::max(f.lds2, g.lds2);
     const int gi = iw_index(g.iw);
     f.groups[gi] = true;
-    f.g1 += count * tx::stage1_tiles(a1);
-    f.g2[gi] += count * tx::stage2_tiles(a2);
+    // grids of one job (a launch of n jobs is sized n times these)
+    f.g1 = std::max(f.g1, tx::stage1_tiles(a1));
+    f.g2[gi] = std::max(f.g2[gi], tx::stage2_tiles(a2));
     if (nw > 0) {
         f.any_box = true;
         f.nwt = std::max(f.nwt, tx::boxcar_nwt(nw));
         f.ldsb = std::max(f.ldsb, tx::boxcar_tmax_bytes(f.nwt, max_nt));
-        f.gb += static_cast<int64_t>(count) * plan->ndm;
+        f.gb = std::max<int64_t>(f.gb, plan->ndm);
     }
-    if (f.g1 > INT32_MAX || f.g2[gi] > INT32_MAX || f.gb > INT32_MAX) return TX_ENOTSUP;
+    const int64_t m = b->max_jobs;
+    if (f.g1 * m > INT32_MAX || f.g2[gi] * m > INT32_MAX || f.gb * m > INT32_MAX) return TX_ENOTSUP;
+    (void)count;
     b->floor = f;
     b->tiles = t;
     b->reserved = true;
@@ -337,9 +357,14 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
     for (const Job& j : b->jobs)
         if (j.has_box && j.nt_out > 0) ldsb = std::max(ldsb, tx::boxcar_tmax_bytes(sig.nwt, j.nt_out));
     const bool use_graph = (b->flags & TX_BATCH_GRAPH) && stream != nullptr;
-    if (use_graph && b->exec) {
+    const int cls = size_class(b, n);
+    GraphSlot* slot = nullptr;
+    if (use_graph)
+        for (GraphSlot& g : b->graphs)
+            if (g.cap_jobs == cls) slot = &g;
+    if (slot) {
         // A captured graph fixes the kernels, grids and LDS sizes.
-        Signature want = b->sig;
+        Signature want = slot->sig;
         bool fits = sig.s1 == want.s1 && sig.s2 == want.s2 && sig.lds1 <= want.lds1 && sig.lds2 <= want.lds2 &&
                     sig.nwt <= want.nwt && (!sig.any_box || want.any_box) && tot1 <= want.g1 && totb <= want.gb;
         for (int g = 0; g < kNIW; ++g)
@@ -348,10 +373,13 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
         sig = want;
     } else {
         // Direct launches use the exact grids.  A graph captured now is sized
-        // for the larger of the reserved capacity and this launch, with every
-        // stream job counted at its largest block.
-        const Signature& f = b->floor;
-        if (use_graph) {
+        // for its size class from the reserved plans (else for this launch,
+        // with every stream job counted at its largest block).
+        Signature f = b->floor;
+        f.g1 *= cls;
+        f.gb *= cls;
+        for (int g = 0; g < kNIW; ++g) f.g2[g] *= cls;
+        if (use_graph && !b->reserved) {
             int64_t c1 = 0, c2[kNIW] = {}, cb = 0;
             for (int k = 0; k < n; ++k) {
                 const Job& j = b->jobs[static_cast<size_t>(k)];
@@ -416,10 +444,13 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
         const tx::DedispGeom& g = geo[static_cast<size_t>(k)];
         tx::Stage1Args a1;
         tx::Stage2Args a2;
-        const uint8_t* in = j.stream ? j.stream->ring : j.in;
+        const uint8_t* in = j.in;
+        int x_off = 0;
+        if (j.stream) tx::stream_input(j.stream, &in, &x_off);
         const int64_t in_pitch = j.stream ? j.stream->pitch : j.in_pitch;
         uint16_t* ws = reinterpret_cast<uint16_t*>(static_cast<uint8_t*>(b->scratch) + scratch_off[static_cast<size_t>(k)]);
         tx::fill_stage_args(j.plan, g, in, in_pitch, j.nt_out, j.out, j.out_pitch, ws, &a1, &a2);
+        a1.x_off = x_off;
         a1.lds_bytes = sig.lds1;
         a2.lds_bytes = sig.lds2;
         h1[n1] = a1;
@@ -453,7 +484,10 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
 
     // Kernels.
     if (use_graph) {
-        if (!b->exec) {
+        if (!slot) {
+            GraphSlot ns;
+            ns.cap_jobs = cls;
+            ns.sig = sig;
             e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
                 const hipError_t ek = run_kernels(b, sig, stream);
@@ -461,19 +495,21 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
                 e = hipStreamEndCapture(stream, &g);
                 if (ek != hipSuccess) e = ek;
                 if (e == hipSuccess) {
-                    b->graph = g;
-                    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+                    ns.graph = g;
+                    e = hipGraphInstantiate(&ns.exec, g, nullptr, nullptr, 0);
                 } else if (g) {
                     (void)hipGraphDestroy(g);
                 }
             }
             if (e != hipSuccess) {
-                destroy_graph(b);
+                if (ns.exec) (void)hipGraphExecDestroy(ns.exec);
+                if (ns.graph) (void)hipGraphDestroy(ns.graph);
                 return tx::status_of(e);
             }
-            b->sig = sig;
+            b->graphs.push_back(ns);
+            slot = &b->graphs.back();
         }
-        e = hipGraphLaunch(b->exec, stream);
+        e = hipGraphLaunch(slot->exec, stream);
     } else {
         e = run_kernels(b, sig, stream);
     }
@@ -490,7 +526,7 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
 tx_status tx_batch_destroy(tx_batch_t b) {
     if (!b) return TX_OK;
     if (b->upload_pending) (void)hipEventSynchronize(b->uploaded);
-    destroy_graph(b);
+    destroy_graphs(b);
     if (b->scratch) {
         (void)hipDeviceSynchronize();
         (void)hipFreeAsync(b->scratch, nullptr);

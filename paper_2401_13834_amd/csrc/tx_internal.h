@@ -46,9 +46,10 @@ constexpr int kBoxPer = kBoxTile / kThreads;
 // Kernel arguments.
 // ---------------------------------------------------------------------------
 struct Stage1Args {
-    const uint8_t* x;       // input rows
+    const uint8_t* x;       // input rows (16-byte aligned)
     int64_t x_pitch;        // bytes between rows
-    int64_t x_len;          // valid samples per row (nt + overlap)
+    int64_t x_len;          // valid samples per row (nt + overlap), counted from x_off
+    int32_t x_off;          // first sample of every row at byte x_off (0..15) from x
     uint16_t* B;            // first-stage series [ngroups][nsub][B_pitch]
     int64_t B_pitch;        // elements per series (multiple of the time tile)
     const int32_t* dT;      // [nchan][gpad] D(c_j, f_ch), trial axis padded with the last group
@@ -149,8 +150,12 @@ struct tx_stream_s {
     int device = -1;
     int64_t max_block = 0;
     int64_t pitch = 0;                 // bytes per ring row (multiple of 256)
-    uint8_t* ring = nullptr;           // nchan rows: held history, then the new block
-    int64_t held = 0;                  // valid samples at the front of every row
+    // Ring row layout: [pad | history | new block].  The history always ends
+    // at byte pad + overlap, a multiple of 16, so every block is written
+    // 16-byte aligned and the history occupies [pad + overlap - held, pad + overlap).
+    uint8_t* ring = nullptr;
+    int64_t pad = 0;                   // (16 - overlap % 16) % 16
+    int64_t held = 0;                  // valid history samples of every row
     int64_t received = 0, emitted = 0;
     void* ws = nullptr;                // dedispersion scratch of standalone pushes (allocated on first use)
     int64_t ws_bytes = 0;
@@ -164,6 +169,9 @@ namespace tx {
 tx_status stream_ingest(tx_stream_s* s, const uint8_t* block, int64_t block_pitch, int64_t nt, int block_on_device,
                         hipStream_t st, int64_t* n_out);
 tx_status stream_advance(tx_stream_s* s, int64_t nt, hipStream_t st);
+// First history sample of every row: the 16-byte aligned base and the byte
+// offset (0..15) of that sample from it.
+void stream_input(const tx_stream_s* s, const uint8_t** base, int* x_off);
 tx_status check_out_args(const int32_t* d_out, int64_t out_pitch, int64_t nt);
 // Validate a width list and fill widths, 1/sqrt(w), nw and the longest width <= nt.
 tx_status boxcar_widths(const int32_t* widths, int32_t nw, int64_t nt, BoxcarArgs* a);
@@ -195,9 +203,9 @@ struct DedispGeom {
     bool ok;                // false if some workgroup cannot fit its LDS rows
 };
 DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want);
-hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in,
-                             int64_t in_pitch, int64_t nt, int32_t* d_out, int64_t out_pitch,
-                             uint16_t* d_B, hipStream_t stream);
+hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in, int64_t in_pitch,
+                             int64_t nt, int32_t* d_out, int64_t out_pitch, uint16_t* d_B, hipStream_t stream,
+                             int x_off = 0);
 hipError_t launch_boxcar(const BoxcarArgs& a, hipStream_t stream);
 
 // Batch building blocks (tx_kernels_dedisp.hip, tx_kernels_boxcar.hip).

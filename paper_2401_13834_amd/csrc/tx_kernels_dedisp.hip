@@ -99,11 +99,14 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
     const TX_GLOBAL int32_t* __restrict__ dT = to_global(a.dT);
     const size_t gp = static_cast<size_t>(a.gpad);
 
-    // Largest shift (from the 16-byte aligned row start) in this workgroup.
+    // Every row starts at byte x_off of its 16-byte aligned base, so shifts
+    // are D + x_off from the base.  Largest shift (from the 16-byte aligned
+    // staging start) in this workgroup:
+    const int xo = a.x_off;
     int sp = 0;
     for (int c = tid; c < a.m; c += kThreads) {
         const TX_GLOBAL int32_t* r = dT + static_cast<size_t>(ch0 + c) * gp;
-        sp = max(sp, r[jl] - (r[j0] & ~15));
+        sp = max(sp, (r[jl] + xo) - ((r[j0] + xo) & ~15));
     }
     sp = block_max(sp, red);
     const int W = ((sp >> 2) + 64 * Q + 1 + 3) & ~3;      // dwords per staged row
@@ -124,15 +127,15 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
         for (int t = tid; t < nc * J; t += kThreads) {
             const int c = t / J, k = t - c * J;
             const TX_GLOBAL int32_t* r = dT + static_cast<size_t>(ch0 + cb + c) * gp;
-            const int sh = r[min(j0 + k, jl)] - (r[j0] & ~15);
+            const int sh = (r[min(j0 + k, jl)] + xo) - ((r[j0] + xo) & ~15);
             tab[t] = c * rowbytes + sh;          // word offset (sh & ~3) plus byte shift (sh & 3)
         }
         // Rows: wave w stages rows w, w + 4, ...
         for (int c = wave; c < nc; c += kWaves) {
             const int ch = ch0 + cb + c;
-            const int64_t start = static_cast<int64_t>(u0) + (dT[static_cast<size_t>(ch) * gp + j0] & ~15);
+            const int64_t start = static_cast<int64_t>(u0) + ((dT[static_cast<size_t>(ch) * gp + j0] + xo) & ~15);
             const TX_GLOBAL uint8_t* row = to_global(a.x) + static_cast<size_t>(ch) * a.x_pitch + start;
-            const int64_t avail_b = a.x_len - start;
+            const int64_t avail_b = a.x_len + xo - start;
             uint32_t* dst = reinterpret_cast<uint32_t*>(dat + c * rowbytes);
             for (int i = lane; 4 * i < W; i += 64) {
                 uint32_t d[5];
@@ -578,6 +581,7 @@ void fill_stage_args(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d
     s1->x = d_in;
     s1->x_pitch = in_pitch;
     s1->x_len = nt + p->overlap;
+    s1->x_off = 0;
     s1->B = d_B;
     s1->B_pitch = geo.B_pitch;
     s1->dT = p->d_dT;
@@ -611,11 +615,13 @@ int64_t stage1_tiles(const Stage1Args& a) { return static_cast<int64_t>(a.nsub) 
 int64_t stage2_tiles(const Stage2Args& a) { return static_cast<int64_t>(a.ngroups) * a.n_ichunks * a.n_ttiles; }
 
 hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in, int64_t in_pitch,
-                             int64_t nt, int32_t* d_out, int64_t out_pitch, uint16_t* d_B, hipStream_t stream) {
-    if (!geo.ok) return hipErrorInvalidValue;
+                             int64_t nt, int32_t* d_out, int64_t out_pitch, uint16_t* d_B, hipStream_t stream,
+                             int x_off) {
+    if (!geo.ok || x_off < 0 || x_off > 15) return hipErrorInvalidValue;
     Stage1Args s1;
     Stage2Args s2;
     fill_stage_args(p, geo, d_in, in_pitch, nt, d_out, out_pitch, d_B, &s1, &s2);
+    s1.x_off = x_off;
     void* a1[] = {&s1};
     int prof = prof_begin(TX_KERNEL_STAGE1, stream);
     hipError_t e = launch(kS1Fn[geo.tiles.s1].single, static_cast<int>(stage1_tiles(s1)), s1.lds_bytes, a1, stream);

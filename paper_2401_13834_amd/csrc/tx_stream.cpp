@@ -13,7 +13,9 @@ tx_status stream_ingest(tx_stream_s* s, const uint8_t* block, int64_t block_pitc
     const tx_plan_s* p = s->plan;
     if (nt < 1 || nt > s->max_block || !block || block_pitch < nt || !n_out) return TX_EINVAL;
     const hipMemcpyKind kind = block_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    hipError_t e = hipMemcpy2DAsync(s->ring + s->held, static_cast<size_t>(s->pitch), block,
+    // The block goes right behind the history, at the 16-byte aligned byte
+    // pad + overlap of every row.
+    hipError_t e = hipMemcpy2DAsync(s->ring + s->pad + p->overlap, static_cast<size_t>(s->pitch), block,
                                     static_cast<size_t>(block_pitch), static_cast<size_t>(nt),
                                     static_cast<size_t>(p->nchan), kind, st);
     if (e != hipSuccess) return status_of(e);
@@ -21,45 +23,56 @@ tx_status stream_ingest(tx_stream_s* s, const uint8_t* block, int64_t block_pitc
     return TX_OK;
 }
 
+void stream_input(const tx_stream_s* s, const uint8_t** base, int* x_off) {
+    const int64_t first = s->pad + s->plan->overlap - s->held;
+    *base = s->ring + (first & ~int64_t(15));
+    *x_off = static_cast<int>(first & 15);
+}
+
 tx_status stream_advance(tx_stream_s* s, int64_t nt, hipStream_t st) {
     const int64_t O = s->plan->overlap;
     const int64_t have = s->held + nt;
     const int64_t n_out = std::max<int64_t>(0, have - O);
-    if (have > O && O > 0) {
-        // Move the last O samples of every row to the front (the paper's
-        // "shift data").  Source and destination overlap when the shift d is
-        // below O: then copy forward in pieces no wider than d, so no piece
-        // overwrites a source byte that a later piece still has to read, or,
-        // for many pieces, through a transient buffer from the stream-ordered
-        // pool.
-        const int64_t d = have - O;
+    const int64_t keep = std::min(have, O);
+    if (keep > 0) {
+        // Move the last `keep` samples of every row back by nt, so that the
+        // history ends at pad + O again (the paper's "shift data").  The copy
+        // is widened at its front to a multiple of 16 bytes, so its
+        // destination starts 16-byte aligned (the extra bytes precede the
+        // history and are never read).  Source and destination overlap when
+        // the shift is below the width: then copy forward in pieces no wider
+        // than the shift, so no piece overwrites a source byte that a later
+        // piece still reads, or, for many pieces, through a transient buffer
+        // from the stream-ordered pool.
+        const int64_t end = s->pad + O;
+        const int64_t w = (keep + 15) & ~int64_t(15);
+        uint8_t* dst = s->ring + (end - w);
+        const uint8_t* src = s->ring + (end + nt - w);
         const size_t rows = static_cast<size_t>(s->plan->nchan);
         const size_t pitch = static_cast<size_t>(s->pitch);
-        if ((O + d - 1) / d <= 8) {
-            for (int64_t x = 0; x < O; x += d) {
-                const int64_t w = std::min(d, O - x);
-                hipError_t e = hipMemcpy2DAsync(s->ring + x, pitch, s->ring + d + x, pitch, static_cast<size_t>(w),
-                                                rows, hipMemcpyDeviceToDevice, st);
+        if (nt >= w || (w + nt - 1) / nt <= 8) {
+            for (int64_t x = 0; x < w; x += nt) {
+                const int64_t pw = std::min(nt, w - x);
+                hipError_t e = hipMemcpy2DAsync(dst + x, pitch, src + x, pitch, static_cast<size_t>(pw), rows,
+                                                hipMemcpyDeviceToDevice, st);
                 if (e != hipSuccess) return status_of(e);
             }
         } else {
             void* tmp = nullptr;
-            hipError_t e = hipMallocAsync(&tmp, static_cast<size_t>(O) * rows, st);
+            hipError_t e = hipMallocAsync(&tmp, static_cast<size_t>(w) * rows, st);
             if (e != hipSuccess) return status_of(e);
             uint8_t* t = static_cast<uint8_t*>(tmp);
-            e = hipMemcpy2DAsync(t, static_cast<size_t>(O), s->ring + d, pitch, static_cast<size_t>(O), rows,
+            e = hipMemcpy2DAsync(t, static_cast<size_t>(w), src, pitch, static_cast<size_t>(w), rows,
                                  hipMemcpyDeviceToDevice, st);
             if (e == hipSuccess)
-                e = hipMemcpy2DAsync(s->ring, pitch, t, static_cast<size_t>(O), static_cast<size_t>(O), rows,
+                e = hipMemcpy2DAsync(dst, pitch, t, static_cast<size_t>(w), static_cast<size_t>(w), rows,
                                      hipMemcpyDeviceToDevice, st);
             const hipError_t ef = hipFreeAsync(tmp, st);
             if (e == hipSuccess) e = ef;
             if (e != hipSuccess) return status_of(e);
         }
-        s->held = O;
-    } else {
-        s->held = std::min(have, O);
     }
+    s->held = keep;
     s->received += nt;
     s->emitted += n_out;
     return TX_OK;
@@ -93,7 +106,8 @@ tx_status tx_stream_open(tx_plan_t plan, int64_t max_block, tx_stream_t* out) {
     s->plan = plan;
     s->device = dev;
     s->max_block = max_block;
-    s->pitch = (plan->overlap + max_block + 255) / 256 * 256;
+    s->pad = (16 - plan->overlap % 16) % 16;
+    s->pitch = (s->pad + plan->overlap + max_block + 255) / 256 * 256;
     const size_t bytes = static_cast<size_t>(s->pitch) * plan->nchan;
     const hipError_t e = hipMalloc(reinterpret_cast<void**>(&s->ring), bytes);
     if (e != hipSuccess) {
@@ -128,8 +142,11 @@ tx_status tx_stream_push(tx_stream_t s, const uint8_t* block, int64_t block_pitc
             if (e != hipSuccess) return tx::status_of(e);
             s->ws_bytes = want;
         }
-        const hipError_t e = tx::launch_dedisperse(s->plan, geo, s->ring, s->pitch, n_out, d_out, out_pitch,
-                                                   static_cast<uint16_t*>(s->ws), stream);
+        const uint8_t* base = nullptr;
+        int x_off = 0;
+        tx::stream_input(s, &base, &x_off);
+        const hipError_t e = tx::launch_dedisperse(s->plan, geo, base, s->pitch, n_out, d_out, out_pitch,
+                                                   static_cast<uint16_t*>(s->ws), stream, x_off);
         if (e != hipSuccess) return tx::status_of(e);
     }
     st = tx::stream_advance(s, nt, stream);
@@ -157,7 +174,8 @@ tx_status tx_stream_snapshot(tx_stream_t s, uint8_t* host_hist, int64_t* held, i
                              hipStream_t stream) {
     if (!s || !held || !received || !emitted || (s->held > 0 && !host_hist)) return TX_EINVAL;
     if (s->held > 0) {
-        hipError_t e = hipMemcpy2DAsync(host_hist, static_cast<size_t>(s->held), s->ring,
+        const int64_t first = s->pad + s->plan->overlap - s->held;
+        hipError_t e = hipMemcpy2DAsync(host_hist, static_cast<size_t>(s->held), s->ring + first,
                                         static_cast<size_t>(s->pitch), static_cast<size_t>(s->held),
                                         static_cast<size_t>(s->plan->nchan), hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -175,7 +193,8 @@ tx_status tx_stream_restore(tx_stream_t s, const uint8_t* host_hist, int64_t hel
         return TX_EINVAL;
     if (received != emitted + held) return TX_EINVAL;
     if (held > 0) {
-        hipError_t e = hipMemcpy2DAsync(s->ring, static_cast<size_t>(s->pitch), host_hist,
+        const int64_t first = s->pad + s->plan->overlap - held;
+        hipError_t e = hipMemcpy2DAsync(s->ring + first, static_cast<size_t>(s->pitch), host_hist,
                                         static_cast<size_t>(held), static_cast<size_t>(held),
                                         static_cast<size_t>(s->plan->nchan), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
