@@ -115,6 +115,39 @@ def place_pulses(plan, wl, synth):
     return out
 
 
+def transpose_leg(torch, tx, nchan, nt, overlap, launches=20):
+    """Time-major ingest: one recorded block (nt rows of nchan channel bytes)
+    transposed into the channel rows of a stream buffer, at the position a
+    block lands (after the overlap), timed per launch with HIP events.  Pure
+    data movement: bytes = read + write of the block, against HBM peak."""
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    d_tf = torch.randint(0, 256, (nt, nchan), dtype=torch.uint8, device="cuda", generator=gen)
+    off = (overlap + 15) // 16 * 16
+    pitch = (off + nt + 255) // 256 * 256
+    ring = torch.empty((nchan, pitch), dtype=torch.uint8, device="cuda")
+    dst = ring[:, off:]
+    for _ in range(3):
+        tx.tx_transpose_tf(d_tf, nchan, nt, dst)
+    torch.cuda.synchronize()
+    tx.tx_profile_collect(tx.TX_KERNEL_TRANSPOSE)
+    tx.tx_profile_enable(True)
+    for _ in range(launches):
+        tx.tx_transpose_tf(d_tf, nchan, nt, dst)
+    torch.cuda.synchronize()
+    tx.tx_profile_enable(False)
+    ms, n = tx.tx_profile_collect(tx.TX_KERNEL_TRANSPOSE)
+    avg = ms / max(n, 1)
+    ok = bool(torch.equal(ring[:, off:off + nt], d_tf.t()))
+    nbytes = 2 * nchan * nt
+    del d_tf, ring
+    torch.cuda.empty_cache()
+    return {"workload": f"one block as recorded, {nt} samples x {nchan} channels (uint8, time-major), "
+                        f"into channel rows behind a {overlap}-sample history",
+            "bytes_per_launch": nbytes, "avg_ms": avg, "launches": n,
+            "achieved_GBps": nbytes / (avg * 1e-3) / 1e9, "peak_GBps": 8000.0,
+            "frac": nbytes / (avg * 1e-3) / 8e12, "matches_torch_transpose": ok}
+
+
 def batched_leg(torch, tx, synth, steps):
     """64 beams of uneven shape (channels 1024-4096, blocks 16384-65536, 512-4096
     DM trials up to DM 3000, sub-band count chosen by each plan) dedispersed
@@ -247,6 +280,7 @@ def main():
                     help="source:speed:blocks-per-beam of the served runs (source host or device)")
     ap.add_argument("--served-lanes", type=int, default=2)
     ap.add_argument("--served-slots", type=int, default=32)
+    ap.add_argument("--no-transpose", action="store_true", help="skip the time-major ingest leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy the DM x time array once (a plain copy of known size "
                          "whose HBM counters scale the kernels' counters)")
@@ -345,6 +379,9 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     tx.tx_pool_trim()
+    if not args.no_transpose:
+        out["transpose"] = transpose_leg(torch, tx, nchan, nt, plan.overlap)
+        print(f"transpose: {json.dumps(out['transpose'])}", file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = batched_leg(torch, tx, synth, args.batched_steps)
         print(f"batched: {json.dumps(out['batched'])}", file=sys.stderr, flush=True)

@@ -201,6 +201,27 @@ tx_status tx_dedisperse_ws(tx_plan_t plan, const uint8_t* d_in, int64_t in_pitch
                            hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* Time-major ingest (Sec. 2.3, Fig. "dedispersion_flow", "transpose" step)  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * tx_transpose_tf: channel rows from a time-major block, as recorded (one
+ * row of nchan channel bytes per time sample).
+ *
+ *   d_tf      uint8, nt rows; row t starts at d_tf + t*tf_pitch and holds the
+ *             nchan channel samples of time t (tf_pitch >= nchan).
+ *   d_ft      uint8, nchan rows; row c starts at d_ft + c*ft_pitch and
+ *             receives d_ft[c][t] = d_tf[t][c] for t < nt (ft_pitch >= nt);
+ *             bytes past nt are untouched.
+ *   d_tf, d_ft, tf_pitch and ft_pitch must be multiples of 16.
+ *
+ * Pure data movement (every byte read and written once), asynchronous on
+ * `stream`.  Errors: TX_EINVAL, TX_EDEVICE.
+ */
+tx_status tx_transpose_tf(const uint8_t* d_tf, int64_t tf_pitch, int32_t nchan, int64_t nt, uint8_t* d_ft,
+                          int64_t ft_pitch, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* Tile shapes (choices of the kernel implementation; results never change)  */
 /* ------------------------------------------------------------------------ */
 
@@ -344,6 +365,20 @@ tx_status tx_stream_push(tx_stream_t s, const uint8_t* block, int64_t block_pitc
                          int32_t block_on_device, int32_t* d_out, int64_t out_pitch, int64_t* nt_out,
                          hipStream_t stream);
 
+/*
+ * tx_stream_push for a time-major block: nt rows of the plan's nchan channel
+ * bytes, row t at block + t*block_pitch (block_pitch >= nchan; a device block
+ * and its pitch must be multiples of 16).  The block is transposed
+ * (tx_transpose_tf) straight into the stream's buffer; a host block is first
+ * copied to a device staging buffer of max_block x nchan bytes (rounded up to
+ * 16), taken from the device's stream-ordered pool on the first such push and
+ * kept until close.  Outputs, ordering and errors are those of
+ * tx_stream_push.
+ */
+tx_status tx_stream_push_tf(tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt,
+                            int32_t block_on_device, int32_t* d_out, int64_t out_pitch, int64_t* nt_out,
+                            hipStream_t stream);
+
 /* Samples received and output samples emitted since open / reset. */
 tx_status tx_stream_position(tx_stream_t s, int64_t* received, int64_t* emitted);
 
@@ -416,6 +451,10 @@ tx_status tx_batch_add(tx_batch_t b, tx_plan_t plan, const uint8_t* d_in, int64_
 tx_status tx_batch_add_stream(tx_batch_t b, tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt,
                               int32_t block_on_device, int32_t* d_out, int64_t out_pitch,
                               const tx_batch_boxcar* box);
+/* tx_batch_add_stream for a time-major block (as tx_stream_push_tf). */
+tx_status tx_batch_add_stream_tf(tx_batch_t b, tx_stream_t s, const uint8_t* block, int64_t block_pitch,
+                                 int64_t nt, int32_t block_on_device, int32_t* d_out, int64_t out_pitch,
+                                 const tx_batch_boxcar* box);
 tx_status tx_batch_stream_output(tx_batch_t b, int32_t job, int64_t* nt_out);
 
 /* Declare, before the first launch, that jobs may use `plan` with at most
@@ -453,7 +492,8 @@ typedef enum tx_kernel {
     TX_KERNEL_STAGE1 = 0,   /* first stage: sub-bands at the coarse DMs */
     TX_KERNEL_STAGE2 = 1,   /* second stage: fine DMs from the sub-band series */
     TX_KERNEL_BOXCAR = 2,   /* boxcar S/N, peaks and candidates */
-    TX_KERNEL_COUNT = 3
+    TX_KERNEL_TRANSPOSE = 3, /* time-major to channel-major ingest */
+    TX_KERNEL_COUNT = 4
 } tx_kernel;
 
 /*

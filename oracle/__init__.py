@@ -10,6 +10,8 @@ It is a plain, slow, obviously correct restatement of what the paper
 computes on its hot path:
 
 * the cold-plasma delay (Sec. 2.3, Eq. 1) turned into integer sample delays;
+* the "transpose" of time-major blocks into channel rows (Sec. 2.3,
+  Fig. "dedispersion_flow");
 * brute-force dedispersion (Sec. 2.3, the O(N_DM N_t N_f) method);
 * two-stage sub-band dedispersion (Sec. 2.3: coarse DM grid per sub-band,
   then the fine DM grid over the sub-banded series; Fig. "subband");
@@ -32,6 +34,7 @@ from .ref import (  # noqa: F401
     Plan,
     make_plan,
     group_size_rule,
+    channel_rows,
     dedisperse_brute,
     subband_stage1,
     subband_stage2,

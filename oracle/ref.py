@@ -170,6 +170,17 @@ def _check_input(x, nchan, need):
         raise ValueError(f"input must be [{nchan}, >= {need}], got {x.shape}")
 
 
+def channel_rows(x_tf, nchan):
+    """The "transpose" step of the dedispersion data flow (Sec. 2.3, Fig.
+    "dedispersion_flow"): a block recorded time-major, one row of channel
+    samples per time sample, as the channel rows every dedispersion function
+    here takes: out[ch][t] = x_tf[t][ch] for ch < nchan."""
+    x_tf = np.asarray(x_tf)
+    if x_tf.ndim != 2 or x_tf.shape[1] < nchan:
+        raise ValueError(f"time-major input must be [nt, >= {nchan}], got {x_tf.shape}")
+    return np.ascontiguousarray(x_tf[:, :nchan].T)
+
+
 def dedisperse_brute(x, freqs, tsamp, dms, nt):
     """Brute-force dedispersion (Sec. 2.3):
     Y[i][t] = sum over channels of x[ch][t + D(dm_i, f_ch)], t in [0, nt)."""

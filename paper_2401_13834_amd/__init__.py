@@ -93,7 +93,7 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_int64)]),
 }
 
-TX_KERNEL_STAGE1, TX_KERNEL_STAGE2, TX_KERNEL_BOXCAR = 0, 1, 2
+TX_KERNEL_STAGE1, TX_KERNEL_STAGE2, TX_KERNEL_BOXCAR, TX_KERNEL_TRANSPOSE = 0, 1, 2, 3
 
 
 def lib():
@@ -238,6 +238,13 @@ def tx_dedisperse(plan, d_in, nt, d_out, stream=None, ws=None):
     _check(st, "tx_dedisperse")
 
 
+def tx_transpose_tf(d_tf, nchan, nt, d_ft, stream=None):
+    """d_tf: uint8 device tensor [>= nt, >= nchan] (time-major); d_ft: uint8
+    device tensor [>= nchan, >= nt] receiving d_ft[c, t] = d_tf[t, c]."""
+    _check(lib().tx_transpose_tf(_ptr(d_tf), d_tf.stride(0) * d_tf.element_size(), int(nchan), int(nt), _ptr(d_ft),
+                                 d_ft.stride(0) * d_ft.element_size(), _stream(stream)), "tx_transpose_tf")
+
+
 def _widths(widths):
     w = np.ascontiguousarray(widths, dtype=np.int32)
     return w, w.ctypes.data_as(_c_i32p)
@@ -312,6 +319,11 @@ _SIGS2 = {
     "tx_stream_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "tx_stream_push_tf": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "tx_transpose_tf": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "tx_stream_position": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                           ctypes.POINTER(ctypes.c_int64)]),
     "tx_stream_reset": (ctypes.c_int, [ctypes.c_void_p]),
@@ -329,6 +341,9 @@ _SIGS2 = {
     "tx_batch_add_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                            ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                            ctypes.POINTER(BatchBoxcar)]),
+    "tx_batch_add_stream_tf": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                              ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                              ctypes.POINTER(BatchBoxcar)]),
     "tx_batch_stream_output": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "tx_batch_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                         ctypes.c_int32]),
@@ -376,6 +391,16 @@ class Stream:
         _check(lib().tx_stream_push(self._h, _ptr(block), block.stride(0) * block.element_size(), int(nt), on_dev,
                                     _ptr(d_out), d_out.stride(0), ctypes.byref(n), _stream(stream)),
                "tx_stream_push")
+        return n.value
+
+    def push_tf(self, block, nt, d_out, stream=None):
+        """block: time-major uint8 tensor [>= nt, >= nchan] (one row of channels
+        per time sample) on the device or in (pinned) host memory."""
+        on_dev = 1 if block.is_cuda else 0
+        n = ctypes.c_int64()
+        _check(lib().tx_stream_push_tf(self._h, _ptr(block), block.stride(0) * block.element_size(), int(nt), on_dev,
+                                       _ptr(d_out), d_out.stride(0), ctypes.byref(n), _stream(stream)),
+               "tx_stream_push_tf")
         return n.value
 
     def position(self):
@@ -450,6 +475,16 @@ class Batch:
                                          block.stride(0) * block.element_size(), int(nt),
                                          1 if block.is_cuda else 0, _ptr(d_out), d_out.stride(0),
                                          None if bx is None else ctypes.byref(bx)), "tx_batch_add_stream")
+
+    def add_stream_tf(self, stream_obj, block, nt, d_out, widths=None, gamma=6.0, peaks=None, cands=None,
+                      count=None):
+        """add_stream for a time-major block [>= nt, >= nchan]."""
+        bx, w = _box(widths, gamma, peaks, cands, count)
+        self._keep.append(w)
+        _check(lib().tx_batch_add_stream_tf(self._h, stream_obj.handle, _ptr(block),
+                                            block.stride(0) * block.element_size(), int(nt),
+                                            1 if block.is_cuda else 0, _ptr(d_out), d_out.stride(0),
+                                            None if bx is None else ctypes.byref(bx)), "tx_batch_add_stream_tf")
 
     def reserve(self, plan, nw, max_nt, count=1):
         """Size a graph captured later for ``count`` jobs of ``plan`` with up to

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libtx.so")
 PEAKS = os.path.join(HERE, "tx_peaks")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["tx_kernels_dedisp.hip", "tx_kernels_boxcar.hip"]
+HIP_SOURCES = ["tx_kernels_dedisp.hip", "tx_kernels_boxcar.hip", "tx_kernels_transpose.hip"]
 HOST_SOURCES = ["tx_plan.cpp", "tx_api.cpp", "tx_profile.cpp", "tx_stream.cpp", "tx_batch.cpp", "tx_autotune.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-result"]

@@ -296,6 +296,16 @@ tx_status tx_dedisperse(tx_plan_t p, const uint8_t* d_in, int64_t in_pitch, int6
     return from_hip(f);
 }
 
+tx_status tx_transpose_tf(const uint8_t* d_tf, int64_t tf_pitch, int32_t nchan, int64_t nt, uint8_t* d_ft,
+                          int64_t ft_pitch, hipStream_t stream) {
+    if (nchan < 1 || nt < 0 || nt > (int64_t(1) << 40) || tf_pitch < nchan || ft_pitch < nt) return TX_EINVAL;
+    if (nt == 0) return TX_OK;
+    if (!d_tf || !d_ft || (reinterpret_cast<uintptr_t>(d_tf) & 15) || (reinterpret_cast<uintptr_t>(d_ft) & 15) ||
+        (tf_pitch & 15) || (ft_pitch & 15))
+        return TX_EINVAL;
+    return from_hip(tx::launch_transpose_tf(d_tf, tf_pitch, nchan, nt, d_ft, ft_pitch, stream));
+}
+
 tx_status tx_tile_variants(int32_t stage, int32_t* count) {
     if (!count || (stage != 1 && stage != 2)) return TX_EINVAL;
     *count = stage == 1 ? tx::stage1_variant_count() : tx::stage2_variant_count();

@@ -27,6 +27,7 @@ struct Job {
     int64_t in_pitch = 0;
     int64_t nt = 0;                    // output samples (device job) / pushed samples (stream job)
     int block_on_device = 1;
+    bool time_major = false;           // stream job: the block is [nt][nchan] (transposed on ingest)
     int32_t* out = nullptr;
     int64_t out_pitch = 0;
     bool has_box = false;
@@ -222,15 +223,17 @@ tx_status tx_batch_add(tx_batch_t b, tx_plan_t plan, const uint8_t* d_in, int64_
     return TX_OK;
 }
 
-tx_status tx_batch_add_stream(tx_batch_t b, tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt,
-                              int32_t block_on_device, int32_t* d_out, int64_t out_pitch,
-                              const tx_batch_boxcar* box) {
+static tx_status add_stream_job(tx_batch_t b, tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt,
+                                int32_t block_on_device, bool time_major, int32_t* d_out, int64_t out_pitch,
+                                const tx_batch_boxcar* box) {
     if (!b || !s || !block) return TX_EINVAL;
     if (static_cast<int>(b->jobs.size()) >= b->max_jobs) return TX_EINVAL;
     if (s->device != b->device) return TX_ESTATE;
     for (const Job& o : b->jobs)
         if (o.stream == s) return TX_EINVAL;
-    if (nt < 1 || nt > s->max_block || block_pitch < nt) return TX_EINVAL;
+    if (nt < 1 || nt > s->max_block || block_pitch < (time_major ? s->plan->nchan : nt)) return TX_EINVAL;
+    if (time_major && block_on_device && ((reinterpret_cast<uintptr_t>(block) & 15) || (block_pitch & 15)))
+        return TX_EINVAL;
     tx_status st = tx::check_out_args(d_out, out_pitch, nt);
     if (st != TX_OK) return st;
     Job j;
@@ -240,6 +243,7 @@ tx_status tx_batch_add_stream(tx_batch_t b, tx_stream_t s, const uint8_t* block,
     j.in_pitch = block_pitch;
     j.nt = nt;
     j.block_on_device = block_on_device ? 1 : 0;
+    j.time_major = time_major;
     j.out = d_out;
     j.out_pitch = out_pitch;
     if (box) {
@@ -250,6 +254,18 @@ tx_status tx_batch_add_stream(tx_batch_t b, tx_stream_t s, const uint8_t* block,
     }
     b->jobs.push_back(j);
     return TX_OK;
+}
+
+tx_status tx_batch_add_stream(tx_batch_t b, tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt,
+                              int32_t block_on_device, int32_t* d_out, int64_t out_pitch,
+                              const tx_batch_boxcar* box) {
+    return add_stream_job(b, s, block, block_pitch, nt, block_on_device, false, d_out, out_pitch, box);
+}
+
+tx_status tx_batch_add_stream_tf(tx_batch_t b, tx_stream_t s, const uint8_t* block, int64_t block_pitch,
+                                 int64_t nt, int32_t block_on_device, int32_t* d_out, int64_t out_pitch,
+                                 const tx_batch_boxcar* box) {
+    return add_stream_job(b, s, block, block_pitch, nt, block_on_device, true, d_out, out_pitch, box);
 }
 
 tx_status tx_batch_reserve(tx_batch_t b, tx_plan_t plan, int32_t nw, int64_t max_nt, int32_t count) {
@@ -313,7 +329,9 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
         j.nt_out = j.nt;
         if (j.stream) {
             int64_t n_out = 0;
-            const tx_status st = tx::stream_ingest(j.stream, j.in, j.in_pitch, j.nt, j.block_on_device, stream, &n_out);
+            const tx_status st =
+                j.time_major ? tx::stream_ingest_tf(j.stream, j.in, j.in_pitch, j.nt, j.block_on_device, stream, &n_out)
+                             : tx::stream_ingest(j.stream, j.in, j.in_pitch, j.nt, j.block_on_device, stream, &n_out);
             if (st != TX_OK) return st;
             j.nt_out = n_out;
         }

@@ -159,6 +159,8 @@ struct tx_stream_s {
     int64_t received = 0, emitted = 0;
     void* ws = nullptr;                // dedispersion scratch of standalone pushes (allocated on first use)
     int64_t ws_bytes = 0;
+    uint8_t* stage = nullptr;          // device copy of a time-major host block (allocated on first use)
+    int64_t stage_pitch = 0;           // bytes per staged time row (nchan rounded up to 16)
 };
 
 namespace tx {
@@ -169,6 +171,11 @@ namespace tx {
 tx_status stream_ingest(tx_stream_s* s, const uint8_t* block, int64_t block_pitch, int64_t nt, int block_on_device,
                         hipStream_t st, int64_t* n_out);
 tx_status stream_advance(tx_stream_s* s, int64_t nt, hipStream_t st);
+// As stream_ingest, for a time-major block (nt rows of nchan channel bytes):
+// transposed into the stream's buffer, through the stream's staging buffer
+// when the block is in host memory.
+tx_status stream_ingest_tf(tx_stream_s* s, const uint8_t* block, int64_t block_pitch, int64_t nt,
+                           int block_on_device, hipStream_t st, int64_t* n_out);
 // First history sample of every row: the 16-byte aligned base and the byte
 // offset (0..15) of that sample from it.
 void stream_input(const tx_stream_s* s, const uint8_t** base, int* x_off);
@@ -203,6 +210,10 @@ struct DedispGeom {
     bool ok;                // false if some workgroup cannot fit its LDS rows
 };
 DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want);
+// Time-major [nt][tf_pitch] -> channel-major [nchan][ft_pitch] uint8
+// (tx_kernels_transpose.hip); pointers and pitches multiples of 16.
+hipError_t launch_transpose_tf(const uint8_t* d_tf, int64_t tf_pitch, int32_t nchan, int64_t nt, uint8_t* d_ft,
+                               int64_t ft_pitch, hipStream_t stream);
 hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in, int64_t in_pitch,
                              int64_t nt, int32_t* d_out, int64_t out_pitch, uint16_t* d_B, hipStream_t stream,
                              int x_off = 0);

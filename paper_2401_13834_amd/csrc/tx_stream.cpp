@@ -23,6 +23,39 @@ tx_status stream_ingest(tx_stream_s* s, const uint8_t* block, int64_t block_pitc
     return TX_OK;
 }
 
+tx_status stream_ingest_tf(tx_stream_s* s, const uint8_t* block, int64_t block_pitch, int64_t nt,
+                           int block_on_device, hipStream_t st, int64_t* n_out) {
+    const tx_plan_s* p = s->plan;
+    if (nt < 1 || nt > s->max_block || !block || block_pitch < p->nchan || !n_out) return TX_EINVAL;
+    const uint8_t* src = block;
+    int64_t src_pitch = block_pitch;
+    if (block_on_device) {
+        if ((reinterpret_cast<uintptr_t>(block) & 15) || (block_pitch & 15)) return TX_EINVAL;
+    } else {
+        if (!s->stage) {
+            // Sized for the largest block; kept until close.
+            const tx_status rp = retain_pool(s->device);
+            if (rp != TX_OK) return rp;
+            const int64_t sp = (static_cast<int64_t>(p->nchan) + 15) / 16 * 16;
+            void* m = nullptr;
+            const hipError_t e = hipMallocAsync(&m, static_cast<size_t>(sp * s->max_block), st);
+            if (e != hipSuccess) return status_of(e);
+            s->stage = static_cast<uint8_t*>(m);
+            s->stage_pitch = sp;
+        }
+        const hipError_t e = hipMemcpy2DAsync(s->stage, static_cast<size_t>(s->stage_pitch), block,
+                                              static_cast<size_t>(block_pitch), static_cast<size_t>(p->nchan),
+                                              static_cast<size_t>(nt), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return status_of(e);
+        src = s->stage;
+        src_pitch = s->stage_pitch;
+    }
+    const hipError_t e = launch_transpose_tf(src, src_pitch, p->nchan, nt, s->ring + s->pad + p->overlap, s->pitch, st);
+    if (e != hipSuccess) return status_of(e);
+    *n_out = std::max<int64_t>(0, s->held + nt - p->overlap);
+    return TX_OK;
+}
+
 void stream_input(const tx_stream_s* s, const uint8_t** base, int* x_off) {
     const int64_t first = s->pad + s->plan->overlap - s->held;
     *base = s->ring + (first & ~int64_t(15));
@@ -81,10 +114,11 @@ tx_status stream_advance(tx_stream_s* s, int64_t nt, hipStream_t st) {
 }  // namespace tx
 
 static void free_stream(tx_stream_s* s) {
-    if (s->ring || s->ws) (void)hipDeviceSynchronize();
+    if (s->ring || s->ws || s->stage) (void)hipDeviceSynchronize();
     if (s->ring) (void)hipFree(s->ring);
-    if (s->ws) {
-        (void)hipFreeAsync(s->ws, nullptr);
+    if (s->ws || s->stage) {
+        if (s->ws) (void)hipFreeAsync(s->ws, nullptr);
+        if (s->stage) (void)hipFreeAsync(s->stage, nullptr);
         (void)hipStreamSynchronize(nullptr);
     }
     delete s;
@@ -118,13 +152,15 @@ tx_status tx_stream_open(tx_plan_t plan, int64_t max_block, tx_stream_t* out) {
     return TX_OK;
 }
 
-tx_status tx_stream_push(tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt, int32_t block_on_device,
-                         int32_t* d_out, int64_t out_pitch, int64_t* nt_out, hipStream_t stream) {
+static tx_status push_block(tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt,
+                            int32_t block_on_device, bool time_major, int32_t* d_out, int64_t out_pitch,
+                            int64_t* nt_out, hipStream_t stream) {
     if (!s || !nt_out) return TX_EINVAL;
     tx_status st = tx::check_out_args(d_out, out_pitch, nt);
     if (st != TX_OK) return st;
     int64_t n_out = 0;
-    st = tx::stream_ingest(s, block, block_pitch, nt, block_on_device, stream, &n_out);
+    st = time_major ? tx::stream_ingest_tf(s, block, block_pitch, nt, block_on_device, stream, &n_out)
+                    : tx::stream_ingest(s, block, block_pitch, nt, block_on_device, stream, &n_out);
     if (st != TX_OK) return st;
     if (n_out > 0) {
         const tx::DedispGeom geo = tx::dedisp_geometry(s->plan, n_out, tx::plan_tiles(s->plan));
@@ -153,6 +189,17 @@ tx_status tx_stream_push(tx_stream_t s, const uint8_t* block, int64_t block_pitc
     if (st != TX_OK) return st;
     *nt_out = n_out;
     return TX_OK;
+}
+
+tx_status tx_stream_push(tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt, int32_t block_on_device,
+                         int32_t* d_out, int64_t out_pitch, int64_t* nt_out, hipStream_t stream) {
+    return push_block(s, block, block_pitch, nt, block_on_device, false, d_out, out_pitch, nt_out, stream);
+}
+
+tx_status tx_stream_push_tf(tx_stream_t s, const uint8_t* block, int64_t block_pitch, int64_t nt,
+                            int32_t block_on_device, int32_t* d_out, int64_t out_pitch, int64_t* nt_out,
+                            hipStream_t stream) {
+    return push_block(s, block, block_pitch, nt, block_on_device, true, d_out, out_pitch, nt_out, stream);
 }
 
 tx_status tx_stream_position(tx_stream_t s, int64_t* received, int64_t* emitted) {

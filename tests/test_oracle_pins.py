@@ -113,6 +113,34 @@ def _python_brute(x, freqs, tsamp, dms, nt):
     return np.array(out, dtype=np.int64)
 
 
+def test_channel_rows_by_element_loops():
+    # The transpose step (Fig. "dedispersion_flow"): element by element on a
+    # small block with a channel pitch wider than nchan.
+    rng = np.random.default_rng(9)
+    x_tf = rng.integers(0, 256, size=(13, 7), dtype=np.uint8)
+    got = oracle.channel_rows(x_tf, 5)
+    assert got.shape == (5, 13)
+    for ch in range(5):
+        for t in range(13):
+            assert got[ch][t] == x_tf[t][ch]
+    with pytest.raises(ValueError):
+        oracle.channel_rows(x_tf, 8)
+
+
+def test_time_major_block_dedisperses_as_its_channel_rows():
+    # Recording order does not change the dedispersed series: brute force on
+    # the time-major block's channel rows equals brute force on the original.
+    freqs = list(synth.band_centres(1400, 1000, 6))
+    dms = [0.0, 9.0, 30.0]
+    tsamp = 5e-4
+    need = 30 + int(oracle.delay_samples(max(dms), min(freqs), max(freqs), tsamp))
+    x = synth.uniform_u8(6, need, 6)
+    x_tf = np.zeros((need, 16), dtype=np.uint8)
+    x_tf[:, :6] = x.T
+    y = oracle.dedisperse_brute(oracle.channel_rows(x_tf, 6), freqs, tsamp, dms, 30)
+    assert np.array_equal(y, _python_brute(x, freqs, tsamp, dms, 30))
+
+
 def test_brute_force_matches_triple_loop():
     freqs = list(synth.band_centres(1400, 1000, 6))
     dms = [0.0, 3.0, 17.5, 40.0, 41.0]
