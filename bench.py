@@ -148,6 +148,51 @@ def transpose_leg(torch, tx, nchan, nt, overlap, launches=20):
             "frac": nbytes / (avg * 1e-3) / 8e12, "matches_torch_transpose": ok}
 
 
+def ranges_leg(torch, tx, synth, steps=10):
+    """The paper-scale block in three DM ranges, coarser in DM and time as DM
+    grows (synth.dm_ranges("ranges-4096")): downsampling and dedispersion of
+    every range in one call, then peaks and candidates per range, against the
+    block's real-time budget."""
+    wl = synth.workload("paper-4096")
+    ranges = synth.dm_ranges("ranges-4096")
+    plans = [tx.tx_plan(wl.freqs, wl.tsamp * k, dms, wl.nsub) for dms, k in ranges]
+    rg = tx.Ranges(plans, [k for _, k in ranges])
+    nt = wl.nt
+    nchan = len(wl.freqs)
+    need = rg.input_len(nt)
+    pitch = (need + 255) // 256 * 256
+    d_in = synth.device_normal_u8(torch, nchan, pitch, wl.seed)
+    outs = [torch.empty((p.ndm, nt // k), dtype=torch.int32, device="cuda") for p, (_, k) in zip(plans, ranges)]
+    cap = 1 << 20
+    cands = [torch.empty((cap, 3), dtype=torch.int64, device="cuda") for _ in ranges]
+    counts = [torch.zeros(1, dtype=torch.int64, device="cuda") for _ in ranges]
+    stream = torch.cuda.current_stream()
+
+    def step():
+        rg.dedisperse(d_in, nt, outs, stream=stream)
+        for r, (_, k) in enumerate(ranges):
+            tx.tx_candidates(outs[r], nt // k, wl.widths, wl.gamma, cands[r], counts[r], stream=stream)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    samples = sum(p.ndm * (nt // k) for p, (_, k) in zip(plans, ranges))
+    out = {"workload": "ranges-4096", "ranges": [{"dm": [float(d[0]), float(d[-1])], "trials": len(d), "factor": k}
+                                                 for d, k in ranges],
+           "ms_per_block": dt * 1e3, "block_duration_ms": nt * wl.tsamp * 1e3,
+           "dm_trial_samples_per_s": samples / dt, "unit": "DM-trial samples/s (at each range's sampling)",
+           "candidates_last_step": [int(c.item()) for c in counts]}
+    rg.close()
+    del d_in, outs, cands
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_leg(torch, tx, synth, steps):
     """64 beams of uneven shape (channels 1024-4096, blocks 16384-65536, 512-4096
     DM trials up to DM 3000, sub-band count chosen by each plan) dedispersed
@@ -281,6 +326,7 @@ def main():
     ap.add_argument("--served-lanes", type=int, default=2)
     ap.add_argument("--served-slots", type=int, default=32)
     ap.add_argument("--no-transpose", action="store_true", help="skip the time-major ingest leg")
+    ap.add_argument("--no-ranges", action="store_true", help="skip the multi-range (downsampled) plan leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy the DM x time array once (a plain copy of known size "
                          "whose HBM counters scale the kernels' counters)")
@@ -382,6 +428,9 @@ def main():
     if not args.no_transpose:
         out["transpose"] = transpose_leg(torch, tx, nchan, nt, plan.overlap)
         print(f"transpose: {json.dumps(out['transpose'])}", file=sys.stderr, flush=True)
+    if not args.no_ranges:
+        out["ranges"] = ranges_leg(torch, tx, synth)
+        print(f"ranges: {json.dumps(out['ranges'])}", file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = batched_leg(torch, tx, synth, args.batched_steps)
         print(f"batched: {json.dumps(out['batched'])}", file=sys.stderr, flush=True)

@@ -222,6 +222,58 @@ tx_status tx_transpose_tf(const uint8_t* d_tf, int64_t tf_pitch, int32_t nchan, 
                           int64_t ft_pitch, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* DM ranges with downsampling (Sec. 2.3, dedispersion plans)                 */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * tx_downsample: out[c][t] = (sum of in[c][k t + i] for i < k, + k/2) / k
+ * (integer division: the mean of k consecutive samples rounded to nearest,
+ * halves up) for c < nchan, t < nt_out; k a power of two, 1..64.
+ *
+ *   d_in      uint8, nchan rows, row c at d_in + c*in_pitch, >= k*nt_out
+ *             samples (in_pitch >= k*nt_out).
+ *   d_out     uint8, nchan rows, row c at d_out + c*out_pitch (>= nt_out).
+ *   Pointers and pitches must be multiples of 16.
+ *
+ * Bound by HBM (k + 1 bytes per output).  Errors: TX_EINVAL, TX_EDEVICE.
+ */
+tx_status tx_downsample(const uint8_t* d_in, int64_t in_pitch, int32_t nchan, int64_t nt_out, int32_t k,
+                        uint8_t* d_out, int64_t out_pitch, hipStream_t stream);
+
+/*
+ * A dedispersion plan in DM ranges: range r dedisperses the block
+ * downsampled by factors[r] (tx_downsample) with plans[r], a plan over the
+ * same channels at sampling time tsamp * factors[r] (tsamp the block's own),
+ * typically covering a higher DM range with a coarser DM step.  The plans
+ * are borrowed: they must outlive the ranges object.  n is 1..64, every
+ * factor a power of two, 1..64.  Errors: TX_EINVAL (factor, channels or
+ * sampling times inconsistent), TX_ESTATE (host-only plan, or plans on
+ * different devices), TX_ENOMEM.
+ */
+typedef struct tx_ranges_s* tx_ranges_t;
+tx_status tx_ranges_create(const tx_plan_t* plans, const int32_t* factors, int32_t n, tx_ranges_t* out);
+
+/* Input samples per channel that a block of nt full-rate samples needs: the
+ * largest factors[r] * (nt / factors[r] + overlap_r).  nt must be a multiple
+ * of every factor (else TX_EINVAL). */
+tx_status tx_ranges_input_len(tx_ranges_t r, int64_t nt, int64_t* need);
+
+/*
+ * Dedisperse one block in every range.  d_in as for tx_dedisperse, with
+ * in_pitch >= tx_ranges_input_len(nt).  Range r writes plans[r]'s ndm rows of
+ * nt / factors[r] samples to d_outs[r] (out_pitches[r] elements per row, as
+ * for tx_dedisperse).  Each distinct factor > 1 downsamples the block once
+ * into a buffer from the device's stream-ordered pool, returned on `stream`.
+ * Every output equals tx_dedisperse of plans[r] on tx_downsample's output.
+ * Errors: TX_EINVAL, TX_ESTATE, TX_ENOMEM, TX_ENOTSUP, TX_EDEVICE.
+ */
+tx_status tx_ranges_dedisperse(tx_ranges_t r, const uint8_t* d_in, int64_t in_pitch, int64_t nt,
+                               int32_t* const* d_outs, const int64_t* out_pitches, hipStream_t stream);
+
+/* Release a ranges object (not its plans).  NULL is accepted. */
+tx_status tx_ranges_destroy(tx_ranges_t r);
+
+/* ------------------------------------------------------------------------ */
 /* Tile shapes (choices of the kernel implementation; results never change)  */
 /* ------------------------------------------------------------------------ */
 
@@ -493,7 +545,8 @@ typedef enum tx_kernel {
     TX_KERNEL_STAGE2 = 1,   /* second stage: fine DMs from the sub-band series */
     TX_KERNEL_BOXCAR = 2,   /* boxcar S/N, peaks and candidates */
     TX_KERNEL_TRANSPOSE = 3, /* time-major to channel-major ingest */
-    TX_KERNEL_COUNT = 4
+    TX_KERNEL_DOWNSAMPLE = 4, /* time downsampling of a DM range */
+    TX_KERNEL_COUNT = 5
 } tx_kernel;
 
 /*

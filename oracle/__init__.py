@@ -12,6 +12,7 @@ computes on its hot path:
 * the cold-plasma delay (Sec. 2.3, Eq. 1) turned into integer sample delays;
 * the "transpose" of time-major blocks into channel rows (Sec. 2.3,
   Fig. "dedispersion_flow");
+* downsampling in time before a DM range of a dedispersion plan (Sec. 2.3);
 * brute-force dedispersion (Sec. 2.3, the O(N_DM N_t N_f) method);
 * two-stage sub-band dedispersion (Sec. 2.3: coarse DM grid per sub-band,
   then the fine DM grid over the sub-banded series; Fig. "subband");
@@ -35,6 +36,7 @@ from .ref import (  # noqa: F401
     make_plan,
     group_size_rule,
     channel_rows,
+    downsample,
     dedisperse_brute,
     subband_stage1,
     subband_stage2,

@@ -181,6 +181,22 @@ def channel_rows(x_tf, nchan):
     return np.ascontiguousarray(x_tf[:, :nchan].T)
 
 
+def downsample(x, k, nt_out=None):
+    """Downsampling in time before dedispersing a DM range (Sec. 2.3, plans
+    in DM ranges): each output is the mean of k consecutive samples.  The
+    paper does not say how the mean is rounded back to the sample type; the
+    reading taken here is to the nearest integer, halves up, i.e.
+    (sum + k // 2) // k in integers."""
+    x = np.asarray(x)
+    if k < 1:
+        raise ValueError("k must be >= 1")
+    n = x.shape[1] // k if nt_out is None else int(nt_out)
+    if n * k > x.shape[1]:
+        raise ValueError(f"need {n * k} samples, have {x.shape[1]}")
+    s = x[:, :n * k].astype(np.int64).reshape(x.shape[0], n, k).sum(axis=2)
+    return ((s + k // 2) // k).astype(x.dtype)
+
+
 def dedisperse_brute(x, freqs, tsamp, dms, nt):
     """Brute-force dedispersion (Sec. 2.3):
     Y[i][t] = sum over channels of x[ch][t + D(dm_i, f_ch)], t in [0, nt)."""

@@ -93,7 +93,7 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_int64)]),
 }
 
-TX_KERNEL_STAGE1, TX_KERNEL_STAGE2, TX_KERNEL_BOXCAR, TX_KERNEL_TRANSPOSE = 0, 1, 2, 3
+TX_KERNEL_STAGE1, TX_KERNEL_STAGE2, TX_KERNEL_BOXCAR, TX_KERNEL_TRANSPOSE, TX_KERNEL_DOWNSAMPLE = 0, 1, 2, 3, 4
 
 
 def lib():
@@ -245,6 +245,51 @@ def tx_transpose_tf(d_tf, nchan, nt, d_ft, stream=None):
                                  d_ft.stride(0) * d_ft.element_size(), _stream(stream)), "tx_transpose_tf")
 
 
+def tx_downsample(d_in, nchan, nt_out, k, d_out, stream=None):
+    """d_in: uint8 device tensor [nchan, >= k*nt_out]; d_out: uint8 device
+    tensor [nchan, >= nt_out] receiving the rounded means of k samples."""
+    _check(lib().tx_downsample(_ptr(d_in), d_in.stride(0) * d_in.element_size(), int(nchan), int(nt_out), int(k),
+                               _ptr(d_out), d_out.stride(0) * d_out.element_size(), _stream(stream)), "tx_downsample")
+
+
+class Ranges:
+    """A dedispersion plan in DM ranges: plans[r] runs on the block
+    downsampled by factors[r] (tx_ranges_*)."""
+
+    def __init__(self, plans, factors):
+        self.plans = list(plans)
+        self.factors = [int(k) for k in factors]
+        hs = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        ks = (ctypes.c_int32 * len(self.factors))(*self.factors)
+        h = ctypes.c_void_p()
+        _check(lib().tx_ranges_create(hs, ks, len(self.plans), ctypes.byref(h)), "tx_ranges_create")
+        self._h = h
+
+    def input_len(self, nt):
+        n = ctypes.c_int64()
+        _check(lib().tx_ranges_input_len(self._h, int(nt), ctypes.byref(n)), "tx_ranges_input_len")
+        return n.value
+
+    def dedisperse(self, d_in, nt, d_outs, stream=None):
+        """d_in: uint8 device tensor [nchan, >= input_len(nt)]; d_outs[r]: int32
+        device tensor [plans[r].ndm, >= nt / factors[r]]."""
+        outs = (ctypes.c_void_p * len(d_outs))(*[_ptr(o) for o in d_outs])
+        pitches = (ctypes.c_int64 * len(d_outs))(*[o.stride(0) for o in d_outs])
+        _check(lib().tx_ranges_dedisperse(self._h, _ptr(d_in), d_in.stride(0) * d_in.element_size(), int(nt), outs,
+                                          pitches, _stream(stream)), "tx_ranges_dedisperse")
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().tx_ranges_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _widths(widths):
     w = np.ascontiguousarray(widths, dtype=np.int32)
     return w, w.ctypes.data_as(_c_i32p)
@@ -324,6 +369,15 @@ _SIGS2 = {
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "tx_transpose_tf": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "tx_downsample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "tx_ranges_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "tx_ranges_input_len": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "tx_ranges_dedisperse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.c_void_p]),
+    "tx_ranges_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "tx_stream_position": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                           ctypes.POINTER(ctypes.c_int64)]),
     "tx_stream_reset": (ctypes.c_int, [ctypes.c_void_p]),

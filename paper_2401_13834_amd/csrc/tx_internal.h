@@ -214,6 +214,11 @@ DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want);
 // (tx_kernels_transpose.hip); pointers and pitches multiples of 16.
 hipError_t launch_transpose_tf(const uint8_t* d_tf, int64_t tf_pitch, int32_t nchan, int64_t nt, uint8_t* d_ft,
                                int64_t ft_pitch, hipStream_t stream);
+// out[c][t] = rounded mean of in[c][k t .. k t + k - 1], t < nt_out, k a power
+// of two up to 64 (tx_kernels_downsample.hip); pointers and pitches multiples
+// of 16, in_pitch >= k * nt_out.
+hipError_t launch_downsample(const uint8_t* d_in, int64_t in_pitch, int32_t nchan, int64_t nt_out, int32_t k,
+                             uint8_t* d_out, int64_t out_pitch, hipStream_t stream);
 hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in, int64_t in_pitch,
                              int64_t nt, int32_t* d_out, int64_t out_pitch, uint16_t* d_B, hipStream_t stream,
                              int x_off = 0);

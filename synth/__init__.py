@@ -162,6 +162,23 @@ def workload(name):
     raise KeyError(name)
 
 
+def dm_ranges(name):
+    """DM ranges of a multi-range plan over a named workload's block, as
+    (dms, downsampling factor) pairs.
+
+    * ``ranges-4096``: the ``paper-4096`` block (4096 channels over
+      856-1712 MHz, 153.12 us, 65536 samples, 64 sub-bands) searched over
+      DM 0..2046 in three ranges, coarser in DM and time as DM grows:
+      0..511.5 step 0.5 at full rate, 512..1023 step 1 downsampled by 2,
+      1024..2046 step 2 downsampled by 4 (2048 trials).
+    """
+    if name == "ranges-4096":
+        return [(np.arange(1024, dtype=np.float64) * 0.5, 1),
+                (512.0 + np.arange(512, dtype=np.float64), 2),
+                (1024.0 + 2.0 * np.arange(512, dtype=np.float64), 4)]
+    raise KeyError(name)
+
+
 def pulse_amplitude(spec, width, nchan, std=16.0):
     """Per-channel amplitude for a pulse spec: ``("amp", ..., a)`` is a fixed
     amplitude; ``("snr", ..., s)`` spreads an integrated S/N ``s`` evenly over

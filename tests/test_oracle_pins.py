@@ -141,6 +141,51 @@ def test_time_major_block_dedisperses_as_its_channel_rows():
     assert np.array_equal(y, _python_brute(x, freqs, tsamp, dms, 30))
 
 
+def test_downsample_by_element_loops_and_special_cases():
+    rng = np.random.default_rng(12)
+    x = rng.integers(0, 256, size=(3, 37), dtype=np.uint8)
+    for k in (1, 2, 4, 8):
+        got = oracle.downsample(x, k)
+        n = 37 // k
+        assert got.shape == (3, n)
+        for c in range(3):
+            for t in range(n):
+                s = sum(int(x[c][k * t + i]) for i in range(k))
+                # nearest integer to s / k, halves up (exact rational comparison)
+                want = math.floor(Fraction(s, k) + Fraction(1, 2))
+                assert got[c][t] == want
+    assert np.array_equal(oracle.downsample(x, 1), x)                 # k = 1 is the identity
+    const = np.full((2, 64), 77, dtype=np.uint8)
+    assert np.all(oracle.downsample(const, 8) == 77)                  # constant in, constant out
+    ramp = np.tile(np.arange(64, dtype=np.uint8), (1, 1))
+    # mean of 2t .. 2t+1 is 2t + 1/2, which rounds up to 2t + 1
+    assert np.array_equal(oracle.downsample(ramp, 2)[0], 2 * np.arange(32) + 1)
+    with pytest.raises(ValueError):
+        oracle.downsample(x, 4, nt_out=10)
+
+
+def test_downsampled_range_recovers_high_dm_pulse():
+    # A dispersed pulse at high DM, downsampled by 4, is found by a plan at 4x
+    # the sampling time near its DM: the trial at the true DM collects the
+    # whole pulse, and it beats trials far from it.
+    nchan, tsamp, k = 64, 2.5e-4, 4
+    freqs = synth.band_centres(1500.0, 1100.0, nchan)
+    dm_true = 400.0
+    fref = max(freqs)
+    d = oracle.delay_samples(dm_true, np.asarray(freqs), fref, tsamp).astype(np.int64)
+    reach = int(oracle.delay_samples(500.0, min(freqs), fref, tsamp))
+    n = k * 1024 + reach + 64
+    x = np.full((nchan, n), 100, dtype=np.uint8)
+    for ch in range(nchan):
+        x[ch, 1000 + d[ch]:1000 + d[ch] + 8] = 140                     # 8 samples wide at full rate
+    xd = oracle.downsample(x, k)
+    dms = np.linspace(300.0, 500.0, 41)
+    y = oracle.dedisperse_brute(xd, freqs, tsamp * k, dms, 1024)
+    best = int(np.argmax(y.max(axis=1)))
+    assert abs(dms[best] - dm_true) <= 10.0
+    assert y[best].max() >= y[0].max() + nchan * 10
+
+
 def test_brute_force_matches_triple_loop():
     freqs = list(synth.band_centres(1400, 1000, 6))
     dms = [0.0, 3.0, 17.5, 40.0, 41.0]
