@@ -176,17 +176,30 @@ def ranges_leg(torch, tx, synth, steps=10):
     for _ in range(2):
         step()
     torch.cuda.synchronize()
+    tx.tx_profile_collect(tx.TX_KERNEL_DOWNSAMPLE)
+    tx.tx_profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    tx.tx_profile_enable(False)
+    ds_ms, ds_n = tx.tx_profile_collect(tx.TX_KERNEL_DOWNSAMPLE)
+    # Downsampling moves (k + 1) bytes per output sample of each distinct factor.
+    ds_bytes = 0
+    for k in sorted(set(k for _, k in ranges if k > 1)):
+        n_k = max(nt // k + p.overlap for p, (_, kk) in zip(plans, ranges) if kk == k)
+        ds_bytes += nchan * n_k * (k + 1)
+    ds_per_block = ds_ms / steps
     samples = sum(p.ndm * (nt // k) for p, (_, k) in zip(plans, ranges))
     out = {"workload": "ranges-4096", "ranges": [{"dm": [float(d[0]), float(d[-1])], "trials": len(d), "factor": k}
                                                  for d, k in ranges],
            "ms_per_block": dt * 1e3, "block_duration_ms": nt * wl.tsamp * 1e3,
            "dm_trial_samples_per_s": samples / dt, "unit": "DM-trial samples/s (at each range's sampling)",
-           "candidates_last_step": [int(c.item()) for c in counts]}
+           "candidates_last_step": [int(c.item()) for c in counts],
+           "downsample": {"ms_per_block": ds_per_block, "launches_per_block": ds_n / steps,
+                          "bytes_per_block": ds_bytes, "achieved_GBps": ds_bytes / (ds_per_block * 1e-3) / 1e9,
+                          "peak_GBps": 8000.0, "frac": ds_bytes / (ds_per_block * 1e-3) / 8e12}}
     rg.close()
     del d_in, outs, cands
     torch.cuda.empty_cache()
