@@ -206,6 +206,32 @@ def ranges_leg(torch, tx, synth, steps=10):
     return out
 
 
+def cluster_leg(torch, tx, synth, sizes=(1000, 10000, 100000, 1000000), radii=(4.0, 8.0, 16.0), min_pts=5,
+                reps=5):
+    """DBSCAN of the DM-time plane (the paper's clustering benchmark axes:
+    time against the number of points, for radii of 4, 8 and 16 samples):
+    seeded planes of blobs plus scattered points over the paper-4096 trial
+    grid, one tx_cluster call each (it returns when its work is done)."""
+    wl = synth.workload("paper-4096")
+    plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    rows = []
+    for n in sizes:
+        raw = torch.from_numpy(synth.plane_points(n, plan.ndm, wl.nt, 31)).to("cuda")
+        for r in radii:
+            tx.tx_cluster(plan, raw, n, r, min_pts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                _, _, _, ncl = tx.tx_cluster(plan, raw, n, r, min_pts)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            rows.append({"points": n, "radius": r, "ms": dt * 1e3, "clusters": int(ncl.item()),
+                         "points_per_s": n / dt})
+        del raw
+    return {"workload": "plane points over the paper-4096 trials (70% in blobs of 200)", "min_pts": min_pts,
+            "runs": rows}
+
+
 def batched_leg(torch, tx, synth, steps):
     """64 beams of uneven shape (channels 1024-4096, blocks 16384-65536, 512-4096
     DM trials up to DM 3000, sub-band count chosen by each plan) dedispersed
@@ -340,6 +366,7 @@ def main():
     ap.add_argument("--served-slots", type=int, default=32)
     ap.add_argument("--no-transpose", action="store_true", help="skip the time-major ingest leg")
     ap.add_argument("--no-ranges", action="store_true", help="skip the multi-range (downsampled) plan leg")
+    ap.add_argument("--no-cluster", action="store_true", help="skip the DM-time clustering leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy the DM x time array once (a plain copy of known size "
                          "whose HBM counters scale the kernels' counters)")
@@ -444,6 +471,9 @@ def main():
     if not args.no_ranges:
         out["ranges"] = ranges_leg(torch, tx, synth)
         print(f"ranges: {json.dumps(out['ranges'])}", file=sys.stderr, flush=True)
+    if not args.no_cluster:
+        out["cluster"] = cluster_leg(torch, tx, synth)
+        print(f"cluster: {json.dumps(out['cluster'])}", file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = batched_leg(torch, tx, synth, args.batched_steps)
         print(f"batched: {json.dumps(out['batched'])}", file=sys.stderr, flush=True)

@@ -375,6 +375,40 @@ tx_status tx_candidates(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64_t p
                         tx_cand* d_out, int64_t cap, int64_t* d_count,
                         double* d_snr, int32_t* d_width, int64_t* d_time, hipStream_t stream);
 
+/*
+ * tx_cluster: DBSCAN of thresholded DM-time points (Sec. 2.5) to remove
+ * duplicate detections of one pulse.
+ *
+ *   plan       the plan whose DM trials the points index.  Each point is
+ *              placed at (x, t): x the dispersion delay of its DM across the
+ *              band, k DM (1/f_lo^2 - 1/f_hi^2) / tsamp in samples (Eq. 1,
+ *              unrounded), t its start sample.
+ *   d_cands    n device records (any order, e.g. from tx_candidates), with
+ *              dm_index in [0, ndm) and time in [0, 2^32); other records are
+ *              treated as noise.  n < 2^31 - 1.
+ *   radius     r in samples (0 < r <= 1e6): neighbours are the other points
+ *              at Euclidean distance <= r.
+ *   min_pts    k >= 0: a core point has more than k neighbours.
+ *   d_sorted   n device records: the points sorted by (dm_index, time).
+ *   d_label    device int32[n]: cluster of d_sorted[i], or -1 for noise.
+ *              Core points connected through core neighbours share a
+ *              cluster; a non-core point within r of core points joins the
+ *              cluster of the nearest one (ties: the first in sorted order);
+ *              clusters are numbered 0.. in the order of their first core
+ *              point.
+ *   d_rep      device int64[n]: d_rep[c] for c < C is the sorted index of
+ *              cluster c's highest-S/N point (ties: the first); -1 beyond C.
+ *   d_nclusters  device int64: C.
+ *
+ * Results are unique for the given points (no dependence on input order or
+ * thread timing).  Scratch comes from the device's stream-ordered pool; the
+ * call waits for its own work on `stream` before returning (its host-built
+ * delay tables are copied on that stream).
+ * Errors: TX_EINVAL, TX_ESTATE, TX_ENOMEM, TX_EDEVICE.
+ */
+tx_status tx_cluster(tx_plan_t plan, const tx_cand* d_cands, int64_t n, double radius, int32_t min_pts,
+                     tx_cand* d_sorted, int32_t* d_label, int64_t* d_rep, int64_t* d_nclusters, hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Streams: a beam's consecutive blocks (Sec. 2.3, Fig. "dedispersion_flow") */
 /* ------------------------------------------------------------------------ */

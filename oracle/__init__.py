@@ -18,7 +18,8 @@ computes on its hot path:
   then the fine DM grid over the sub-banded series; Fig. "subband");
 * per-DM noise statistics and the boxcar S/N of Sec. 2.4, Eq. 5, computed
   from a running sum and the difference of two of its values;
-* the DM-time plane: best width per (DM, time), thresholded (Sec. 2.5).
+* the DM-time plane: best width per (DM, time), thresholded (Sec. 2.5);
+* DBSCAN clustering of that plane with DM turned into delay (Sec. 2.5).
 
 Where the paper is silent (the dispersion constant's value, the reference
 frequency, rounding of delays, how the coarse grid is chosen, the boxcar
@@ -49,4 +50,6 @@ from .ref import (  # noqa: F401
     boxcar_peaks,
     boxcar_candidates,
     boxcar_snr_fixed,
+    delay_axis,
+    dbscan_plane,
 )

@@ -427,3 +427,88 @@ def boxcar_snr_fixed(y, widths, mean, sigma):
         S = p[w:T + 1] - p[0:T - w + 1]
         out.append(float(np.max((S - w * mean) / (sigma * math.sqrt(w)))))
     return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# Clustering of the DM-time plane (Sec. 2.5)
+# ---------------------------------------------------------------------------
+
+def delay_axis(dms, freqs, tsamp):
+    """DM turned into dispersion delay (Sec. 2.5 uses Eq. 1 so that both axes
+    of the DM-time plane are times).  Reading: the delay across the band, from
+    the highest to the lowest channel frequency, in samples and unrounded,
+    ((k DM) (1/f_lo^2 - 1/f_hi^2)) / tsamp in float64 in this order."""
+    freqs = np.asarray(freqs, dtype=np.float64)
+    f_lo, f_hi = np.float64(freqs.min()), np.float64(freqs.max())
+    inv = np.float64(1.0) / (f_lo * f_lo) - np.float64(1.0) / (f_hi * f_hi)
+    return ((np.float64(K_DM) * np.asarray(dms, dtype=np.float64)) * inv) / np.float64(tsamp)
+
+
+def dbscan_plane(points, dms, freqs, tsamp, radius, min_pts):
+    """DBSCAN (Sec. 2.5) of DM-time points ``points`` = [(d, t, w, snr), ...]
+    (d a DM trial index, t a start sample), by the definitions the paper gives:
+
+    * neighbours of p: the other points within Euclidean distance ``radius``
+      in the (delay, time) plane, both in samples;
+    * core point: more than ``min_pts`` neighbours (the paper's "exceeds");
+    * a cluster: all core points joined by chains of core neighbours, plus the
+      non-core points within ``radius`` of them ("reachable" points);
+    * everything else is noise.
+
+    Readings where the paper leaves a choice: a non-core point within reach of
+    several clusters joins the one of its nearest core neighbour (ties: the
+    first in (d, t) order); points are ordered by (d, t), clusters numbered by
+    their first core point; a cluster's representative (the candidate that
+    survives de-duplication) is its highest-S/N point, ties to the first.
+
+    Returns (sorted points, labels (-1 noise), representatives (sorted index
+    per cluster), number of clusters).  Plain O(n^2) pairwise distances.
+    """
+    pts = sorted((int(d), int(t), int(w), float(snr)) for d, t, w, snr in points)
+    n = len(pts)
+    xs = delay_axis(dms, freqs, tsamp)
+    x = np.array([xs[d] for d, _, _, _ in pts], dtype=np.float64)
+    t = np.array([tt for _, tt, _, _ in pts], dtype=np.float64)
+    r2 = np.float64(radius) * np.float64(radius)
+    nbr = []
+    dist2 = []
+    for i in range(n):
+        dx = x - x[i]
+        dt = t - t[i]
+        d2 = dx * dx + dt * dt
+        mask = d2 <= r2
+        mask[i] = False
+        nbr.append(np.nonzero(mask)[0])
+        dist2.append(d2)
+    core = np.array([len(nb) > min_pts for nb in nbr], dtype=bool)
+    # connected components of the core graph (breadth-first), root = smallest index
+    comp = np.full(n, -1, dtype=np.int64)
+    for i in range(n):
+        if not core[i] or comp[i] >= 0:
+            continue
+        comp[i] = i
+        queue = [i]
+        while queue:
+            a = queue.pop()
+            for b in nbr[a]:
+                if core[b] and comp[b] < 0:
+                    comp[b] = i
+                    queue.append(b)
+    root = comp.copy()
+    for i in range(n):
+        if core[i]:
+            continue
+        best = None
+        for q in nbr[i]:
+            if core[q] and (best is None or dist2[i][q] < dist2[i][best] or (dist2[i][q] == dist2[i][best] and q < best)):
+                best = q
+        root[i] = comp[best] if best is not None else -1
+    roots = sorted(set(int(r) for r in root[core]))
+    cid = {r: c for c, r in enumerate(roots)}
+    labels = np.array([cid[int(r)] if r >= 0 else -1 for r in root], dtype=np.int64)
+    reps = []
+    for c in range(len(roots)):
+        members = [i for i in range(n) if labels[i] == c]
+        reps.append(max(members, key=lambda i: (pts[i][3], -i)))
+    return pts, labels, np.array(reps, dtype=np.int64), len(roots)
+

@@ -245,6 +245,23 @@ def tx_transpose_tf(d_tf, nchan, nt, d_ft, stream=None):
                                  d_ft.stride(0) * d_ft.element_size(), _stream(stream)), "tx_transpose_tf")
 
 
+def tx_cluster(plan, cands, n, radius, min_pts, stream=None):
+    """DBSCAN of the first n candidate records of the device tensor ``cands``
+    (int64 [>= n, 3], as filled by tx_candidates).  Returns device tensors
+    (sorted records [n, 3], labels int32 [n], reps int64 [n], nclusters
+    int64 [1])."""
+    import torch
+    n = int(n)
+    dev = cands.device
+    srt = torch.empty((max(n, 1), 3), dtype=torch.int64, device=dev)
+    lab = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    rep = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+    ncl = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(lib().tx_cluster(plan.handle, _ptr(cands), n, float(radius), int(min_pts), _ptr(srt), _ptr(lab), _ptr(rep),
+                            _ptr(ncl), _stream(stream)), "tx_cluster")
+    return srt[:n], lab[:n], rep[:n], ncl
+
+
 def tx_downsample(d_in, nchan, nt_out, k, d_out, stream=None):
     """d_in: uint8 device tensor [nchan, >= k*nt_out]; d_out: uint8 device
     tensor [nchan, >= nt_out] receiving the rounded means of k samples."""
@@ -369,6 +386,9 @@ _SIGS2 = {
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "tx_transpose_tf": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "tx_cluster": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
     "tx_downsample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "tx_ranges_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int32),

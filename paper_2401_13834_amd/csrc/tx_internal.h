@@ -217,6 +217,11 @@ hipError_t launch_transpose_tf(const uint8_t* d_tf, int64_t tf_pitch, int32_t nc
 // out[c][t] = rounded mean of in[c][k t .. k t + k - 1], t < nt_out, k a power
 // of two up to 64 (tx_kernels_downsample.hip); pointers and pitches multiples
 // of 16, in_pitch >= k * nt_out.
+// DBSCAN of n DM-time points (tx_kernels_cluster.hip): d_x[ndm] delays in
+// samples, [d_dlo[d], d_dhi[d]] the DM indices within the radius of d.
+hipError_t launch_cluster(const tx_cand* d_in, int64_t n, int32_t ndm, const double* d_x, const int32_t* d_dlo,
+                          const int32_t* d_dhi, double r, int32_t kmin, tx_cand* d_sorted, int32_t* d_label,
+                          int64_t* d_rep, int64_t* d_nclusters, hipStream_t st);
 hipError_t launch_downsample(const uint8_t* d_in, int64_t in_pitch, int32_t nchan, int64_t nt_out, int32_t k,
                              uint8_t* d_out, int64_t out_pitch, hipStream_t stream);
 hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in, int64_t in_pitch,

@@ -257,3 +257,37 @@ def poisson_arrivals(nbeams, nblocks, period_s, speed, seed):
     gaps = rng.exponential(period_s / speed, size=(nbeams, nblocks))
     gaps[:, 0] = 0.0
     return start[:, None] + np.cumsum(gaps, axis=1)
+
+
+def plane_points(n, ndm, nt, seed, blob_frac=0.7, blob_size=200, spread=3):
+    """``n`` distinct DM-time points (d, t, width, snr) as a thresholded plane
+    holds them: about ``blob_frac`` of them in blobs of about ``blob_size``
+    points around random (d, t) (a pulse seen at neighbouring trials and
+    times, +-spread trials and +-4 spread samples), the rest scattered
+    uniformly; widths 1..64, S/N uniform in [6, 20).  Returned as an int64
+    array [n, 3] in the record layout of the candidate list
+    (d | width << 32, time, snr bits), rows in random order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    keys = np.empty(0, dtype=np.int64)
+    n_blob = int(n * blob_frac)
+    while keys.size < n_blob:
+        nb = max(1, (n_blob - keys.size) // blob_size + 1)
+        d0 = rng.integers(0, ndm, size=nb)
+        t0 = rng.integers(0, nt, size=nb)
+        d = (np.repeat(d0, blob_size) + rng.integers(-spread, spread + 1, size=nb * blob_size))
+        t = (np.repeat(t0, blob_size) + rng.integers(-4 * spread, 4 * spread + 1, size=nb * blob_size))
+        ok = (d >= 0) & (d < ndm) & (t >= 0) & (t < nt)
+        keys = np.unique(np.concatenate([keys, d[ok] * nt + t[ok]]))
+    keys = rng.permutation(keys)[:n_blob] if keys.size > n_blob else keys
+    while keys.size < n:
+        extra = rng.integers(0, ndm, size=n - keys.size) * nt + rng.integers(0, nt, size=n - keys.size)
+        keys = np.unique(np.concatenate([keys, extra]))
+    keys = keys[rng.permutation(keys.size)[:n]]
+    d, t = keys // nt, keys % nt
+    w = rng.integers(1, 65, size=n).astype(np.int64)
+    snr = rng.uniform(6.0, 20.0, size=n)
+    out = np.empty((n, 3), dtype=np.int64)
+    out[:, 0] = d | (w << 32)
+    out[:, 1] = t
+    out[:, 2] = snr.view(np.int64)
+    return out

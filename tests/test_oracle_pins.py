@@ -546,3 +546,85 @@ def test_spectral_index_dedispersed_pulse_matches_discrete_closed_form():
     a8 = (f8 / 816.0) ** -1.5
     discrete = a8.sum() / math.sqrt(8192 * np.sum(a8 ** 2))
     assert discrete == pytest.approx(_spectral_closed_form(1.5, 2.0), abs=2e-9)
+
+
+# ---------------------------------------------------------------------------
+# Clustering of the DM-time plane (Sec. 2.5)
+# ---------------------------------------------------------------------------
+
+def _plane_points(rng, n_blobs, per_blob, n_noise, ndm, nt, spread):
+    pts = set()
+    for _ in range(n_blobs):
+        d0, t0 = int(rng.integers(5, ndm - 5)), int(rng.integers(50, nt - 50))
+        for _ in range(per_blob):
+            pts.add((int(np.clip(d0 + rng.integers(-spread, spread + 1), 0, ndm - 1)),
+                     int(t0 + rng.integers(-4 * spread, 4 * spread + 1))))
+    for _ in range(n_noise):
+        pts.add((int(rng.integers(0, ndm)), int(rng.integers(0, nt))))
+    return [(d, t, 1, float(rng.uniform(6.0, 20.0))) for d, t in sorted(pts)]
+
+
+@pytest.mark.parametrize("seed,radius,min_pts", [(1, 4.0, 2), (2, 8.0, 3), (3, 6.5, 0), (4, 16.0, 5)])
+def test_dbscan_core_partition_matches_scikit_learn(seed, radius, min_pts):
+    # The paper's definitions against an independent DBSCAN: scikit-learn's
+    # core points (min_samples counts the point itself, so k + 2 for "more than
+    # k others") and its partition of them must agree exactly; its border
+    # assignment is order-dependent, so border points are checked for validity.
+    from sklearn.cluster import DBSCAN
+    rng = np.random.default_rng(seed)
+    freqs = synth.band_centres(1712.0, 856.0, 64)
+    ndm, nt, tsamp = 200, 2000, 1e-3
+    dms = np.arange(ndm) * 0.37 + rng.uniform(0, 0.2)
+    pts = _plane_points(rng, 6, 40, 120, ndm, nt, 3)
+    srt, lab, reps, ncl = oracle.dbscan_plane(pts, dms, freqs, tsamp, radius, min_pts)
+    xs = oracle.delay_axis(dms, freqs, tsamp)
+    X = np.array([[xs[d], t] for d, t, _, _ in srt], dtype=np.float64)
+    sk = DBSCAN(eps=radius, min_samples=min_pts + 2).fit(X)
+    core = np.zeros(len(srt), dtype=bool)
+    core[sk.core_sample_indices_] = True
+    # our core points are exactly those with a cluster of their own making
+    d2 = ((X[:, None, :] - X[None, :, :]) ** 2).sum(axis=2)
+    ours_core = ((d2 <= radius * radius).sum(axis=1) - 1) > min_pts
+    assert np.array_equal(core, ours_core)
+    # same partition of the core points
+    pairs_sk = {(int(a), int(b)) for a in np.nonzero(core)[0] for b in np.nonzero(core)[0]
+                if sk.labels_[a] == sk.labels_[b]}
+    pairs_us = {(int(a), int(b)) for a in np.nonzero(core)[0] for b in np.nonzero(core)[0] if lab[a] == lab[b]}
+    assert pairs_sk == pairs_us
+    assert ncl == len(set(sk.labels_[core]))
+    # noise agrees; every border point sits within r of a core point of its cluster
+    assert np.array_equal(lab < 0, sk.labels_ < 0)
+    for i in np.nonzero(~core & (lab >= 0))[0]:
+        near = np.nonzero(core & (d2[i] <= radius * radius))[0]
+        assert any(lab[q] == lab[i] for q in near)
+    # representatives: the highest S/N of each cluster
+    for c in range(ncl):
+        members = np.nonzero(lab == c)[0]
+        assert srt[reps[c]][3] == max(srt[i][3] for i in members)
+
+
+def test_dbscan_hand_cases():
+    freqs = [1500.0, 1400.0]
+    tsamp = 1e-3
+    dms = np.zeros(10)                                  # every DM at delay 0: a 1-D problem in time
+    chain = [(0, 10 * i, 1, 7.0 + i) for i in range(6)]  # spaced 10 apart
+    far = [(0, 500, 1, 9.0), (0, 505, 1, 8.0)]
+    pts = chain + far
+    srt, lab, reps, ncl = oracle.dbscan_plane(pts, dms, freqs, tsamp, 10.0, 1)
+    # interior chain points have 2 neighbours (> 1): core; the ends are reachable
+    assert ncl == 1 and list(lab) == [0] * 6 + [-1, -1]
+    assert reps[0] == 5                                 # highest S/N, the last of the chain
+    srt, lab, reps, ncl = oracle.dbscan_plane(pts, dms, freqs, tsamp, 10.0, 2)
+    assert ncl == 0 and np.all(lab == -1)               # no point has more than 2 neighbours
+    srt, lab, reps, ncl = oracle.dbscan_plane(pts, dms, freqs, tsamp, 9.99, 0)
+    assert ncl == 1 and list(lab) == [-1] * 6 + [0, 0]  # only the close pair is within 9.99
+    srt, lab, reps, ncl = oracle.dbscan_plane([], dms, freqs, tsamp, 5.0, 1)
+    assert ncl == 0 and len(lab) == 0
+
+
+def test_delay_axis_rounds_to_the_plan_delay_of_the_lowest_channel():
+    freqs = synth.band_centres(1712.0, 856.0, 256)
+    dms = np.array([0.0, 3.5, 100.0, 1234.5])
+    x = oracle.delay_axis(dms, freqs, 306.24e-6)
+    d = oracle.delay_samples(dms, freqs.min(), freqs.max(), 306.24e-6)
+    assert np.array_equal(np.floor(x + 0.5).astype(np.int64), d)
