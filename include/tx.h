@@ -222,6 +222,44 @@ tx_status tx_transpose_tf(const uint8_t* d_tf, int64_t tf_pitch, int32_t nchan, 
                           int64_t ft_pitch, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* Channel masks (Sec. 2.2, narrow-band RFI removal)                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Drop channels from a plan's sums: mask[c] == 0 gives channel c weight 0 in
+ * every trial of every later dedispersion with this plan (its samples are
+ * read as zeros), exactly as if its row were zero; non-zero keeps it.  NULL,
+ * or a mask that keeps every channel, removes the mask.  Waits for all queued
+ * device work first (queued work may read the mask).  Errors: TX_EINVAL,
+ * TX_ESTATE (host-only plan), TX_ENOMEM, TX_EDEVICE.
+ */
+tx_status tx_plan_set_mask(tx_plan_t plan, const uint8_t* mask);
+/* The plan's mask as nchan bytes of 0 / 1 (all 1 without a mask). */
+tx_status tx_plan_get_mask(tx_plan_t plan, uint8_t* mask);
+
+/*
+ * tx_channel_power_sums: d_sums[4c + j] = sum over t < nt of x[c][t]^(j+1),
+ * j = 0..3, exact in uint64, for the nchan channel rows of d_in (row c at
+ * d_in + c*in_pitch; d_in and in_pitch multiples of 16, in_pitch >= nt,
+ * nt <= 2^32; d_sums 8-byte aligned, 4*nchan values).  Asynchronous on
+ * `stream`.  Errors: TX_EINVAL, TX_EDEVICE.
+ */
+tx_status tx_channel_power_sums(const uint8_t* d_in, int64_t in_pitch, int32_t nchan, int64_t nt, uint64_t* d_sums,
+                                hipStream_t stream);
+
+/*
+ * tx_skf_mask (host): the skewness-kurtosis channel mask from power sums of
+ * nt samples per channel (host array, 4*nchan values; 1 <= nt <= 2^23).
+ * Per channel, from exact integer central moments: skewness m3 / m2^1.5 and
+ * kurtosis m4 / m2^2.  Over the channels with m2 > 0, a channel is an outlier
+ * in a statistic when its distance to the median exceeds threshold times
+ * 1.482602218505602 times the median absolute deviation (with a zero
+ * deviation, any value off the median).  mask[c] = 0 for outliers in either
+ * statistic and for channels with m2 = 0, else 1.  Errors: TX_EINVAL.
+ */
+tx_status tx_skf_mask(const uint64_t* sums, int32_t nchan, int64_t nt, double threshold, uint8_t* mask);
+
+/* ------------------------------------------------------------------------ */
 /* DM ranges with downsampling (Sec. 2.3, dedispersion plans)                 */
 /* ------------------------------------------------------------------------ */
 

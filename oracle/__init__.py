@@ -10,6 +10,8 @@ It is a plain, slow, obviously correct restatement of what the paper
 computes on its hot path:
 
 * the cold-plasma delay (Sec. 2.3, Eq. 1) turned into integer sample delays;
+* per-channel power sums, skewness and kurtosis, and the channel mask of the
+  narrow-band RFI filter (Sec. 2.2);
 * the "transpose" of time-major blocks into channel rows (Sec. 2.3,
   Fig. "dedispersion_flow");
 * downsampling in time before a DM range of a dedispersion plan (Sec. 2.3);
@@ -52,4 +54,7 @@ from .ref import (  # noqa: F401
     boxcar_snr_fixed,
     delay_axis,
     dbscan_plane,
+    channel_power_sums,
+    channel_moments,
+    skf_mask,
 )

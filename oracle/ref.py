@@ -512,3 +512,66 @@ def dbscan_plane(points, dms, freqs, tsamp, radius, min_pts):
         reps.append(max(members, key=lambda i: (pts[i][3], -i)))
     return pts, labels, np.array(reps, dtype=np.int64), len(roots)
 
+
+# ---------------------------------------------------------------------------
+# Narrow-band RFI: channel statistics and mask (Sec. 2.2)
+# ---------------------------------------------------------------------------
+
+def channel_power_sums(x):
+    """Per channel row: (sum x, sum x^2, sum x^3, sum x^4), exact integers."""
+    x = np.asarray(x).astype(np.int64)
+    return np.stack([(x ** j).sum(axis=1) for j in (1, 2, 3, 4)], axis=1)
+
+
+def channel_moments(sums, nt):
+    """Skewness m3 / m2^1.5 and kurtosis m4 / m2^2 of each channel from its
+    power sums over nt samples (population central moments).  The central
+    moments are formed exactly in integers (n^2 m2, n^3 m3, n^4 m4) and turned
+    to float64 once; channels with m2 = 0 give None."""
+    out = []
+    n = int(nt)
+    for s1, s2, s3, s4 in np.asarray(sums).tolist():
+        s1, s2, s3, s4 = int(s1), int(s2), int(s3), int(s4)
+        m2 = n * s2 - s1 * s1
+        m3 = n * n * s3 - 3 * n * s1 * s2 + 2 * s1 ** 3
+        m4 = n ** 3 * s4 - 4 * n * n * s1 * s3 + 6 * n * s1 * s1 * s2 - 3 * s1 ** 4
+        if m2 <= 0:
+            out.append(None)
+            continue
+        f2, f3, f4 = float(m2), float(m3), float(m4)
+        out.append((f3 / (f2 * np.sqrt(f2)), f4 / (f2 * f2)))
+    return out
+
+
+def skf_mask(sums, nt, threshold):
+    """The skewness-kurtosis filter (Sec. 2.2): channels that are outliers in
+    skewness or kurtosis across the band are removed.  The paper states the
+    intent; the rule taken here (a reading) is the robust z-score: over the
+    channels with non-zero variance, a value s is an outlier when
+    |s - median| > threshold * 1.482602218505602 * MAD (MAD the median absolute
+    deviation; with MAD = 0, any value off the median).  Returns uint8, 0 for
+    removed channels (outliers, and channels of zero variance), 1 to keep."""
+    mom = channel_moments(sums, nt)
+    idx = [c for c, m in enumerate(mom) if m is not None]
+    mask = np.zeros(len(mom), dtype=np.uint8)
+    if not idx:
+        return mask
+
+    def med(v):
+        v = sorted(v)
+        k = len(v)
+        return v[k // 2] if k % 2 else (v[k // 2 - 1] + v[k // 2]) / 2.0
+
+    bad = [False] * len(idx)
+    for j in (0, 1):
+        s = [mom[c][j] for c in idx]
+        m = med(s)
+        dev = [abs(v - m) for v in s]
+        mad = med(dev)
+        lim = threshold * (1.482602218505602 * mad)
+        for i, dv in enumerate(dev):
+            bad[i] = bad[i] or (dv > lim if mad > 0.0 else dv != 0.0)
+    for i, c in enumerate(idx):
+        mask[c] = 0 if bad[i] else 1
+    return mask
+

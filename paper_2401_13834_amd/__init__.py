@@ -181,6 +181,21 @@ class Plan:
         _check(lib().tx_plan_delays(self._h, float(dm), out.ctypes.data_as(_c_i32p)), "tx_plan_delays")
         return out
 
+    def set_mask(self, mask):
+        """mask: nchan values, 0 drops a channel from every sum (None keeps all)."""
+        if mask is None:
+            _check(lib().tx_plan_set_mask(self._h, None), "tx_plan_set_mask")
+            return
+        m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
+        if m.size != self.info["nchan"]:
+            raise ValueError("mask needs one value per channel")
+        _check(lib().tx_plan_set_mask(self._h, m.ctypes.data_as(ctypes.c_void_p)), "tx_plan_set_mask")
+
+    def get_mask(self):
+        m = np.empty(self.info["nchan"], dtype=np.uint8)
+        _check(lib().tx_plan_get_mask(self._h, m.ctypes.data_as(ctypes.c_void_p)), "tx_plan_get_mask")
+        return m
+
     def get_tiles(self):
         t = Tiles()
         _check(lib().tx_plan_get_tiles(self._h, ctypes.byref(t)), "tx_plan_get_tiles")
@@ -243,6 +258,22 @@ def tx_transpose_tf(d_tf, nchan, nt, d_ft, stream=None):
     device tensor [>= nchan, >= nt] receiving d_ft[c, t] = d_tf[t, c]."""
     _check(lib().tx_transpose_tf(_ptr(d_tf), d_tf.stride(0) * d_tf.element_size(), int(nchan), int(nt), _ptr(d_ft),
                                  d_ft.stride(0) * d_ft.element_size(), _stream(stream)), "tx_transpose_tf")
+
+
+def tx_channel_power_sums(d_in, nchan, nt, d_sums, stream=None):
+    """d_in: uint8 device tensor [nchan, >= nt]; d_sums: int64 device tensor
+    [nchan, 4] receiving sum x, x^2, x^3, x^4 per channel (as uint64 bits)."""
+    _check(lib().tx_channel_power_sums(_ptr(d_in), d_in.stride(0) * d_in.element_size(), int(nchan), int(nt),
+                                       _ptr(d_sums), _stream(stream)), "tx_channel_power_sums")
+
+
+def tx_skf_mask(sums, nt, threshold):
+    """Host: channel mask (uint8, 1 keep / 0 drop) from power sums [nchan, 4]."""
+    s = np.ascontiguousarray(sums).view(np.uint64).reshape(-1, 4)
+    m = np.empty(s.shape[0], dtype=np.uint8)
+    _check(lib().tx_skf_mask(s.ctypes.data_as(ctypes.c_void_p), s.shape[0], int(nt), float(threshold),
+                             m.ctypes.data_as(ctypes.c_void_p)), "tx_skf_mask")
+    return m
 
 
 def tx_cluster(plan, cands, n, radius, min_pts, stream=None):
@@ -386,6 +417,12 @@ _SIGS2 = {
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "tx_transpose_tf": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "tx_plan_set_mask": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tx_plan_get_mask": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tx_channel_power_sums": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "tx_skf_mask": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                   ctypes.c_void_p]),
     "tx_cluster": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p]),

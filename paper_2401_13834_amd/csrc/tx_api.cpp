@@ -20,8 +20,10 @@ tx_status from_hip(hipError_t e) { return tx::status_of(e); }
 void release_device(tx_plan_s* p) {
     if (p->d_dT) (void)hipFree(p->d_dT);
     if (p->d_rT) (void)hipFree(p->d_rT);
+    if (p->d_mask) (void)hipFree(p->d_mask);
     p->d_dT = nullptr;
     p->d_rT = nullptr;
+    p->d_mask = nullptr;
     p->on_device = false;
 }
 
@@ -294,6 +296,41 @@ tx_status tx_dedisperse(tx_plan_t p, const uint8_t* d_in, int64_t in_pitch, int6
     hipError_t f = hipFreeAsync(ws, stream);
     if (e != hipSuccess) return from_hip(e);
     return from_hip(f);
+}
+
+tx_status tx_plan_set_mask(tx_plan_t p, const uint8_t* mask) {
+    if (!p) return TX_EINVAL;
+    tx_status st = check_device_plan(p);
+    if (st != TX_OK) return st;
+    // Work already queued may still read the old mask.
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return from_hip(e);
+    bool keep_all = true;
+    if (mask)
+        for (int32_t c = 0; c < p->nchan; ++c) keep_all = keep_all && mask[c] != 0;
+    if (keep_all) {
+        if (p->d_mask) (void)hipFree(p->d_mask);
+        p->d_mask = nullptr;
+        p->mask.clear();
+        return TX_OK;
+    }
+    if (!p->d_mask) {
+        e = hipMalloc(reinterpret_cast<void**>(&p->d_mask), static_cast<size_t>(p->nchan));
+        if (e != hipSuccess) {
+            p->d_mask = nullptr;
+            return from_hip(e);
+        }
+    }
+    p->mask.assign(mask, mask + p->nchan);
+    for (uint8_t& m : p->mask) m = m ? 1 : 0;
+    e = hipMemcpy(p->d_mask, p->mask.data(), static_cast<size_t>(p->nchan), hipMemcpyHostToDevice);
+    return from_hip(e);
+}
+
+tx_status tx_plan_get_mask(tx_plan_t p, uint8_t* mask) {
+    if (!p || !mask) return TX_EINVAL;
+    for (int32_t c = 0; c < p->nchan; ++c) mask[c] = p->mask.empty() ? 1 : p->mask[c];
+    return TX_OK;
 }
 
 tx_status tx_transpose_tf(const uint8_t* d_tf, int64_t tf_pitch, int32_t nchan, int64_t nt, uint8_t* d_ft,

@@ -50,6 +50,7 @@ struct Stage1Args {
     int64_t x_pitch;        // bytes between rows
     int64_t x_len;          // valid samples per row (nt + overlap), counted from x_off
     int32_t x_off;          // first sample of every row at byte x_off (0..15) from x
+    const uint8_t* mask;    // per channel, 0 = dropped (staged as zeros); null = keep all
     uint16_t* B;            // first-stage series [ngroups][nsub][B_pitch]
     int64_t B_pitch;        // elements per series (multiple of the time tile)
     const int32_t* dT;      // [nchan][gpad] D(c_j, f_ch), trial axis padded with the last group
@@ -139,6 +140,8 @@ struct tx_plan_s {
     bool on_device = false;
     int32_t* d_dT = nullptr;
     int32_t* d_rT = nullptr;
+    uint8_t* d_mask = nullptr;         // per channel: 0 drops it from every sum (null: keep all)
+    std::vector<uint8_t> mask;         // host copy (empty: keep all)
     mutable std::mutex mu;             // guards `tiles` and the spread cache
     tx::Tiles tiles;
     mutable std::vector<std::pair<int, int32_t>> spread1_cache;   // (J, spread)
@@ -222,6 +225,9 @@ hipError_t launch_transpose_tf(const uint8_t* d_tf, int64_t tf_pitch, int32_t nc
 hipError_t launch_cluster(const tx_cand* d_in, int64_t n, int32_t ndm, const double* d_x, const int32_t* d_dlo,
                           const int32_t* d_dhi, double r, int32_t kmin, tx_cand* d_sorted, int32_t* d_label,
                           int64_t* d_rep, int64_t* d_nclusters, hipStream_t st);
+// Exact per-channel (sum x, x^2, x^3, x^4) of nt samples (tx_kernels_stats.hip).
+hipError_t launch_power_sums(const uint8_t* d_in, int64_t in_pitch, int32_t nchan, int64_t nt, uint64_t* d_sums,
+                             hipStream_t stream);
 hipError_t launch_downsample(const uint8_t* d_in, int64_t in_pitch, int32_t nchan, int64_t nt_out, int32_t k,
                              uint8_t* d_out, int64_t out_pitch, hipStream_t stream);
 hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in, int64_t in_pitch,

@@ -135,7 +135,9 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
             const int ch = ch0 + cb + c;
             const int64_t start = static_cast<int64_t>(u0) + ((dT[static_cast<size_t>(ch) * gp + j0] + xo) & ~15);
             const TX_GLOBAL uint8_t* row = to_global(a.x) + static_cast<size_t>(ch) * a.x_pitch + start;
-            const int64_t avail_b = a.x_len + xo - start;
+            // A dropped channel is staged as zeros (weight 0 in every sum).
+            const bool keep = !a.mask || to_global(a.mask)[ch] != 0;
+            const int64_t avail_b = keep ? a.x_len + xo - start : 0;
             uint32_t* dst = reinterpret_cast<uint32_t*>(dat + c * rowbytes);
             for (int i = lane; 4 * i < W; i += 64) {
                 uint32_t d[5];
@@ -582,6 +584,7 @@ void fill_stage_args(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d
     s1->x_pitch = in_pitch;
     s1->x_len = nt + p->overlap;
     s1->x_off = 0;
+    s1->mask = p->d_mask;
     s1->B = d_B;
     s1->B_pitch = geo.B_pitch;
     s1->dT = p->d_dT;

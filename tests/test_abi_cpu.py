@@ -134,3 +134,22 @@ def test_tune_cache_roundtrip(tmp_path):
     assert tune.load(path)[k1]["tiles"] == [3, 32768, 1, 32768]
     assert tune.nsub_candidates(4096) == [16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
     assert all(4096 % n == 0 and 4096 // n <= 256 for n in tune.nsub_candidates(4096))
+
+
+def test_skf_mask_host_function_matches_oracle():
+    # tx_skf_mask is host code: the C decision from power sums equals the
+    # oracle's on random channel statistics, including planted outliers and a
+    # zero-variance channel.
+    import oracle
+    import synth
+    rng = np.random.default_rng(40)
+    for trial in range(20):
+        nchan, nt = int(rng.integers(3, 200)), int(rng.integers(2, 5000))
+        x = synth.normal_u8(nchan, nt, 100 + trial)
+        if nchan > 5:
+            x[2] = 9
+            x[4, ::7] = 250
+        sums = oracle.channel_power_sums(x)
+        want = oracle.skf_mask(sums, nt, 3.5)
+        got = tx.tx_skf_mask(sums.astype(np.uint64), nt, 3.5)
+        assert np.array_equal(got, want), trial

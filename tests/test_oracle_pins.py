@@ -628,3 +628,58 @@ def test_delay_axis_rounds_to_the_plan_delay_of_the_lowest_channel():
     x = oracle.delay_axis(dms, freqs, 306.24e-6)
     d = oracle.delay_samples(dms, freqs.min(), freqs.max(), 306.24e-6)
     assert np.array_equal(np.floor(x + 0.5).astype(np.int64), d)
+
+
+# ---------------------------------------------------------------------------
+# Narrow-band RFI: channel statistics and mask (Sec. 2.2)
+# ---------------------------------------------------------------------------
+
+def test_power_sums_by_loops():
+    rng = np.random.default_rng(31)
+    x = rng.integers(0, 256, size=(3, 23), dtype=np.uint8)
+    s = oracle.channel_power_sums(x)
+    for c in range(3):
+        for j in range(4):
+            assert s[c][j] == sum(int(v) ** (j + 1) for v in x[c])
+
+
+def test_moments_match_scipy_and_closed_forms():
+    from scipy import stats
+    rng = np.random.default_rng(32)
+    x = np.concatenate([rng.integers(0, 256, size=(4, 5000)), np.full((1, 5000), 7),
+                        np.tile([0, 2], (1, 2500))]).astype(np.uint8)
+    mom = oracle.channel_moments(oracle.channel_power_sums(x), 5000)
+    for c in range(4):
+        g1, b2 = mom[c]
+        assert g1 == pytest.approx(stats.skew(x[c].astype(np.float64)), rel=1e-9, abs=1e-12)
+        assert b2 == pytest.approx(stats.kurtosis(x[c].astype(np.float64), fisher=False), rel=1e-9)
+    assert mom[4] is None                       # constant channel: no variance
+    assert mom[5] == (0.0, 1.0)                 # two equal point masses: skew 0, kurtosis 1
+
+
+def test_skf_mask_removes_planted_rfi_channels():
+    # Noise channels plus: an impulsive channel (rare spikes: huge kurtosis),
+    # a skewed channel (one-sided bursts), a constant channel.
+    x = synth.normal_u8(40, 8000, 33)
+    x[5] = 128
+    x[5, ::97] = 255
+    x[17] = np.clip(x[17].astype(np.int64) + (np.arange(8000) % 50 < 5) * 90, 0, 255).astype(np.uint8)
+    x[30] = 128
+    mask = oracle.skf_mask(oracle.channel_power_sums(x), 8000, 5.0)
+    assert list(np.nonzero(mask == 0)[0]) == [5, 17, 30]
+
+
+def test_masked_channels_count_as_zero_rows():
+    plan = _rand_plan(34)
+    x = synth.uniform_u8(32, 400 + plan.overlap, 35)
+    mask = np.ones(32, dtype=np.uint8)
+    mask[[0, 3, 31]] = 0
+    xz = x * mask[:, None]
+    y = oracle.dedisperse_subband(xz, plan, 400)
+    # one channel's removal subtracts exactly its own delayed row
+    y_all = oracle.dedisperse_subband(x, plan, 400)
+    y_one = oracle.dedisperse_subband(x * (np.arange(32) != 3)[:, None].astype(np.uint8), plan, 400)
+    off = plan.offsets[:, 3]
+    for i in range(plan.ndm):
+        assert np.array_equal(y_all[i] - y_one[i], x[3, off[i]:off[i] + 400])
+    assert y.dtype == np.int64
