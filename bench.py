@@ -30,7 +30,9 @@ PAPER_DM_SAMPLES_PER_S = 4096 / 153e-6  # real time on one CPU core, 4096 channe
 
 
 KERNEL_SOURCES = {"stage1": "tx_kernels_dedisp.hip", "stage2": "tx_kernels_dedisp.hip",
-                  "boxcar": "tx_kernels_boxcar.hip"}
+                  "boxcar": "tx_kernels_boxcar.hip", "transpose": "tx_kernels_transpose.hip",
+                  "stats": "tx_kernels_stats.hip", "downsample2": "tx_kernels_downsample.hip",
+                  "downsample4": "tx_kernels_downsample.hip"}
 
 
 def kernel_source_hash(kernel):
@@ -145,7 +147,8 @@ def transpose_leg(torch, tx, nchan, nt, overlap, launches=20):
                         f"into channel rows behind a {overlap}-sample history",
             "bytes_per_launch": nbytes, "avg_ms": avg, "launches": n,
             "achieved_GBps": nbytes / (avg * 1e-3) / 1e9, "peak_GBps": 8000.0,
-            "frac": nbytes / (avg * 1e-3) / 8e12, "matches_torch_transpose": ok}
+            "frac": nbytes / (avg * 1e-3) / 8e12, "matches_torch_transpose": ok,
+            "traffic": load_traffic("transpose", "paper-4096")}
 
 
 def ranges_leg(torch, tx, synth, steps=10):
@@ -199,11 +202,38 @@ def ranges_leg(torch, tx, synth, steps=10):
            "candidates_last_step": [int(c.item()) for c in counts],
            "downsample": {"ms_per_block": ds_per_block, "launches_per_block": ds_n / steps,
                           "bytes_per_block": ds_bytes, "achieved_GBps": ds_bytes / (ds_per_block * 1e-3) / 1e9,
-                          "peak_GBps": 8000.0, "frac": ds_bytes / (ds_per_block * 1e-3) / 8e12}}
+                          "peak_GBps": 8000.0, "frac": ds_bytes / (ds_per_block * 1e-3) / 8e12,
+                          "traffic": [load_traffic("downsample2", "ranges-4096"),
+                                      load_traffic("downsample4", "ranges-4096")]}}
     rg.close()
     del d_in, outs, cands
     torch.cuda.empty_cache()
     return out
+
+
+def stats_leg(torch, tx, nchan, nt, launches=20):
+    """Per-channel power sums (the statistics of the narrow-band RFI mask) of
+    one paper-scale block: a pure read of the block, against HBM peak."""
+    gen = torch.Generator(device="cuda").manual_seed(13)
+    pitch = (nt + 255) // 256 * 256
+    d_in = torch.randint(0, 256, (nchan, pitch), dtype=torch.uint8, device="cuda", generator=gen)
+    sums = torch.empty((nchan, 4), dtype=torch.int64, device="cuda")
+    for _ in range(3):
+        tx.tx_channel_power_sums(d_in, nchan, nt, sums)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        tx.tx_channel_power_sums(d_in, nchan, nt, sums)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    nbytes = nchan * nt
+    del d_in
+    torch.cuda.empty_cache()
+    return {"workload": f"{nchan} channels x {nt} samples (uint8)", "bytes_per_launch": nbytes, "avg_ms": ms,
+            "achieved_GBps": nbytes / (ms * 1e-3) / 1e9, "peak_GBps": 8000.0, "frac": nbytes / (ms * 1e-3) / 8e12,
+            "traffic": load_traffic("stats", "paper-4096")}
 
 
 def cluster_leg(torch, tx, synth, sizes=(1000, 10000, 100000, 1000000), radii=(4.0, 8.0, 16.0), min_pts=5,
@@ -367,6 +397,7 @@ def main():
     ap.add_argument("--no-transpose", action="store_true", help="skip the time-major ingest leg")
     ap.add_argument("--no-ranges", action="store_true", help="skip the multi-range (downsampled) plan leg")
     ap.add_argument("--no-cluster", action="store_true", help="skip the DM-time clustering leg")
+    ap.add_argument("--no-stats", action="store_true", help="skip the channel statistics leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy the DM x time array once (a plain copy of known size "
                          "whose HBM counters scale the kernels' counters)")
@@ -468,6 +499,9 @@ def main():
     if not args.no_transpose:
         out["transpose"] = transpose_leg(torch, tx, nchan, nt, plan.overlap)
         print(f"transpose: {json.dumps(out['transpose'])}", file=sys.stderr, flush=True)
+    if not args.no_stats:
+        out["channel_stats"] = stats_leg(torch, tx, nchan, nt + plan.overlap)
+        print(f"channel_stats: {json.dumps(out['channel_stats'])}", file=sys.stderr, flush=True)
     if not args.no_ranges:
         out["ranges"] = ranges_leg(torch, tx, synth)
         print(f"ranges: {json.dumps(out['ranges'])}", file=sys.stderr, flush=True)
