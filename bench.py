@@ -124,7 +124,7 @@ def transpose_leg(torch, tx, nchan, nt, overlap, launches=20):
     data movement: bytes = read + write of the block, against HBM peak."""
     gen = torch.Generator(device="cuda").manual_seed(11)
     d_tf = torch.randint(0, 256, (nt, nchan), dtype=torch.uint8, device="cuda", generator=gen)
-    off = (overlap + 15) // 16 * 16
+    off = (overlap + 127) // 128 * 128
     pitch = (off + nt + 255) // 256 * 256
     ring = torch.empty((nchan, pitch), dtype=torch.uint8, device="cuda")
     dst = ring[:, off:]

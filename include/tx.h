@@ -463,12 +463,12 @@ tx_status tx_cluster(tx_plan_t plan, const tx_cand* d_cands, int64_t n, double r
 typedef struct tx_stream_s* tx_stream_t;
 
 /* Open a stream for blocks of at most max_block samples.  Allocates one
- * device buffer of nchan rows of overlap + max_block bytes (plus up to 15
+ * device buffer of nchan rows of overlap + max_block bytes (plus up to 127
  * bytes so that the history always ends, and every block is written, at a
- * 16-byte aligned byte; rows rounded up to 256 bytes) on the plan's device.
- * Each push moves the kept history back by the block length (16-byte aligned
+ * 128-byte aligned byte; rows rounded up to 256 bytes) on the plan's device.
+ * Each push moves the kept history back by the block length (128-byte aligned
  * destination; the source is aligned when the block length is a multiple of
- * 16, which makes the device-to-device copies several times faster).  The
+ * 128, which makes the device-to-device copies several times faster).  The
  * first-stage scratch of standalone
  * pushes (tx_dedisperse_ws_size(max_block)) comes from the device's
  * stream-ordered pool on the first push that emits output, and stream jobs of

@@ -154,10 +154,10 @@ struct tx_stream_s {
     int64_t max_block = 0;
     int64_t pitch = 0;                 // bytes per ring row (multiple of 256)
     // Ring row layout: [pad | history | new block].  The history always ends
-    // at byte pad + overlap, a multiple of 16, so every block is written
-    // 16-byte aligned and the history occupies [pad + overlap - held, pad + overlap).
+    // at byte pad + overlap, a multiple of 128, so every block is written at a
+    // cache-line boundary and the history occupies [pad + overlap - held, pad + overlap).
     uint8_t* ring = nullptr;
-    int64_t pad = 0;                   // (16 - overlap % 16) % 16
+    int64_t pad = 0;                   // (128 - overlap % 128) % 128
     int64_t held = 0;                  // valid history samples of every row
     int64_t received = 0, emitted = 0;
     void* ws = nullptr;                // dedispersion scratch of standalone pushes (allocated on first use)

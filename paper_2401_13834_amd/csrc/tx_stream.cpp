@@ -70,15 +70,15 @@ tx_status stream_advance(tx_stream_s* s, int64_t nt, hipStream_t st) {
     if (keep > 0) {
         // Move the last `keep` samples of every row back by nt, so that the
         // history ends at pad + O again (the paper's "shift data").  The copy
-        // is widened at its front to a multiple of 16 bytes, so its
-        // destination starts 16-byte aligned (the extra bytes precede the
+        // is widened at its front to a multiple of 128 bytes, so its
+        // destination covers whole cache lines (the extra bytes precede the
         // history and are never read).  Source and destination overlap when
         // the shift is below the width: then copy forward in pieces no wider
         // than the shift, so no piece overwrites a source byte that a later
         // piece still reads, or, for many pieces, through a transient buffer
         // from the stream-ordered pool.
         const int64_t end = s->pad + O;
-        const int64_t w = (keep + 15) & ~int64_t(15);
+        const int64_t w = (keep + 127) & ~int64_t(127);
         uint8_t* dst = s->ring + (end - w);
         const uint8_t* src = s->ring + (end + nt - w);
         const size_t rows = static_cast<size_t>(s->plan->nchan);
@@ -140,7 +140,7 @@ tx_status tx_stream_open(tx_plan_t plan, int64_t max_block, tx_stream_t* out) {
     s->plan = plan;
     s->device = dev;
     s->max_block = max_block;
-    s->pad = (16 - plan->overlap % 16) % 16;
+    s->pad = (128 - plan->overlap % 128) % 128;
     s->pitch = (s->pad + plan->overlap + max_block + 255) / 256 * 256;
     const size_t bytes = static_cast<size_t>(s->pitch) * plan->nchan;
     const hipError_t e = hipMalloc(reinterpret_cast<void**>(&s->ring), bytes);
