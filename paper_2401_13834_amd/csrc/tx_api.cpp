@@ -139,7 +139,7 @@ void tx::boxcar_fit(tx::BoxcarArgs* a, const int32_t* widths, int32_t nw, int64_
     }
 }
 
-int tx::boxcar_nwt(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 12 ? 12 : n <= 16 ? 16 : 32; }
+int tx::boxcar_nwt(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : n <= 10 ? 10 : n <= 12 ? 12 : n <= 16 ? 16 : 32; }
 
 tx_status tx::check_out_args(const int32_t* d_out, int64_t out_pitch, int64_t nt) {
     if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 7) || (out_pitch & 1) || out_pitch < nt) return TX_EINVAL;

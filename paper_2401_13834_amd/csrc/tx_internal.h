@@ -188,7 +188,7 @@ tx_status boxcar_widths(const int32_t* widths, int32_t nw, int64_t nt, BoxcarArg
 // Effective widths of a row of nt samples (ne, wmax and padding, from the
 // widths given); call after boxcar_widths and whenever nt changes.
 void boxcar_fit(BoxcarArgs* a, const int32_t* widths, int32_t nw, int64_t nt);
-// Widths a boxcar kernel instance handles (4, 8, 12, 16 or 32) for n widths.
+// Widths a boxcar kernel instance handles (4, 8, 10, 12, 16 or 32) for n widths.
 int boxcar_nwt(int n);
 tx_status status_of(hipError_t e);
 // Keep freed stream-ordered scratch in the device's pool (idempotent per device).

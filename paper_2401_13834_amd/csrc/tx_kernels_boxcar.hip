@@ -498,6 +498,7 @@ hipError_t launch_boxcar(const BoxcarArgs& a_in, hipStream_t stream) {
     switch (nwt) {
         case 4: hipLaunchKernelGGL(boxcar_kernel<4>, dim3(grid), dim3(kThreads), lds, stream, a); break;
         case 8: hipLaunchKernelGGL(boxcar_kernel<8>, dim3(grid), dim3(kThreads), lds, stream, a); break;
+        case 10: hipLaunchKernelGGL(boxcar_kernel<10>, dim3(grid), dim3(kThreads), lds, stream, a); break;
         case 12: hipLaunchKernelGGL(boxcar_kernel<12>, dim3(grid), dim3(kThreads), lds, stream, a); break;
         case 16: hipLaunchKernelGGL(boxcar_kernel<16>, dim3(grid), dim3(kThreads), lds, stream, a); break;
         default: hipLaunchKernelGGL(boxcar_kernel<32>, dim3(grid), dim3(kThreads), lds, stream, a); break;
@@ -514,6 +515,7 @@ hipError_t launch_boxcar_batch(int nwt, int lds, const BoxcarArgs* d_jobs, const
     switch (boxcar_nwt(nwt)) {
         case 4: hipLaunchKernelGGL(boxcar_batch_kernel<4>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
         case 8: hipLaunchKernelGGL(boxcar_batch_kernel<8>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
+        case 10: hipLaunchKernelGGL(boxcar_batch_kernel<10>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
         case 12: hipLaunchKernelGGL(boxcar_batch_kernel<12>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
         case 16: hipLaunchKernelGGL(boxcar_batch_kernel<16>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
         default: hipLaunchKernelGGL(boxcar_batch_kernel<32>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
