@@ -6,12 +6,11 @@
 //
 // Both stages are shift-and-add with one shift per (trial, row) that is the
 // same for every lane of a wave: lanes walk the time axis and read one
-// contiguous LDS window per (trial, row).  To make every such read an aligned,
-// bank-conflict-free dword, a staged row is kept in several copies shifted by
-// one element each (4 byte-shifted copies in stage 1, 2 element-shifted copies
-// in stage 2); a per-(row, trial) table gives the byte offset of the copy and
-// word to read.  A workgroup whose rows are too long for that many copies
-// falls back to a single copy and joins neighbouring words with v_alignbyte.
+// contiguous LDS window per (trial, row).  A staged row is kept once, from a
+// 16-byte aligned start; a per-(row, trial) table gives the word to read and
+// the remaining byte (stage 1) or element (stage 2) shift, which v_alignbyte
+// applies to each pair of neighbouring dwords.  Consecutive lanes read
+// consecutive dwords, so the paired reads are bank-conflict free.
 #include <algorithm>
 
 #include "tx_internal.h"
