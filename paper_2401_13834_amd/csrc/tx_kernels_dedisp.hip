@@ -12,6 +12,7 @@
 // applies to each pair of neighbouring dwords.  Consecutive lanes read
 // consecutive dwords, so the paired reads are bank-conflict free.
 #include <algorithm>
+#include <type_traits>
 
 #include "tx_internal.h"
 
@@ -218,12 +219,14 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
 // waves split the time tile and each handles all IW trials.  Lane l of wave w
 // owns the output dwords (two uint16 outputs each) w*64*Q + l + 64 q, so a wave
 // reads consecutive LDS dwords.  Sub-band rows are staged from the chunk's
-// first trial's shift rounded down to 8 elements; a per-(sub-band, trial) table
-// holds the byte offset of the first word and, for an odd element shift, a
-// 2-byte shift that v_alignbyte applies.  Outputs are summed as packed 16-bit
-// lanes of one 32-bit word (sub-bands in pairs through one 3-input add) for
-// `flush` sub-bands (exact: flush * 255 * m < 2^16), then widened into two
-// int32 accumulators.
+// first trial's shift rounded down to 8 elements, twice: as they are and one
+// element later, so that an even element shift reads whole dwords of the first
+// copy and an odd one whole dwords of the second (one aligned 4-byte read per
+// output dword, no byte joins); a per-(sub-band, trial) table holds the byte
+// offset of the trial's first dword.  Outputs are summed as packed 16-bit
+// lanes of one 32-bit word over groups of up to 4 sub-bands (exact while the
+// group is at most `flush` = floor(65535 / (255 m)) sub-bands), and each
+// group's sum is widened into two 32-bit totals.
 // ---------------------------------------------------------------------------
 template <int IW, int Q>
 __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8_t* lds, int* red) {
@@ -251,23 +254,50 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
         sp = max(sp, r[il] - (r[i0] & ~7));
     }
     sp = block_max(sp, red);
-    const int W = ((sp >> 1) + 256 * Q + 1 + 3) & ~3;     // dwords per staged row
+    // A staged row is kept twice: copy 0 from the 8-element aligned start,
+    // copy 1 one element later, so that every trial's window starts at a
+    // dword of one of them (one aligned 4-byte read per output dword).
+    const int W = ((sp >> 1) + 256 * Q + 1 + 3) & ~3;     // dwords per staged copy
     const int rowbytes = 4 * W;
+    const int chb = 2 * rowbytes;
     const int avail = a.lds_bytes - 16;
-    const int nsb = max(1, min(a.nsub, avail / (rowbytes + 4 * IWP)));
+    const int nsb = max(1, min(a.nsub, avail / (chb + 4 * IWP)));
     int32_t* tab = reinterpret_cast<int32_t*>(lds);
     uint8_t* dat = lds + ((nsb * IWP * 4 + 15) & ~15);
 
-    uint32_t acc[IW][Q], lo[IW][Q], hi[IW][Q];
+    // Exact 32-bit sums of the low and high 16-bit outputs of each dword.
+    uint32_t lo[IW][Q], hi[IW][Q];
 #pragma unroll
     for (int ii = 0; ii < IW; ++ii)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc[ii][q] = lo[ii][q] = hi[ii][q] = 0u;
-    int pending = 0;
-    const bool pairs = a.flush >= 2;
-    const int step_max = pairs ? 2 : 1;
+        for (int q = 0; q < Q; ++q) lo[ii][q] = hi[ii][q] = 0u;
     const TX_GLOBAL uint16_t* Bj = to_global(a.B) + static_cast<size_t>(j) * a.nsub * a.B_pitch;
     const int wbase = wave * 64 * Q + lane;
+
+    // G sub-bands of one trial summed as packed 16-bit lanes (exact while
+    // G <= flush), then added to the 32-bit sums.
+    auto group = [&](auto gtag, int r) {
+        constexpr int G = decltype(gtag)::value;
+#pragma unroll
+        for (int ii = 0; ii < IW; ++ii) {
+            const uint32_t* p[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+                p[k] = reinterpret_cast<const uint32_t*>(dat + uniform(tab[(r + k) * IWP + ii])) + wbase;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                uint32_t x[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) x[k] = p[k][64 * q];
+                uint32_t sum;
+                if constexpr (G == 4) sum = (x[0] + x[1] + x[2]) + x[3];
+                else if constexpr (G == 2) sum = x[0] + x[1];
+                else sum = x[0];
+                lo[ii][q] += sum & 0xFFFFu;
+                hi[ii][q] += sum >> 16;
+            }
+        }
+    };
 
     for (int sb = 0; sb < a.nsub; sb += nsb) {
         const int ns = min(nsb, a.nsub - sb);
@@ -275,82 +305,30 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
             const int r = t / IWP, k = t - r * IWP;
             const TX_GLOBAL int32_t* rr = rT + static_cast<size_t>(sb + r) * dp;
             const int e = rr[i0 + min(k, ni - 1)] - (rr[i0] & ~7);
-            tab[t] = r * rowbytes + 2 * e;       // word offset plus a 2-byte shift for odd e
+            tab[t] = r * chb + (e & 1) * rowbytes + 4 * (e >> 1);   // copy (e & 1), dword e / 2
         }
         for (int r = wave; r < ns; r += kWaves) {
             const int s = sb + r;
             const TX_GLOBAL uint16_t* src = Bj + static_cast<size_t>(s) * a.B_pitch + t0 + (rT[static_cast<size_t>(s) * dp + i0] & ~7);
-            uint32_t* dst = reinterpret_cast<uint32_t*>(dat + r * rowbytes);
-            for (int i = lane; 4 * i < W; i += 64)
-                *reinterpret_cast<uint4*>(dst + 4 * i) = *reinterpret_cast<const TX_GLOBAL uint4*>(src + 8 * i);
+            uint32_t* dst0 = reinterpret_cast<uint32_t*>(dat + r * chb);
+            uint32_t* dst1 = dst0 + W;
+            for (int i = lane; 4 * i < W; i += 64) {
+                const uint4 v = *reinterpret_cast<const TX_GLOBAL uint4*>(src + 8 * i);
+                const uint32_t nx = *reinterpret_cast<const TX_GLOBAL uint32_t*>(src + 8 * i + 8);
+                *reinterpret_cast<uint4*>(dst0 + 4 * i) = v;
+                *reinterpret_cast<uint4*>(dst1 + 4 * i) = make_uint4(align_b32(v.y, v.x, 2), align_b32(v.z, v.y, 2),
+                                                                     align_b32(v.w, v.z, 2), align_b32(nx, v.w, 2));
+            }
         }
         __syncthreads();
         int r = 0;
-        while (r < ns) {
-            const int step = (pairs && r + 1 < ns) ? 2 : 1;
-            if (step == 2) {
-                // Reads of trial ii + 1 are issued before the arithmetic of
-                // trial ii (see the first stage).
-                uint32_t ra[2][Q][2], rb[2][Q][2];
-                int e0[IW], e1[IW];
-#pragma unroll
-                for (int ii = 0; ii < IW; ++ii) {
-                    e0[ii] = uniform(tab[r * IWP + ii]);
-                    e1[ii] = uniform(tab[(r + 1) * IWP + ii]);
-                }
-                auto fetch = [&](int ii, int buf) {
-                    const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0[ii] & ~3)) + wbase;
-                    const uint32_t* p1 = reinterpret_cast<const uint32_t*>(dat + (e1[ii] & ~3)) + wbase;
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) {
-                        ra[buf][q][0] = p0[64 * q];
-                        ra[buf][q][1] = p0[64 * q + 1];
-                        rb[buf][q][0] = p1[64 * q];
-                        rb[buf][q][1] = p1[64 * q + 1];
-                    }
-                };
-                fetch(0, 0);
-#pragma unroll
-                for (int ii = 0; ii < IW; ++ii) {
-                    if (ii + 1 < IW) fetch(ii + 1, (ii + 1) & 1);
-                    const int buf = ii & 1;
-#pragma unroll
-                    for (int q = 0; q < Q; ++q)
-                        acc[ii][q] += align_b32(ra[buf][q][1], ra[buf][q][0], e0[ii] & 3) +
-                                      align_b32(rb[buf][q][1], rb[buf][q][0], e1[ii] & 3);
-                }
-            } else {
-#pragma unroll
-                for (int ii = 0; ii < IW; ++ii) {
-                    const int e0 = uniform(tab[r * IWP + ii]);
-                    const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3)) + wbase;
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) acc[ii][q] += align_b32(p0[64 * q + 1], p0[64 * q], e0 & 3);
-                }
-            }
-            pending += step;
-            r += step;
-            if (pending + step_max > a.flush) {
-#pragma unroll
-                for (int ii = 0; ii < IW; ++ii)
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) {
-                        lo[ii][q] += acc[ii][q] & 0xFFFFu;
-                        hi[ii][q] += acc[ii][q] >> 16;
-                        acc[ii][q] = 0u;
-                    }
-                pending = 0;
-            }
-        }
+        if (a.flush >= 4)
+            for (; r + 4 <= ns; r += 4) group(std::integral_constant<int, 4>{}, r);
+        if (a.flush >= 2)
+            for (; r + 2 <= ns; r += 2) group(std::integral_constant<int, 2>{}, r);
+        for (; r < ns; ++r) group(std::integral_constant<int, 1>{}, r);
         __syncthreads();
     }
-#pragma unroll
-    for (int ii = 0; ii < IW; ++ii)
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            lo[ii][q] += acc[ii][q] & 0xFFFFu;
-            hi[ii][q] += acc[ii][q] >> 16;
-        }
 
 #pragma unroll
     for (int ii = 0; ii < IW; ++ii) {
@@ -446,12 +424,13 @@ static const Stage1Variant kS1[] = {{8, 2}, {4, 4}, {4, 2}, {8, 4}, {16, 1}, {16
 static const Stage2Variant kS2[] = {{1}, {2}, {4}};
 constexpr int kNS1 = sizeof(kS1) / sizeof(kS1[0]);
 constexpr int kNS2 = sizeof(kS2) / sizeof(kS2[0]);
-constexpr int kDefaultLds = 32 * 1024;
-// Defaults: the fastest pair at 32 KB on the 4096-channel paper-scale block
-// (first stage 8 output dwords x 4 trials per wavefront, second stage 1024
-// outputs per workgroup); tx_plan_autotune measures per plan.
+constexpr int kDefaultLds = 32 * 1024;    // first stage
+constexpr int kDefaultLds2 = 24 * 1024;   // second stage
+// Defaults: the fastest pair on the 4096-channel paper-scale block (first
+// stage 8 output dwords x 4 trials per wavefront at 32 KB, second stage 512
+// outputs per workgroup at 24 KB); tx_plan_autotune measures per plan.
 constexpr int kDefaultS1 = 3;
-constexpr int kDefaultS2 = 1;
+constexpr int kDefaultS2 = 0;
 
 int stage1_variant_count() { return kNS1; }
 int stage2_variant_count() { return kNS2; }
@@ -498,8 +477,8 @@ DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want) {
     g.lds1 = std::max(g.tiles.s1_lds > 0 ? g.tiles.s1_lds : kDefaultLds, need1);
     const int sp2 = plan_spread2(p, g.iw) + 7;
     const int W2 = ((sp2 >> 1) + 256 * v2.q + 1 + 3) & ~3;
-    const int need2 = 4 * W2 + 4 * iwp + 48;
-    g.lds2 = std::max(g.tiles.s2_lds > 0 ? g.tiles.s2_lds : kDefaultLds, need2);
+    const int need2 = 2 * 4 * W2 + 4 * iwp + 48;   // two copies of a row
+    g.lds2 = std::max(g.tiles.s2_lds > 0 ? g.tiles.s2_lds : kDefaultLds2, need2);
     const int max_lds = device_max_lds();
     g.lds1 = std::min(g.lds1, std::max(need1, max_lds));
     g.lds2 = std::min(g.lds2, std::max(need2, max_lds));
@@ -508,9 +487,10 @@ DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want) {
     g.tiles.s2_lds = g.lds2;
 
     g.n_ttiles2 = static_cast<int32_t>((nt + g.tt2 - 1) / g.tt2);
-    // Stage 2 stages elements [start, start + 2 W) of a series, start <= last
-    // tile start + max extent.
-    const int64_t need = static_cast<int64_t>(std::max(g.n_ttiles2 - 1, 0)) * g.tt2 + p->max_extent + 2 * W2;
+    // Stage 2 stages elements [start, start + 2 W + 2) of a series (the
+    // second copy reads one dword past the first), start <= last tile start +
+    // max extent.
+    const int64_t need = static_cast<int64_t>(std::max(g.n_ttiles2 - 1, 0)) * g.tt2 + p->max_extent + 2 * W2 + 2;
     g.B_pitch = round_up(std::max<int64_t>(need, nt + p->max_extent), g.tt1);
     g.n_ttiles1 = static_cast<int32_t>(g.B_pitch / g.tt1);
     g.n_jchunks = (p->ngroups + g.J1 - 1) / g.J1;
