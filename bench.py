@@ -87,6 +87,15 @@ def cpu_baseline(wl, x, g, seconds):
     if dt < 0.5 * seconds and k < kmax:           # fixed costs made the first estimate short
         k = max(k + 1, min(kmax, int(k * seconds / max(dt, 1e-3))))
         dt, ntrials = run(k)
+    reps = 1
+    if dt < 0.5 * seconds:                        # the whole block is quick: repeat it
+        reps = max(1, int(seconds / max(dt, 1e-3)))
+        total, n = 0.0, 0
+        for _ in range(reps):
+            d1, n1 = run(k)
+            total += d1
+            n += n1
+        dt, ntrials = total, n
     ref = oracle.make_plan(wl.freqs, wl.tsamp, wl.dms[:g], wl.nsub, g=g)
     t = time.perf_counter()
     yn = oracle.dedisperse_subband(x[:, :nt + ref.overlap], ref, nt)
@@ -94,7 +103,8 @@ def cpu_baseline(wl, x, g, seconds):
     oracle.boxcar_candidates(yn, wl.widths, wl.gamma)
     dtn = time.perf_counter() - t
     return {"value": ntrials * nt / dt, "unit": "DM-trial samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"{ntrials} of {len(wl.dms)} DM trials ({k} coarse groups of {g}) x {nt} samples, "
+            "sample": f"{ntrials // reps} of {len(wl.dms)} DM trials ({k} coarse groups of {g}) x {nt} samples"
+                      f"{f', run {reps} times' if reps > 1 else ''}, "
                       f"two-stage dedispersion + peaks + candidates, C oracle with {threads} OpenMP threads, "
                       f"{dt:.1f} s",
             "numpy_oracle_1core": g * nt / dtn}
