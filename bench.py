@@ -474,7 +474,14 @@ def main():
     traffic = load_traffic("stage1", args.workload)
     roofline = {"bound": "alu", "kernel": "stage1", "achieved": round(achieved, 3),
                 "peak": round(PEAK_ADD16 / 1e12, 3), "unit": "Tadd/s", "frac": round(achieved * 1e12 / PEAK_ADD16, 4),
-                "traffic": traffic}
+                "traffic": traffic,
+                # HBM rate of the same launches (counter bytes / event time), against 8 TB/s
+                "hbm_GBps": None if traffic is None else round(traffic / t1 / 1e9, 1),
+                "hbm_frac": None if traffic is None else round(traffic / t1 / 8e12, 4),
+                # the kernel's own binding ceiling: paired 4-byte LDS reads, 2 bytes per add,
+                # at the 110 B/clk/CU measured on this part (2.4 GHz, 256 CUs)
+                "lds_ceiling_Tadd_s": round(110.0 * 256 * 2.4e9 / 2 / 1e12, 2),
+                "lds_ceiling_frac": round(achieved / (110.0 * 256 * 2.4e9 / 2 / 1e12), 4)}
 
     out = {
         "metric": "dedispersed DM-trial samples/s (plain one-beam-per-launch path)",
