@@ -102,7 +102,7 @@ struct BoxcarArgs {
     unsigned long long* count;
 };
 
-// Tile variants (tx_kernels_dedisp.hip).  Stage 1: Q1 dwords (4 outputs each)
+// Tile variants (tx_kernels_dedisp.hip).  Stage 1: Q1 consecutive dwords (odd Q1, 4 outputs each)
 // per lane, JW coarse trials per wave, 4 waves sharing one time tile of
 // 256*Q1 outputs.  Stage 2: Q2 dwords (2 outputs each) per lane, the 4 waves
 // splitting a time tile of 512*Q2 outputs, IW fine trials per workgroup.

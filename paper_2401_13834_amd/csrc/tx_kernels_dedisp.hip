@@ -6,11 +6,12 @@
 //
 // Both stages are shift-and-add with one shift per (trial, row) that is the
 // same for every lane of a wave: lanes walk the time axis and read one
-// contiguous LDS window per (trial, row).  A staged row is kept once, from a
-// 16-byte aligned start; a per-(row, trial) table gives the word to read and
-// the remaining byte (stage 1) or element (stage 2) shift, which v_alignbyte
-// applies to each pair of neighbouring dwords.  Consecutive lanes read
-// consecutive dwords, so the paired reads are bank-conflict free.
+// contiguous LDS window per (trial, row).  A per-(row, trial) table gives the
+// word to read and the remaining byte (stage 1) or copy (stage 2) of the
+// shift.  Stage 1 keeps one copy of a row and joins neighbouring dwords with
+// v_alignbyte; stage 2 keeps two copies, one element apart, and reads whole
+// dwords.  Lane address patterns are chosen so that the 4-byte and paired
+// 4-byte LDS reads are bank-conflict free.
 #include <algorithm>
 #include <type_traits>
 
@@ -66,13 +67,17 @@ __device__ __forceinline__ void load20(const TX_GLOBAL uint8_t* row, int b, int6
 // Stage 1: B[j][s][u] = sum over ch in s of x[ch][u + D(c_j, f_ch)].
 //
 // Workgroup = (sub-band s, J = 4*JW coarse trials, TT = 256*Q outputs); wave w
-// owns trials j0 + w*JW .. + JW-1 and lane l owns the output dwords l + 64 q
-// (4 outputs each), so the lanes of a wave read consecutive LDS dwords (no bank
-// conflicts) and each output dword needs one two-dword LDS read.  Channel rows
-// are staged starting at the row's shift for the first trial, rounded down to
-// 16 bytes; a per-(channel, trial) table holds the byte offset of the first
-// word and the remaining byte shift k.  v_alignbyte picks the 4 input bytes of
-// an output dword, a byte permute picks bytes 1 and 3 into 16-bit lanes.
+// owns trials j0 + w*JW .. + JW-1 and lane l owns the Q consecutive output
+// dwords Q l .. Q l + Q - 1 (4 outputs each).  A lane reads its Q + 1 input
+// dwords of a (channel, trial) as (Q + 1) / 2 paired 4-byte reads from one
+// base; Q is odd, so the lanes' addresses (Q dwords apart) fall in distinct
+// banks.  That is 1 + 1/Q dwords of LDS read per output dword, against 2 when
+// a lane reads words w and w + 1 of every output dword separately.  Channel
+// rows are staged starting at the row's shift for the first trial, rounded
+// down to 16 bytes; a per-(channel, trial) table holds the byte offset of the
+// first word and the remaining byte shift k.  v_alignbyte picks the 4 input
+// bytes of an output dword, a byte permute picks bytes 1 and 3 into 16-bit
+// lanes.
 //
 // "full" accumulates the 4 bytes as one 32-bit word (carries cross bytes) and
 // "odd" accumulates bytes 1 and 3 as two 16-bit lanes; at the end
@@ -147,11 +152,7 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
         }
         __syncthreads();
         const int32_t* tw = tab + wave * JW;
-        // For Q > 4: 1, hidden from the compiler, which would otherwise merge
-        // words w and w + 1 into one read and pay an address add for every
-        // q >= 4 (the paired-read offsets reach 255 words).
-        int one = 1;
-        if (Q > 4) asm volatile("" : "+v"(one));
+        const int lane_b = 4 * Q * lane;   // byte offset of the lane's first dword
         int c = 0;
         for (; c + 1 < nc; c += 2) {
 #pragma unroll
@@ -160,19 +161,18 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
                 const int e1 = uniform(tw[(c + 1) * J + jj]);
                 const uint32_t k0 = static_cast<uint32_t>(e0 & 3), k1 = static_cast<uint32_t>(e1 & 3);
                 const uint32_t sel0 = kOdd + k0 * 0x00010001u, sel1 = kOdd + k1 * 0x00010001u;
-                // Words w and w + 1 through two bases, so that every read is a
-                // multiple of 64 words from its base (one read per two q, with
-                // no per-q address arithmetic).
-                const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3)) + lane;
-                const uint32_t* p1 = reinterpret_cast<const uint32_t*>(dat + (e1 & ~3)) + lane;
-                const uint32_t* p0n = p0 + one;
-                const uint32_t* p1n = p1 + one;
+                const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3) + lane_b);
+                const uint32_t* p1 = reinterpret_cast<const uint32_t*>(dat + (e1 & ~3) + lane_b);
+                uint32_t a[Q + 1], b[Q + 1];
+#pragma unroll
+                for (int q = 0; q <= Q; ++q) {
+                    a[q] = p0[q];
+                    b[q] = p1[q];
+                }
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    const uint32_t a0 = p0[64 * q], a1 = p0n[64 * q];
-                    const uint32_t b0 = p1[64 * q], b1 = p1n[64 * q];
-                    full[jj][q] += align_b32(a1, a0, k0) + align_b32(b1, b0, k1);
-                    odd[jj][q] += perm_b32(a1, a0, sel0) + perm_b32(b1, b0, sel1);
+                    full[jj][q] += align_b32(a[q + 1], a[q], k0) + align_b32(b[q + 1], b[q], k1);
+                    odd[jj][q] += perm_b32(a[q + 1], a[q], sel0) + perm_b32(b[q + 1], b[q], sel1);
                 }
             }
         }
@@ -182,13 +182,14 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
                 const int e0 = uniform(tw[c * J + jj]);
                 const uint32_t k0 = static_cast<uint32_t>(e0 & 3);
                 const uint32_t sel0 = kOdd + k0 * 0x00010001u;
-                const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3)) + lane;
-                const uint32_t* p0n = p0 + one;
+                const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3) + lane_b);
+                uint32_t a[Q + 1];
+#pragma unroll
+                for (int q = 0; q <= Q; ++q) a[q] = p0[q];
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    const uint32_t a0 = p0[64 * q], a1 = p0n[64 * q];
-                    full[jj][q] += align_b32(a1, a0, k0);
-                    odd[jj][q] += perm_b32(a1, a0, sel0);
+                    full[jj][q] += align_b32(a[q + 1], a[q], k0);
+                    odd[jj][q] += perm_b32(a[q + 1], a[q], sel0);
                 }
             }
         }
@@ -205,7 +206,7 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
                 const uint32_t even = full[jj][q] - (odd[jj][q] << 8);
                 const uint32_t w01 = perm_b32(odd[jj][q], even, 0x05040100u);
                 const uint32_t w23 = perm_b32(odd[jj][q], even, 0x07060302u);
-                *reinterpret_cast<TX_GLOBAL uint2*>(out + 4 * (lane + 64 * q)) = make_uint2(w01, w23);
+                *reinterpret_cast<TX_GLOBAL uint2*>(out + 4 * (Q * lane + q)) = make_uint2(w01, w23);
             }
         }
     }
@@ -420,16 +421,17 @@ __global__ __launch_bounds__(kThreads) void stage2_batch_kernel(const Stage2Args
 // ---------------------------------------------------------------------------
 // Variants, geometry and launches.
 // ---------------------------------------------------------------------------
-static const Stage1Variant kS1[] = {{8, 2}, {4, 4}, {4, 2}, {8, 4}, {16, 1}, {16, 2}, {8, 1}};
+static const Stage1Variant kS1[] = {{5, 4}, {7, 4}, {9, 4}, {5, 2}, {7, 2}, {9, 2}, {11, 2}, {13, 1}, {3, 4}};
 static const Stage2Variant kS2[] = {{1}, {2}, {4}};
 constexpr int kNS1 = sizeof(kS1) / sizeof(kS1[0]);
 constexpr int kNS2 = sizeof(kS2) / sizeof(kS2[0]);
 constexpr int kDefaultLds = 32 * 1024;    // first stage
 constexpr int kDefaultLds2 = 24 * 1024;   // second stage
 // Defaults: the fastest pair on the 4096-channel paper-scale block (first
-// stage 8 output dwords x 4 trials per wavefront at 32 KB, second stage 512
-// outputs per workgroup at 24 KB); tx_plan_autotune measures per plan.
-constexpr int kDefaultS1 = 3;
+// stage 7 output dwords per lane x 4 trials per wavefront at 32 KB, second
+// stage 512 outputs per workgroup at 24 KB); tx_plan_autotune measures per
+// plan.  First-stage Q is odd (bank-conflict-free lane stride).
+constexpr int kDefaultS1 = 1;
 constexpr int kDefaultS2 = 0;
 
 int stage1_variant_count() { return kNS1; }
@@ -534,7 +536,8 @@ struct KernelPair {
     const void* batch;
 };
 #define TX_S1(Q, JW) {reinterpret_cast<const void*>(&stage1_kernel<Q, JW>), reinterpret_cast<const void*>(&stage1_batch_kernel<Q, JW>)}
-static const KernelPair kS1Fn[kNS1] = {TX_S1(8, 2), TX_S1(4, 4), TX_S1(4, 2), TX_S1(8, 4), TX_S1(16, 1), TX_S1(16, 2), TX_S1(8, 1)};
+static const KernelPair kS1Fn[kNS1] = {TX_S1(5, 4), TX_S1(7, 4), TX_S1(9, 4), TX_S1(5, 2), TX_S1(7, 2),
+                                        TX_S1(9, 2), TX_S1(11, 2), TX_S1(13, 1), TX_S1(3, 4)};
 #undef TX_S1
 static const int kIW[] = {16, 13, 8, 4, 2, 1};
 constexpr int kNIW = 6;
