@@ -27,6 +27,20 @@ __device__ __forceinline__ uint32_t align_b32(uint32_t hi, uint32_t lo, uint32_t
 }
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// s_waitcnt operand for "vector memory count 0", other counters untouched
+// (vmcnt bits 3:0 and 15:14 zero, expcnt 6:4 = 7, lgkmcnt 11:8 = 15).
+constexpr int kWaitVm0 = 0x0F70;
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint64_t>(v)), l);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint64_t>(v) >> 32), l);
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ __attribute__((address_space(3))) void* to_lds(uint8_t* p) {
+    return (__attribute__((address_space(3))) void*)(p);
+}
+
 // Consecutive workgroup ids are dealt round-robin to the 8 XCDs; give each XCD
 // a contiguous range of tiles so that tiles sharing input rows share an L2.
 __device__ __forceinline__ int xcd_tile(int bid, int total) {
@@ -116,10 +130,68 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
     sp = block_max(sp, red);
     const int W = ((sp >> 2) + 64 * Q + 1 + 3) & ~3;      // dwords per staged row
     const int rowbytes = 4 * W;
-    const int avail = a.lds_bytes - 16;
+    // Two staging buffers where two rows fit: round r + 1's rows load while
+    // round r is summed.  Otherwise one, staged between two barriers.
+    const int nbuf = 2 * (rowbytes + 4 * J) + 32 <= a.lds_bytes ? 2 : 1;
+    const int avail = (a.lds_bytes - 32) / nbuf;
     const int nch = max(1, min(a.m, avail / (rowbytes + 4 * J)));
-    int32_t* tab = reinterpret_cast<int32_t*>(lds);
-    uint8_t* dat = lds + ((nch * J * 4 + 15) & ~15);
+    const int tab_bytes = (nch * J * 4 + 15) & ~15;
+    const int buf_bytes = tab_bytes + nch * rowbytes;
+
+    // Stage channels [cb, cb + nch) into `buf`: their (channel, trial) table
+    // and their rows.  Whole 16-byte pieces of a row go from global memory
+    // straight to LDS (global_load_lds: no registers, completes in the
+    // background; a wave's 64 pieces land at consecutive 16-byte slots of one
+    // 1 KB span); pieces that reach past the row's end, and dropped channels,
+    // go through registers with zeros past the end.
+    auto stage = [&](int cb, uint8_t* buf) {
+        const int nc = min(nch, a.m - cb);
+        int32_t* tab = reinterpret_cast<int32_t*>(buf);
+        uint8_t* dat = buf + tab_bytes;
+        for (int t = tid; t < nc * J; t += kThreads) {
+            const int c = t / J, k = t - c * J;
+            const TX_GLOBAL int32_t* r = dT + static_cast<size_t>(ch0 + cb + c) * gp;
+            const int sh = (r[min(j0 + k, jl)] + xo) - ((r[j0] + xo) & ~15);
+            tab[t] = c * rowbytes + sh;          // word offset (sh & ~3) plus byte shift (sh & 3)
+        }
+        // Rows: wave w stages rows w, w + 4, ...  Lane l first fetches the
+        // start and valid length of row c0 + 4 l, so that the row loop waits
+        // on no memory (a wait would also wait for the background loads).
+        for (int c0 = wave; c0 < nc; c0 += kWaves * 64) {
+            const int cr = c0 + kWaves * lane;
+            int64_t st = 0, av = 0;
+            if (cr < nc) {
+                const int ch = ch0 + cb + cr;
+                st = static_cast<int64_t>(u0) + ((dT[static_cast<size_t>(ch) * gp + j0] + xo) & ~15);
+                // A dropped channel is staged as zeros (weight 0 in every sum).
+                const bool keep = !a.mask || to_global(a.mask)[ch] != 0;
+                av = keep ? a.x_len + xo - st : 0;
+            }
+            const int nr = min(64, (nc - c0 + kWaves - 1) / kWaves);
+            for (int rr = 0; rr < nr; ++rr) {
+            const int c = c0 + kWaves * rr;
+            const int ch = ch0 + cb + c;
+            const int64_t start = readlane64(st, rr);
+            const int64_t avail_b = readlane64(av, rr);
+            const TX_GLOBAL uint8_t* row = to_global(a.x) + static_cast<size_t>(ch) * a.x_pitch + start;
+            uint8_t* dst = dat + c * rowbytes;
+            for (int k = 0; 256 * k < W; ++k) {
+                const int i = lane + 64 * k;     // 16-byte piece of the row
+                if (4 * i < W) {
+                    if (16 * static_cast<int64_t>(i) + 16 <= avail_b) {
+                        __builtin_amdgcn_global_load_lds(
+                            reinterpret_cast<const TX_GLOBAL void*>(row + 16 * i),
+                            to_lds(dst + 1024 * k), 16, 0, 0);
+                    } else {
+                        uint32_t d[5];
+                        load20(row, 16 * i, avail_b, d);
+                        *reinterpret_cast<uint4*>(dst + 16 * i) = make_uint4(d[0], d[1], d[2], d[3]);
+                    }
+                }
+            }
+            }
+        }
+    };
 
     uint32_t full[JW][Q], odd[JW][Q];
 #pragma unroll
@@ -127,30 +199,17 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
 #pragma unroll
         for (int q = 0; q < Q; ++q) full[jj][q] = odd[jj][q] = 0u;
 
-    for (int cb = 0; cb < a.m; cb += nch) {
+    stage(0, lds);
+    for (int cb = 0, r = 0; cb < a.m; cb += nch, ++r) {
         const int nc = min(nch, a.m - cb);
-        for (int t = tid; t < nc * J; t += kThreads) {
-            const int c = t / J, k = t - c * J;
-            const TX_GLOBAL int32_t* r = dT + static_cast<size_t>(ch0 + cb + c) * gp;
-            const int sh = (r[min(j0 + k, jl)] + xo) - ((r[j0] + xo) & ~15);
-            tab[t] = c * rowbytes + sh;          // word offset (sh & ~3) plus byte shift (sh & 3)
-        }
-        // Rows: wave w stages rows w, w + 4, ...
-        for (int c = wave; c < nc; c += kWaves) {
-            const int ch = ch0 + cb + c;
-            const int64_t start = static_cast<int64_t>(u0) + ((dT[static_cast<size_t>(ch) * gp + j0] + xo) & ~15);
-            const TX_GLOBAL uint8_t* row = to_global(a.x) + static_cast<size_t>(ch) * a.x_pitch + start;
-            // A dropped channel is staged as zeros (weight 0 in every sum).
-            const bool keep = !a.mask || to_global(a.mask)[ch] != 0;
-            const int64_t avail_b = keep ? a.x_len + xo - start : 0;
-            uint32_t* dst = reinterpret_cast<uint32_t*>(dat + c * rowbytes);
-            for (int i = lane; 4 * i < W; i += 64) {
-                uint32_t d[5];
-                load20(row, 16 * i, avail_b, d);
-                *reinterpret_cast<uint4*>(dst + 4 * i) = make_uint4(d[0], d[1], d[2], d[3]);
-            }
-        }
+        uint8_t* cur = lds + (r & (nbuf - 1)) * buf_bytes;
+        // This wave's background loads into `cur` are done; after the barrier
+        // every wave's are, and nobody still reads the other buffer.
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
         __syncthreads();
+        if (nbuf == 2 && cb + nch < a.m) stage(cb + nch, lds + ((r + 1) & 1) * buf_bytes);
+        const int32_t* tab = reinterpret_cast<const int32_t*>(cur);
+        const uint8_t* dat = cur + tab_bytes;
         const int32_t* tw = tab + wave * JW;
         const int lane_b = 4 * Q * lane;   // byte offset of the lane's first dword
         int c = 0;
@@ -193,22 +252,37 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
                 }
             }
         }
-        __syncthreads();
+        if (nbuf == 1 && cb + nch < a.m) {
+            __syncthreads();
+            stage(cb + nch, lds);
+        }
     }
 
+    // Outputs: a lane's Q output dwords are consecutive, so it would store
+    // 8 bytes at a stride of 8 Q bytes.  Each wave passes a trial's sums
+    // through its own LDS span instead, and stores them as whole contiguous
+    // 512-byte runs.
+    uint8_t* wb = lds + wave * (512 * Q);
+    __syncthreads();
 #pragma unroll
     for (int jj = 0; jj < JW; ++jj) {
         const int j = j0 + wave * JW + jj;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const uint32_t even = full[jj][q] - (odd[jj][q] << 8);
+            const uint32_t w01 = perm_b32(odd[jj][q], even, 0x05040100u);
+            const uint32_t w23 = perm_b32(odd[jj][q], even, 0x07060302u);
+            *reinterpret_cast<uint2*>(wb + 8 * (Q * lane + q)) = make_uint2(w01, w23);
+        }
+        __syncthreads();
         if (j <= jl) {
             TX_GLOBAL uint16_t* out = to_global(a.B) + (static_cast<size_t>(j) * a.nsub + s) * a.B_pitch + u0;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const uint32_t even = full[jj][q] - (odd[jj][q] << 8);
-                const uint32_t w01 = perm_b32(odd[jj][q], even, 0x05040100u);
-                const uint32_t w23 = perm_b32(odd[jj][q], even, 0x07060302u);
-                *reinterpret_cast<TX_GLOBAL uint2*>(out + 4 * (Q * lane + q)) = make_uint2(w01, w23);
-            }
+            for (int q = 0; q < Q; ++q)
+                *reinterpret_cast<TX_GLOBAL uint2*>(out + 4 * (lane + 64 * q)) =
+                    *reinterpret_cast<const uint2*>(wb + 8 * (lane + 64 * q));
         }
+        __syncthreads();
     }
 }
 
@@ -428,10 +502,10 @@ constexpr int kNS2 = sizeof(kS2) / sizeof(kS2[0]);
 constexpr int kDefaultLds = 32 * 1024;    // first stage
 constexpr int kDefaultLds2 = 24 * 1024;   // second stage
 // Defaults: the fastest pair on the 4096-channel paper-scale block (first
-// stage 7 output dwords per lane x 4 trials per wavefront at 32 KB, second
+// stage 9 output dwords per lane x 4 trials per wavefront at 32 KB, second
 // stage 512 outputs per workgroup at 24 KB); tx_plan_autotune measures per
 // plan.  First-stage Q is odd (bank-conflict-free lane stride).
-constexpr int kDefaultS1 = 1;
+constexpr int kDefaultS1 = 2;
 constexpr int kDefaultS2 = 0;
 
 int stage1_variant_count() { return kNS1; }
@@ -472,10 +546,11 @@ DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want) {
     g.iw = pick_iw(p->g);
     const int iwp = (g.iw + 3) & ~3;
 
-    // LDS: at least one single-copy row per workgroup.
+    // LDS: at least one row (and its table) per workgroup; stage 1 double
+    // buffers when two fit in its LDS size.
     const int sp1 = plan_spread1(p, g.J1) + 15;
     const int W1 = ((sp1 >> 2) + 64 * v1.q + 1 + 3) & ~3;
-    const int need1 = 4 * W1 + 4 * g.J1 + 48;
+    const int need1 = std::max(4 * W1 + 4 * g.J1 + 48, kWaves * 512 * v1.q);   // rows; output pass
     g.lds1 = std::max(g.tiles.s1_lds > 0 ? g.tiles.s1_lds : kDefaultLds, need1);
     const int sp2 = plan_spread2(p, g.iw) + 7;
     const int W2 = ((sp2 >> 1) + 256 * v2.q + 1 + 3) & ~3;
