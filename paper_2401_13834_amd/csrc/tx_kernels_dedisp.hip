@@ -292,8 +292,10 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
 //
 // Workgroup = (group j, IW of its fine trials, TT = 512*Q outputs); the 4
 // waves split the time tile and each handles all IW trials.  Lane l of wave w
-// owns the output dwords (two uint16 outputs each) w*64*Q + l + 64 q, so a wave
-// reads consecutive LDS dwords.  Sub-band rows are staged from the chunk's
+// owns the Q consecutive output dwords (two uint16 outputs each) from
+// w*64*Q + Q l, so one address add per (sub-band, trial) serves Q reads, which
+// pair into 8-byte reads; Q is odd, so the lanes' addresses fall in distinct
+// banks.  Sub-band rows are staged from the chunk's
 // first trial's shift rounded down to 8 elements, twice: as they are and one
 // element later, so that an even element shift reads whole dwords of the first
 // copy and an odd one whole dwords of the second (one aligned 4-byte read per
@@ -347,7 +349,7 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
 #pragma unroll
         for (int q = 0; q < Q; ++q) lo[ii][q] = hi[ii][q] = 0u;
     const TX_GLOBAL uint16_t* Bj = to_global(a.B) + static_cast<size_t>(j) * a.nsub * a.B_pitch;
-    const int wbase = wave * 64 * Q + lane;
+    const int wbase = wave * 64 * Q + Q * lane;   // the lane's first output dword
 
     // G sub-bands of one trial summed as packed 16-bit lanes (exact while
     // G <= flush), then added to the 32-bit sums.
@@ -363,7 +365,7 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
             for (int q = 0; q < Q; ++q) {
                 uint32_t x[G];
 #pragma unroll
-                for (int k = 0; k < G; ++k) x[k] = p[k][64 * q];
+                for (int k = 0; k < G; ++k) x[k] = p[k][q];
                 uint32_t sum;
                 if constexpr (G == 4) sum = (x[0] + x[1] + x[2]) + x[3];
                 else if constexpr (G == 2) sum = x[0] + x[1];
@@ -405,21 +407,33 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
         __syncthreads();
     }
 
+    // Outputs: with Q > 1 a lane's output pairs are consecutive, so its
+    // stores would be 8 bytes at a stride of 8 Q bytes; each wave passes a
+    // trial's sums through its own LDS span and stores contiguous runs.
+    uint8_t* wb = lds + wave * (512 * Q);
 #pragma unroll
     for (int ii = 0; ii < IW; ++ii) {
+        if (Q > 1) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) *reinterpret_cast<uint2*>(wb + 8 * (Q * lane + q)) = make_uint2(lo[ii][q], hi[ii][q]);
+            __syncthreads();
+        }
         if (ii < ni) {
             TX_GLOBAL int32_t* out = to_global(a.Y) + static_cast<size_t>(i0 + ii) * a.y_pitch;
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                const int64_t t = t0 + 2 * static_cast<int64_t>(wbase + 64 * q);
+                const int64_t t = t0 + 2 * static_cast<int64_t>(wave * 64 * Q + lane + 64 * q);
+                const uint2 v = Q > 1 ? *reinterpret_cast<const uint2*>(wb + 8 * (lane + 64 * q))
+                                      : make_uint2(lo[ii][q], hi[ii][q]);
                 if (t + 1 < a.nt) {
                     *reinterpret_cast<TX_GLOBAL int2*>(out + t) =
-                        make_int2(static_cast<int32_t>(lo[ii][q]), static_cast<int32_t>(hi[ii][q]));
+                        make_int2(static_cast<int32_t>(v.x), static_cast<int32_t>(v.y));
                 } else if (t < a.nt) {
-                    out[t] = static_cast<int32_t>(lo[ii][q]);
+                    out[t] = static_cast<int32_t>(v.x);
                 }
             }
         }
+        if (Q > 1) __syncthreads();
     }
 }
 
@@ -496,17 +510,17 @@ __global__ __launch_bounds__(kThreads) void stage2_batch_kernel(const Stage2Args
 // Variants, geometry and launches.
 // ---------------------------------------------------------------------------
 static const Stage1Variant kS1[] = {{5, 4}, {7, 4}, {9, 4}, {5, 2}, {7, 2}, {9, 2}, {11, 2}, {13, 1}, {3, 4}};
-static const Stage2Variant kS2[] = {{1}, {2}, {4}};
+static const Stage2Variant kS2[] = {{1}, {3}, {5}};
 constexpr int kNS1 = sizeof(kS1) / sizeof(kS1[0]);
 constexpr int kNS2 = sizeof(kS2) / sizeof(kS2[0]);
 constexpr int kDefaultLds = 32 * 1024;    // first stage
-constexpr int kDefaultLds2 = 24 * 1024;   // second stage
+constexpr int kDefaultLds2 = 32 * 1024;   // second stage
 // Defaults: the fastest pair on the 4096-channel paper-scale block (first
 // stage 9 output dwords per lane x 4 trials per wavefront at 32 KB, second
-// stage 512 outputs per workgroup at 24 KB); tx_plan_autotune measures per
-// plan.  First-stage Q is odd (bank-conflict-free lane stride).
+// stage 3 output dwords per lane at 32 KB); tx_plan_autotune measures per
+// plan.  Q is odd in both stages (bank-conflict-free lane stride).
 constexpr int kDefaultS1 = 2;
-constexpr int kDefaultS2 = 0;
+constexpr int kDefaultS2 = 1;
 
 int stage1_variant_count() { return kNS1; }
 int stage2_variant_count() { return kNS2; }
@@ -554,7 +568,7 @@ DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want) {
     g.lds1 = std::max(g.tiles.s1_lds > 0 ? g.tiles.s1_lds : kDefaultLds, need1);
     const int sp2 = plan_spread2(p, g.iw) + 7;
     const int W2 = ((sp2 >> 1) + 256 * v2.q + 1 + 3) & ~3;
-    const int need2 = 2 * 4 * W2 + 4 * iwp + 48;   // two copies of a row
+    const int need2 = std::max(2 * 4 * W2 + 4 * iwp + 48, kWaves * 512 * v2.q);   // two copies of a row; output pass
     g.lds2 = std::max(g.tiles.s2_lds > 0 ? g.tiles.s2_lds : kDefaultLds2, need2);
     const int max_lds = device_max_lds();
     g.lds1 = std::min(g.lds1, std::max(need1, max_lds));
@@ -617,7 +631,7 @@ static const KernelPair kS1Fn[kNS1] = {TX_S1(5, 4), TX_S1(7, 4), TX_S1(9, 4), TX
 static const int kIW[] = {16, 13, 8, 4, 2, 1};
 constexpr int kNIW = 6;
 #define TX_S2(IW, Q) {reinterpret_cast<const void*>(&stage2_kernel<IW, Q>), reinterpret_cast<const void*>(&stage2_batch_kernel<IW, Q>)}
-#define TX_S2Q(IW) TX_S2(IW, 1), TX_S2(IW, 2), TX_S2(IW, 4)
+#define TX_S2Q(IW) TX_S2(IW, 1), TX_S2(IW, 3), TX_S2(IW, 5)
 static const KernelPair kS2Fn[kNIW * kNS2] = {TX_S2Q(16), TX_S2Q(13), TX_S2Q(8), TX_S2Q(4), TX_S2Q(2), TX_S2Q(1)};
 #undef TX_S2Q
 #undef TX_S2
