@@ -472,16 +472,25 @@ def main():
     t1 = kern["stage1"]["avg_ms"] * 1e-3
     achieved = adds1 / t1 / 1e12
     traffic = load_traffic("stage1", args.workload)
+    # The first stage's inner loop, per 4 byte-adds of one channel: 3 VALU ops
+    # (byte align, byte permute, half of each of two 3-input adds) and
+    # (Q + 1) / Q 4-byte LDS reads issued as paired reads (Q = output dwords
+    # per lane of the tile variant in use).  Its two ceilings: 256 CUs x 4
+    # SIMDs x 16 lanes x 2.4 GHz lane-ops at 4/3 adds each, and paired LDS
+    # reads at the 110 B/clk/CU measured on this part.
+    q1 = tx.tx_tile_variants(1)[plan.resolved_tiles(nt)[0]][0] // 256
+    valu_ceiling = 256 * 4 * 16 * 2.4e9 * 4 / 3 / 1e12
+    lds_ceiling = 110.0 * 256 * 2.4e9 / ((q1 + 1) / q1) / 1e12
+    loop_ceiling = min(valu_ceiling, lds_ceiling)
     roofline = {"bound": "alu", "kernel": "stage1", "achieved": round(achieved, 3),
                 "peak": round(PEAK_ADD16 / 1e12, 3), "unit": "Tadd/s", "frac": round(achieved * 1e12 / PEAK_ADD16, 4),
                 "traffic": traffic,
                 # HBM rate of the same launches (counter bytes / event time), against 8 TB/s
                 "hbm_GBps": None if traffic is None else round(traffic / t1 / 1e9, 1),
                 "hbm_frac": None if traffic is None else round(traffic / t1 / 8e12, 4),
-                # the kernel's own binding ceiling: paired 4-byte LDS reads, 2 bytes per add,
-                # at the 110 B/clk/CU measured on this part (2.4 GHz, 256 CUs)
-                "lds_ceiling_Tadd_s": round(110.0 * 256 * 2.4e9 / 2 / 1e12, 2),
-                "lds_ceiling_frac": round(achieved / (110.0 * 256 * 2.4e9 / 2 / 1e12), 4)}
+                "loop_ceiling_Tadd_s": round(loop_ceiling, 2),
+                "loop_bound": "valu" if valu_ceiling <= lds_ceiling else "lds",
+                "loop_ceiling_frac": round(achieved / loop_ceiling, 4)}
 
     out = {
         "metric": "dedispersed DM-trial samples/s (plain one-beam-per-launch path)",

@@ -338,6 +338,12 @@ tx_status tx_tile_variant_info(int32_t stage, int32_t variant, int32_t* outputs_
 tx_status tx_plan_get_tiles(tx_plan_t plan, tx_tiles* tiles);
 tx_status tx_plan_set_tiles(tx_plan_t plan, const tx_tiles* tiles);
 
+/* The tiles a dedispersion of nt outputs with this plan launches with: the
+ * plan's choice with defaults resolved (variant indices >= 0, LDS bytes as
+ * raised to what the staged rows need).  Launches nothing; TX_EINVAL for
+ * nt < 0. */
+tx_status tx_plan_resolved_tiles(tx_plan_t plan, int64_t nt, tx_tiles* tiles);
+
 /*
  * Autotuner: time every first-stage variant with the default second stage,
  * then every second-stage variant with the fastest first stage, dedispersing

@@ -87,6 +87,7 @@ _SIGS = {
     "tx_tile_variant_info": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32)]),
     "tx_plan_get_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tx_plan_resolved_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "tx_plan_set_tiles": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "tx_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "tx_profile_collect": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -199,6 +200,13 @@ class Plan:
     def get_tiles(self):
         t = Tiles()
         _check(lib().tx_plan_get_tiles(self._h, ctypes.byref(t)), "tx_plan_get_tiles")
+        return (t.stage1, t.stage1_lds, t.stage2, t.stage2_lds)
+
+    def resolved_tiles(self, nt):
+        """(stage1, stage1_lds, stage2, stage2_lds) a dedispersion of ``nt``
+        outputs launches with, defaults resolved."""
+        t = Tiles()
+        _check(lib().tx_plan_resolved_tiles(self._h, int(nt), ctypes.byref(t)), "tx_plan_resolved_tiles")
         return (t.stage1, t.stage1_lds, t.stage2, t.stage2_lds)
 
     def set_tiles(self, stage1=-1, stage1_lds=0, stage2=-1, stage2_lds=0):

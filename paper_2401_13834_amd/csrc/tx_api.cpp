@@ -375,6 +375,16 @@ tx_status tx_plan_get_tiles(tx_plan_t p, tx_tiles* t) {
     return TX_OK;
 }
 
+tx_status tx_plan_resolved_tiles(tx_plan_t p, int64_t nt, tx_tiles* t) {
+    if (!p || !t || nt < 0) return TX_EINVAL;
+    const tx::Tiles c = tx::dedisp_geometry(p, nt, current_tiles(p)).tiles;
+    t->stage1 = c.s1;
+    t->stage1_lds = c.s1_lds;
+    t->stage2 = c.s2;
+    t->stage2_lds = c.s2_lds;
+    return TX_OK;
+}
+
 tx_status tx_plan_set_tiles(tx_plan_t p, const tx_tiles* t) {
     if (!p || !t) return TX_EINVAL;
     if (t->stage1 < -1 || t->stage1 >= tx::stage1_variant_count()) return TX_EINVAL;

@@ -120,6 +120,22 @@ def test_device_calls_on_host_only_plan_are_refused():
         p.delays(-1.0)
 
 
+def test_resolved_tiles():
+    # Defaults resolve to real variant indices and LDS sizes; an explicit
+    # choice comes back as set, its LDS raised to what the rows need.
+    wl = synth.workload("paper-4096")
+    p = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub, host_only=True)
+    assert p.get_tiles() == (-1, 0, -1, 0)
+    s1, l1, s2, l2 = p.resolved_tiles(wl.nt)
+    assert 0 <= s1 < len(tx.tx_tile_variants(1)) and 0 <= s2 < len(tx.tx_tile_variants(2))
+    assert l1 > 0 and l2 > 0
+    p.set_tiles(0, 1024, 0, 1024)
+    r = p.resolved_tiles(wl.nt)
+    assert r[0] == 0 and r[2] == 0 and r[1] > 1024 and r[3] > 1024
+    with pytest.raises(tx.TxError):
+        p.resolved_tiles(-1)
+
+
 def test_tune_cache_roundtrip(tmp_path):
     from paper_2401_13834_amd import tune
     f = synth.band_centres(1712.0, 856.0, 64)
