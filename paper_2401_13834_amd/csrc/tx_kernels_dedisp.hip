@@ -351,27 +351,53 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
     const TX_GLOBAL uint16_t* Bj = to_global(a.B) + static_cast<size_t>(j) * a.nsub * a.B_pitch;
     const int wbase = wave * 64 * Q + Q * lane;   // the lane's first output dword
 
-    // G sub-bands of one trial summed as packed 16-bit lanes (exact while
-    // G <= flush), then added to the 32-bit sums.
+    // G sub-bands of each trial summed as packed 16-bit lanes (exact while
+    // G <= flush), then added to the 32-bit sums.  Software-pipelined over
+    // the trials: trial ii + 1's words are read while trial ii is summed, and
+    // the table entries of trial ii + 2 while those words are in flight, so
+    // the one wait per trial finds its data already there.
     auto group = [&](auto gtag, int r) {
         constexpr int G = decltype(gtag)::value;
+        uint32_t xc[G][Q], xn[G][Q];
+        int tn[G];                                   // table entries (uniform) of the next trial to read
+        auto tab_read = [&](int ii) {
+#pragma unroll
+            for (int k = 0; k < G; ++k) tn[k] = tab[(r + k) * IWP + ii];
+        };
+        auto fetch = [&](uint32_t (&x)[G][Q]) {
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const uint32_t* p = reinterpret_cast<const uint32_t*>(dat + uniform(tn[k])) + wbase;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) x[k][q] = p[q];
+            }
+        };
+        tab_read(0);
+        fetch(xc);
+        if (IW > 1) tab_read(1);
 #pragma unroll
         for (int ii = 0; ii < IW; ++ii) {
-            const uint32_t* p[G];
-#pragma unroll
-            for (int k = 0; k < G; ++k)
-                p[k] = reinterpret_cast<const uint32_t*>(dat + uniform(tab[(r + k) * IWP + ii])) + wbase;
+            if (ii + 1 < IW) {
+                fetch(xn);
+                if (ii + 2 < IW) tab_read(ii + 2);
+            }
+            // Keep the compiler from sinking the reads below the adds.
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                uint32_t x[G];
-#pragma unroll
-                for (int k = 0; k < G; ++k) x[k] = p[k][q];
                 uint32_t sum;
-                if constexpr (G == 4) sum = (x[0] + x[1] + x[2]) + x[3];
-                else if constexpr (G == 2) sum = x[0] + x[1];
-                else sum = x[0];
+                if constexpr (G == 4) sum = (xc[0][q] + xc[1][q] + xc[2][q]) + xc[3][q];
+                else if constexpr (G == 2) sum = xc[0][q] + xc[1][q];
+                else sum = xc[0][q];
                 lo[ii][q] += sum & 0xFFFFu;
                 hi[ii][q] += sum >> 16;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (ii + 1 < IW) {
+#pragma unroll
+                for (int k = 0; k < G; ++k)
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) xc[k][q] = xn[k][q];
             }
         }
     };

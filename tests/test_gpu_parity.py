@@ -310,7 +310,7 @@ def test_all_tile_variants_match_oracle(case):
     n1 = len(tx.tx_tile_variants(1))
     n2 = len(tx.tx_tile_variants(2))
     combos = [(s1, l1, 0, 0) for s1 in range(n1) for l1 in (0, 8192, 16384)]
-    combos += [(0, 0, s2, l2) for s2 in range(n2) for l2 in (0, 8192)]
+    combos += [(0, 0, s2, l2) for s2 in range(n2) for l2 in (0, 8192, 24576, 65536)]
     for s1, l1, s2, l2 in combos:
         _say(f"  tiles {s1} {l1} {s2} {l2}")
         plan.set_tiles(s1, l1, s2, l2)
