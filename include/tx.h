@@ -348,7 +348,9 @@ tx_status tx_plan_resolved_tiles(tx_plan_t plan, int64_t nt, tx_tiles* tiles);
  * Autotuner: time every first-stage variant with the default second stage,
  * then every second-stage variant with the fastest first stage, dedispersing
  * a scratch block of nt outputs of the plan's shape on `stream` (effort 0:
- * default LDS sizes; 1: also 16, 24, 32 and 48 KB per workgroup), and store
+ * default LDS sizes; 1: instead the sizes that fit 7, 6, 5, 4 and 3
+ * workgroups in a 160 KB CU: 23392, 27296, 32768, 40960 and 54608 bytes per
+ * workgroup), and store
  * the fastest pair in the plan as tx_plan_set_tiles would.  Scratch comes
  * from the device's stream-ordered pool; the call synchronises `stream`
  * (not for use under graph capture).  *best_ms (may be NULL) receives the

@@ -29,22 +29,26 @@ extern "C" tx_status tx_plan_autotune(tx_plan_t p, int64_t nt, int32_t effort, d
     if (st != TX_OK) return st;
 
     std::vector<int> ldss = {0};
-    if (effort >= 1) ldss = {16 * 1024, 24 * 1024, 32 * 1024, 48 * 1024};
+    // LDS sizes at the workgroups-per-CU steps of a 160 KB CU: 7, 6, 5, 4, 3.
+    if (effort >= 1) ldss = {23392, 27296, 32768, 40960, 54608};
     std::vector<tx::Tiles> s1c, s2c;
     for (int v = 0; v < tx::stage1_variant_count(); ++v)
         for (int l : ldss) s1c.push_back(tx::Tiles{v, l, -1, 0});
     for (int v = 0; v < tx::stage2_variant_count(); ++v)
         for (int l : ldss) s2c.push_back(tx::Tiles{-1, 0, v, l});
 
-    // Scratch sized for the largest geometry of any candidate.
+    // Scratch sized for the largest geometry of any pair that can run: every
+    // first-stage candidate with the default second stage, then the chosen
+    // first stage (any of them) with every second-stage candidate.  The
+    // first-stage series' pitch depends on both stages' tiles.
     int64_t ws_bytes = 0;
-    for (const auto& c : s1c) {
-        const tx::DedispGeom g = tx::dedisp_geometry(p, nt, c);
+    for (const auto& c1 : s1c) {
+        tx::DedispGeom g = tx::dedisp_geometry(p, nt, c1);
         if (g.ok) ws_bytes = std::max(ws_bytes, g.ws_bytes);
-    }
-    for (const auto& c : s2c) {
-        const tx::DedispGeom g = tx::dedisp_geometry(p, nt, c);
-        if (g.ok) ws_bytes = std::max(ws_bytes, g.ws_bytes);
+        for (const auto& c2 : s2c) {
+            g = tx::dedisp_geometry(p, nt, tx::Tiles{c1.s1, c1.s1_lds, c2.s2, c2.s2_lds});
+            if (g.ok) ws_bytes = std::max(ws_bytes, g.ws_bytes);
+        }
     }
     const int64_t in_pitch = (nt + p->overlap + 255) / 256 * 256;
     const int64_t out_pitch = (nt + 1) / 2 * 2;
@@ -60,7 +64,7 @@ extern "C" tx_status tx_plan_autotune(tx_plan_t p, int64_t nt, int32_t effort, d
 
     auto run = [&](const tx::Tiles& t, float* ms) -> hipError_t {
         const tx::DedispGeom g = tx::dedisp_geometry(p, nt, t);
-        if (!g.ok) {
+        if (!g.ok || g.ws_bytes > ws_bytes) {       // the second never happens: sized above
             *ms = -1.0f;
             return hipSuccess;
         }

@@ -130,42 +130,50 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
     sp = block_max(sp, red);
     const int W = ((sp >> 2) + 64 * Q + 1 + 3) & ~3;      // dwords per staged row
     const int rowbytes = 4 * W;
-    // Two staging buffers where two rows fit: round r + 1's rows load while
-    // round r is summed.  Otherwise one, staged between two barriers.
-    const int nbuf = 2 * (rowbytes + 4 * J) + 32 <= a.lds_bytes ? 2 : 1;
-    const int avail = (a.lds_bytes - 32) / nbuf;
-    const int nch = max(1, min(a.m, avail / (rowbytes + 4 * J)));
-    const int tab_bytes = (nch * J * 4 + 15) & ~15;
-    const int buf_bytes = tab_bytes + nch * rowbytes;
 
-    // Stage channels [cb, cb + nch) into `buf`: their (channel, trial) table
-    // and their rows.  Whole 16-byte pieces of a row go from global memory
-    // straight to LDS (global_load_lds: no registers, completes in the
-    // background; a wave's 64 pieces land at consecutive 16-byte slots of one
-    // 1 KB span); pieces that reach past the row's end, and dropped channels,
-    // go through registers with zeros past the end.
-    auto stage = [&](int cb, uint8_t* buf) {
+    // The workgroup's tables, built once at the top of LDS: per channel its
+    // staging start (16-byte aligned, from the row's base; complemented for a
+    // dropped channel) and per (channel, trial) the shift from that start.
+    // Staging rounds then read only LDS and never wait on global memory.
+    const int fix_off = (a.lds_bytes - ((a.m * (J + 1) * 4 + 15) & ~15)) & ~15;
+    int32_t* tabA = reinterpret_cast<int32_t*>(lds + fix_off);   // [m][J]
+    int32_t* rst = tabA + a.m * J;                                // [m]
+    for (int t = tid; t < a.m * J; t += kThreads) {
+        const int c = t / J, k = t - c * J;
+        const TX_GLOBAL int32_t* r = dT + static_cast<size_t>(ch0 + c) * gp;
+        tabA[t] = (r[min(j0 + k, jl)] + xo) - ((r[j0] + xo) & ~15);
+    }
+    for (int c = tid; c < a.m; c += kThreads) {
+        const int ch = ch0 + c;
+        const int st = (dT[static_cast<size_t>(ch) * gp + j0] + xo) & ~15;
+        const bool keep = !a.mask || to_global(a.mask)[ch] != 0;   // a dropped channel is staged as zeros
+        rst[c] = keep ? st : ~st;
+    }
+    // Two staging buffers where two rows fit below the tables: round r + 1's
+    // rows load while round r is summed.  Otherwise one, staged between two
+    // barriers.
+    const int nbuf = 2 * rowbytes <= fix_off ? 2 : 1;
+    const int nch = max(1, min(a.m, fix_off / nbuf / rowbytes));
+    const int buf_bytes = nch * rowbytes;
+    __syncthreads();
+
+    // Stage the rows of channels [cb, cb + nch) into `buf`.  Whole 16-byte
+    // pieces of a row go from global memory straight to LDS (global_load_lds:
+    // no registers, completes in the background; a wave's 64 pieces land at
+    // consecutive 16-byte slots of one 1 KB span); pieces that reach past the
+    // row's end, and dropped channels, go through registers with zeros past
+    // the end.
+    auto stage = [&](int cb, uint8_t* dat) {
         const int nc = min(nch, a.m - cb);
-        int32_t* tab = reinterpret_cast<int32_t*>(buf);
-        uint8_t* dat = buf + tab_bytes;
-        for (int t = tid; t < nc * J; t += kThreads) {
-            const int c = t / J, k = t - c * J;
-            const TX_GLOBAL int32_t* r = dT + static_cast<size_t>(ch0 + cb + c) * gp;
-            const int sh = (r[min(j0 + k, jl)] + xo) - ((r[j0] + xo) & ~15);
-            tab[t] = c * rowbytes + sh;          // word offset (sh & ~3) plus byte shift (sh & 3)
-        }
-        // Rows: wave w stages rows w, w + 4, ...  Lane l first fetches the
-        // start and valid length of row c0 + 4 l, so that the row loop waits
-        // on no memory (a wait would also wait for the background loads).
+        // Wave w stages rows w, w + 4, ...  Lane l first reads the start and
+        // valid length of row c0 + 4 l, so that the row loop needs no wait.
         for (int c0 = wave; c0 < nc; c0 += kWaves * 64) {
             const int cr = c0 + kWaves * lane;
             int64_t st = 0, av = 0;
             if (cr < nc) {
-                const int ch = ch0 + cb + cr;
-                st = static_cast<int64_t>(u0) + ((dT[static_cast<size_t>(ch) * gp + j0] + xo) & ~15);
-                // A dropped channel is staged as zeros (weight 0 in every sum).
-                const bool keep = !a.mask || to_global(a.mask)[ch] != 0;
-                av = keep ? a.x_len + xo - st : 0;
+                const int v = rst[cb + cr];
+                st = static_cast<int64_t>(u0) + (v >= 0 ? v : ~v);
+                av = v >= 0 ? a.x_len + xo - st : 0;
             }
             const int nr = min(64, (nc - c0 + kWaves - 1) / kWaves);
             for (int rr = 0; rr < nr; ++rr) {
@@ -202,22 +210,20 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
     stage(0, lds);
     for (int cb = 0, r = 0; cb < a.m; cb += nch, ++r) {
         const int nc = min(nch, a.m - cb);
-        uint8_t* cur = lds + (r & (nbuf - 1)) * buf_bytes;
-        // This wave's background loads into `cur` are done; after the barrier
+        const uint8_t* dat = lds + (r & (nbuf - 1)) * buf_bytes;
+        // This wave's background loads into `dat` are done; after the barrier
         // every wave's are, and nobody still reads the other buffer.
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
         __syncthreads();
         if (nbuf == 2 && cb + nch < a.m) stage(cb + nch, lds + ((r + 1) & 1) * buf_bytes);
-        const int32_t* tab = reinterpret_cast<const int32_t*>(cur);
-        const uint8_t* dat = cur + tab_bytes;
-        const int32_t* tw = tab + wave * JW;
+        const int32_t* tw = tabA + cb * J + wave * JW;
         const int lane_b = 4 * Q * lane;   // byte offset of the lane's first dword
         int c = 0;
         for (; c + 1 < nc; c += 2) {
 #pragma unroll
             for (int jj = 0; jj < JW; ++jj) {
-                const int e0 = uniform(tw[c * J + jj]);
-                const int e1 = uniform(tw[(c + 1) * J + jj]);
+                const int e0 = uniform(tw[c * J + jj]) + c * rowbytes;
+                const int e1 = uniform(tw[(c + 1) * J + jj]) + (c + 1) * rowbytes;
                 const uint32_t k0 = static_cast<uint32_t>(e0 & 3), k1 = static_cast<uint32_t>(e1 & 3);
                 const uint32_t sel0 = kOdd + k0 * 0x00010001u, sel1 = kOdd + k1 * 0x00010001u;
                 const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3) + lane_b);
@@ -238,7 +244,7 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
         if (c < nc) {
 #pragma unroll
             for (int jj = 0; jj < JW; ++jj) {
-                const int e0 = uniform(tw[c * J + jj]);
+                const int e0 = uniform(tw[c * J + jj]) + c * rowbytes;
                 const uint32_t k0 = static_cast<uint32_t>(e0 & 3);
                 const uint32_t sel0 = kOdd + k0 * 0x00010001u;
                 const uint32_t* p0 = reinterpret_cast<const uint32_t*>(dat + (e0 & ~3) + lane_b);
@@ -493,7 +499,7 @@ __device__ __forceinline__ int batch_tile(int total) {
 template <int Q, int JW>
 __global__ __launch_bounds__(kThreads) void stage1_kernel(Stage1Args a) {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ int red[kWaves];
+    int* red = reinterpret_cast<int*>(lds);   // block_max scratch, used before anything is staged
     stage1_tile<Q, JW>(a, xcd_tile(blockIdx.x, a.nsub * a.n_ttiles * a.n_jchunks), lds, red);
 }
 
@@ -502,7 +508,7 @@ __global__ __launch_bounds__(kThreads) void stage1_batch_kernel(const Stage1Args
                                                                 const int* __restrict__ prefix,
                                                                 const int* __restrict__ njobs_p) {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ int red[kWaves];
+    int* red = reinterpret_cast<int*>(lds);   // block_max scratch, used before anything is staged
     const int njobs = *njobs_p;
     const int t = batch_tile(prefix[njobs]);
     if (t < 0) return;
@@ -514,7 +520,7 @@ __global__ __launch_bounds__(kThreads) void stage1_batch_kernel(const Stage1Args
 template <int IW, int Q>
 __global__ __launch_bounds__(kThreads) void stage2_kernel(Stage2Args a) {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ int red[kWaves];
+    int* red = reinterpret_cast<int*>(lds);   // block_max scratch, used before anything is staged
     stage2_tile<IW, Q>(a, xcd_tile(blockIdx.x, a.ngroups * a.n_ichunks * a.n_ttiles), lds, red);
 }
 
@@ -523,7 +529,7 @@ __global__ __launch_bounds__(kThreads) void stage2_batch_kernel(const Stage2Args
                                                                 const int* __restrict__ prefix,
                                                                 const int* __restrict__ njobs_p) {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ int red[kWaves];
+    int* red = reinterpret_cast<int*>(lds);   // block_max scratch, used before anything is staged
     const int njobs = *njobs_p;
     const int t = batch_tile(prefix[njobs]);
     if (t < 0) return;
@@ -539,10 +545,10 @@ static const Stage1Variant kS1[] = {{5, 4}, {7, 4}, {9, 4}, {5, 2}, {7, 2}, {9, 
 static const Stage2Variant kS2[] = {{1}, {3}, {5}};
 constexpr int kNS1 = sizeof(kS1) / sizeof(kS1[0]);
 constexpr int kNS2 = sizeof(kS2) / sizeof(kS2[0]);
-constexpr int kDefaultLds = 32 * 1024;    // first stage
+constexpr int kDefaultLds = 40 * 1024;    // first stage: a quarter of a CU's LDS, 4 workgroups per CU
 constexpr int kDefaultLds2 = 32 * 1024;   // second stage
 // Defaults: the fastest pair on the 4096-channel paper-scale block (first
-// stage 9 output dwords per lane x 4 trials per wavefront at 32 KB, second
+// stage 9 output dwords per lane x 4 trials per wavefront at 40 KB, second
 // stage 3 output dwords per lane at 32 KB); tx_plan_autotune measures per
 // plan.  Q is odd in both stages (bank-conflict-free lane stride).
 constexpr int kDefaultS1 = 2;
@@ -590,7 +596,8 @@ DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want) {
     // buffers when two fit in its LDS size.
     const int sp1 = plan_spread1(p, g.J1) + 15;
     const int W1 = ((sp1 >> 2) + 64 * v1.q + 1 + 3) & ~3;
-    const int need1 = std::max(4 * W1 + 4 * g.J1 + 48, kWaves * 512 * v1.q);   // rows; output pass
+    const int tabs1 = (p->m * (g.J1 + 1) * 4 + 15) & ~15;                            // shift tables
+    const int need1 = std::max(4 * W1 + tabs1 + 48, kWaves * 512 * v1.q);   // a row and the tables; output pass
     g.lds1 = std::max(g.tiles.s1_lds > 0 ? g.tiles.s1_lds : kDefaultLds, need1);
     const int sp2 = plan_spread2(p, g.iw) + 7;
     const int W2 = ((sp2 >> 1) + 256 * v2.q + 1 + 3) & ~3;
