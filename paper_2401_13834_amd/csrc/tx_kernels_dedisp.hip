@@ -339,14 +339,26 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
     sp = block_max(sp, red);
     // A staged row is kept twice: copy 0 from the 8-element aligned start,
     // copy 1 one element later, so that every trial's window starts at a
-    // dword of one of them (one aligned 4-byte read per output dword).
-    const int W = ((sp >> 1) + 256 * Q + 1 + 3) & ~3;     // dwords per staged copy
-    const int rowbytes = 4 * W;
-    const int chb = 2 * rowbytes;
-    const int avail = a.lds_bytes - 16;
-    const int nsb = max(1, min(a.nsub, avail / (chb + 4 * IWP)));
-    int32_t* tab = reinterpret_cast<int32_t*>(lds);
-    uint8_t* dat = lds + ((nsb * IWP * 4 + 15) & ~15);
+    // dword of one of them (one aligned 4-byte read per output dword).  Copy 1
+    // spans the W dwords the trials read; copy 0 holds one more 16-byte
+    // piece, the next dwords copy 1 is built from.
+    const int W = ((sp >> 1) + 256 * Q + 1 + 3) & ~3;
+    const int W0 = W + 4;
+    const int chb = 4 * (W0 + W);                  // bytes per staged sub-band row
+
+    // The workgroup's table, built once at the top of LDS: per (sub-band,
+    // trial) the byte offset of the trial's first dword within the row's
+    // two copies.  Staging rounds then wait only on their own rows.
+    const int tab_off = (a.lds_bytes - ((a.nsub * IWP * 4 + 15) & ~15)) & ~15;
+    int32_t* tab = reinterpret_cast<int32_t*>(lds + tab_off);   // [nsub][IWP]
+    for (int t = tid; t < a.nsub * IWP; t += kThreads) {
+        const int s = t / IWP, k = t - s * IWP;
+        const TX_GLOBAL int32_t* rr = rT + static_cast<size_t>(s) * dp;
+        const int e = rr[i0 + min(k, ni - 1)] - (rr[i0] & ~7);
+        tab[t] = (e & 1) * (4 * W0) + 4 * (e >> 1);   // copy (e & 1), dword e / 2
+    }
+    const int nsb = max(1, min(a.nsub, tab_off / chb));
+    uint8_t* dat = lds;
 
     // Exact 32-bit sums of the low and high 16-bit outputs of each dword.
     uint32_t lo[IW][Q], hi[IW][Q];
@@ -362,18 +374,19 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
     // the trials: trial ii + 1's words are read while trial ii is summed, and
     // the table entries of trial ii + 2 while those words are in flight, so
     // the one wait per trial finds its data already there.
-    auto group = [&](auto gtag, int r) {
+    auto group = [&](auto gtag, int sb, int r) {
         constexpr int G = decltype(gtag)::value;
         uint32_t xc[G][Q], xn[G][Q];
         int tn[G];                                   // table entries (uniform) of the next trial to read
         auto tab_read = [&](int ii) {
 #pragma unroll
-            for (int k = 0; k < G; ++k) tn[k] = tab[(r + k) * IWP + ii];
+            for (int k = 0; k < G; ++k) tn[k] = tab[(sb + r + k) * IWP + ii];
         };
         auto fetch = [&](uint32_t (&x)[G][Q]) {
 #pragma unroll
             for (int k = 0; k < G; ++k) {
-                const uint32_t* p = reinterpret_cast<const uint32_t*>(dat + uniform(tn[k])) + wbase;
+                const uint32_t* p =
+                    reinterpret_cast<const uint32_t*>(dat + uniform(tn[k]) + (r + k) * chb) + wbase;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) x[k][q] = p[q];
             }
@@ -408,34 +421,45 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
         }
     };
 
+    __syncthreads();
     for (int sb = 0; sb < a.nsub; sb += nsb) {
         const int ns = min(nsb, a.nsub - sb);
-        for (int t = tid; t < ns * IWP; t += kThreads) {
-            const int r = t / IWP, k = t - r * IWP;
-            const TX_GLOBAL int32_t* rr = rT + static_cast<size_t>(sb + r) * dp;
-            const int e = rr[i0 + min(k, ni - 1)] - (rr[i0] & ~7);
-            tab[t] = r * chb + (e & 1) * rowbytes + 4 * (e >> 1);   // copy (e & 1), dword e / 2
-        }
+        // Copy 0 of wave w's rows (w, w + 4, ...) straight from global memory
+        // into LDS (global_load_lds: whole 16-byte pieces, no registers; a
+        // wave's 64 pieces land at consecutive 16-byte slots of one 1 KB
+        // span), all in flight at once ...
         for (int r = wave; r < ns; r += kWaves) {
             const int s = sb + r;
-            const TX_GLOBAL uint16_t* src = Bj + static_cast<size_t>(s) * a.B_pitch + t0 + (rT[static_cast<size_t>(s) * dp + i0] & ~7);
-            uint32_t* dst0 = reinterpret_cast<uint32_t*>(dat + r * chb);
-            uint32_t* dst1 = dst0 + W;
+            const TX_GLOBAL uint16_t* src =
+                Bj + static_cast<size_t>(s) * a.B_pitch + t0 + (rT[static_cast<size_t>(s) * dp + i0] & ~7);
+            uint8_t* dst = dat + r * chb;
+            for (int k = 0; 256 * k < W0; ++k) {
+                const int i = lane + 64 * k;
+                if (4 * i < W0)
+                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const TX_GLOBAL void*>(src + 8 * i),
+                                                     to_lds(dst + 1024 * k), 16, 0, 0);
+            }
+        }
+        // ... then, once they have landed, copy 1 of the same rows from it.
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        asm volatile("" ::: "memory");
+        for (int r = wave; r < ns; r += kWaves) {
+            const uint32_t* c0 = reinterpret_cast<const uint32_t*>(dat + r * chb);
+            uint32_t* c1 = reinterpret_cast<uint32_t*>(dat + r * chb) + W0;
             for (int i = lane; 4 * i < W; i += 64) {
-                const uint4 v = *reinterpret_cast<const TX_GLOBAL uint4*>(src + 8 * i);
-                const uint32_t nx = *reinterpret_cast<const TX_GLOBAL uint32_t*>(src + 8 * i + 8);
-                *reinterpret_cast<uint4*>(dst0 + 4 * i) = v;
-                *reinterpret_cast<uint4*>(dst1 + 4 * i) = make_uint4(align_b32(v.y, v.x, 2), align_b32(v.z, v.y, 2),
-                                                                     align_b32(v.w, v.z, 2), align_b32(nx, v.w, 2));
+                const uint4 v = *reinterpret_cast<const uint4*>(c0 + 4 * i);
+                const uint32_t nx = c0[4 * i + 4];
+                *reinterpret_cast<uint4*>(c1 + 4 * i) = make_uint4(align_b32(v.y, v.x, 2), align_b32(v.z, v.y, 2),
+                                                                   align_b32(v.w, v.z, 2), align_b32(nx, v.w, 2));
             }
         }
         __syncthreads();
         int r = 0;
         if (a.flush >= 4)
-            for (; r + 4 <= ns; r += 4) group(std::integral_constant<int, 4>{}, r);
+            for (; r + 4 <= ns; r += 4) group(std::integral_constant<int, 4>{}, sb, r);
         if (a.flush >= 2)
-            for (; r + 2 <= ns; r += 2) group(std::integral_constant<int, 2>{}, r);
-        for (; r < ns; ++r) group(std::integral_constant<int, 1>{}, r);
+            for (; r + 2 <= ns; r += 2) group(std::integral_constant<int, 2>{}, sb, r);
+        for (; r < ns; ++r) group(std::integral_constant<int, 1>{}, sb, r);
         __syncthreads();
     }
 
@@ -601,7 +625,8 @@ DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want) {
     g.lds1 = std::max(g.tiles.s1_lds > 0 ? g.tiles.s1_lds : kDefaultLds, need1);
     const int sp2 = plan_spread2(p, g.iw) + 7;
     const int W2 = ((sp2 >> 1) + 256 * v2.q + 1 + 3) & ~3;
-    const int need2 = std::max(2 * 4 * W2 + 4 * iwp + 48, kWaves * 512 * v2.q);   // two copies of a row; output pass
+    const int tabs2 = (p->nsub * iwp * 4 + 15) & ~15;                               // shift table
+    const int need2 = std::max(4 * (2 * W2 + 4) + tabs2 + 48, kWaves * 512 * v2.q);   // both copies of a row; output pass
     g.lds2 = std::max(g.tiles.s2_lds > 0 ? g.tiles.s2_lds : kDefaultLds2, need2);
     const int max_lds = device_max_lds();
     g.lds1 = std::min(g.lds1, std::max(need1, max_lds));
@@ -611,10 +636,10 @@ DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want) {
     g.tiles.s2_lds = g.lds2;
 
     g.n_ttiles2 = static_cast<int32_t>((nt + g.tt2 - 1) / g.tt2);
-    // Stage 2 stages elements [start, start + 2 W + 2) of a series (the
-    // second copy reads one dword past the first), start <= last tile start +
-    // max extent.
-    const int64_t need = static_cast<int64_t>(std::max(g.n_ttiles2 - 1, 0)) * g.tt2 + p->max_extent + 2 * W2 + 2;
+    // Stage 2 stages elements [start, start + 2 W + 8) of a series (copy 0
+    // holds one 16-byte piece more than the W dwords the trials read), start
+    // <= last tile start + max extent.
+    const int64_t need = static_cast<int64_t>(std::max(g.n_ttiles2 - 1, 0)) * g.tt2 + p->max_extent + 2 * W2 + 8;
     g.B_pitch = round_up(std::max<int64_t>(need, nt + p->max_extent), g.tt1);
     g.n_ttiles1 = static_cast<int32_t>(g.B_pitch / g.tt1);
     g.n_jchunks = (p->ngroups + g.J1 - 1) / g.J1;
