@@ -31,6 +31,10 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // (vmcnt bits 3:0 and 15:14 zero, expcnt 6:4 = 7, lgkmcnt 11:8 = 15).
 constexpr int kWaitVm0 = 0x0F70;
 
+// Word 3 of a raw (stride 0) buffer resource on gfx9-family parts: 32-bit
+// data format, no swizzle, no thread-id offset.
+constexpr int kRawBufferWord3 = 0x00020000;
+
 __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
     const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint64_t>(v)), l);
     const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint64_t>(v) >> 32), l);
@@ -58,23 +62,6 @@ __device__ __forceinline__ int block_max(int v, int* red) {
     v = max(max(red[0], red[1]), max(red[2], red[3]));
     __syncthreads();
     return v;
-}
-
-// Bytes [b, b + 20) of a row with `avail` valid bytes (zeros past the end).
-__device__ __forceinline__ void load20(const TX_GLOBAL uint8_t* row, int b, int64_t avail, uint32_t d[5]) {
-    if (b + 20 <= avail) {
-        const uint4 v = *reinterpret_cast<const TX_GLOBAL uint4*>(row + b);
-        d[0] = v.x;
-        d[1] = v.y;
-        d[2] = v.z;
-        d[3] = v.w;
-        d[4] = *reinterpret_cast<const TX_GLOBAL uint32_t*>(row + b + 16);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) d[k] = 0u;
-        for (int k = 0; k < 20; ++k)
-            if (b + k < avail) d[k >> 2] |= static_cast<uint32_t>(row[b + k]) << (8 * (k & 3));
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -127,7 +114,7 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
         const TX_GLOBAL int32_t* r = dT + static_cast<size_t>(ch0 + c) * gp;
         sp = max(sp, (r[jl] + xo) - ((r[j0] + xo) & ~15));
     }
-    sp = block_max(sp, red);
+    sp = uniform(block_max(sp, red));
     const int W = ((sp >> 2) + 64 * Q + 1 + 3) & ~3;      // dwords per staged row
     const int rowbytes = 4 * W;
 
@@ -157,46 +144,38 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
     const int buf_bytes = nch * rowbytes;
     __syncthreads();
 
-    // Stage the rows of channels [cb, cb + nch) into `buf`.  Whole 16-byte
-    // pieces of a row go from global memory straight to LDS (global_load_lds:
-    // no registers, completes in the background; a wave's 64 pieces land at
-    // consecutive 16-byte slots of one 1 KB span); pieces that reach past the
-    // row's end, and dropped channels, go through registers with zeros past
-    // the end.
+    // Stage the rows of channels [cb, cb + nch) into `dat`.  Whole 16-byte
+    // pieces go from global memory straight to LDS (buffer_load ... lds: no
+    // registers, completes in the background; a wave's 64 pieces land at
+    // consecutive 16-byte slots of one 1 KB span).  Each row is read through
+    // a raw buffer resource sized to the row's whole valid pieces, so the
+    // hardware range check returns zeros for the pieces past the row's end,
+    // and for a dropped channel (size 0) everywhere.  The one piece that
+    // straddles the end goes through registers, byte by byte, with zeros past
+    // the end (nothing past the row's valid bytes is read).
     auto stage = [&](int cb, uint8_t* dat) {
         const int nc = min(nch, a.m - cb);
-        // Wave w stages rows w, w + 4, ...  Lane l first reads the start and
-        // valid length of row c0 + 4 l, so that the row loop needs no wait.
-        for (int c0 = wave; c0 < nc; c0 += kWaves * 64) {
-            const int cr = c0 + kWaves * lane;
-            int64_t st = 0, av = 0;
-            if (cr < nc) {
-                const int v = rst[cb + cr];
-                st = static_cast<int64_t>(u0) + (v >= 0 ? v : ~v);
-                av = v >= 0 ? a.x_len + xo - st : 0;
-            }
-            const int nr = min(64, (nc - c0 + kWaves - 1) / kWaves);
-            for (int rr = 0; rr < nr; ++rr) {
-            const int c = c0 + kWaves * rr;
-            const int ch = ch0 + cb + c;
-            const int64_t start = readlane64(st, rr);
-            const int64_t avail_b = readlane64(av, rr);
-            const TX_GLOBAL uint8_t* row = to_global(a.x) + static_cast<size_t>(ch) * a.x_pitch + start;
+        for (int c = wave; c < nc; c += kWaves) {
+            const int v = uniform(rst[cb + c]);
+            const int64_t start = static_cast<int64_t>(u0) + (v >= 0 ? v : ~v);
+            int64_t nb64 = v >= 0 ? a.x_len + xo - start : 0;   // valid bytes of the staged row
+            nb64 = nb64 < 0 ? 0 : (nb64 > rowbytes ? rowbytes : nb64);
+            const int nb = uniform(static_cast<int>(nb64));
+            const int part = (nb & 15) ? nb >> 4 : -1;         // the straddling piece, if any
+            const uint8_t* row = a.x + static_cast<size_t>(ch0 + cb + c) * a.x_pitch + start;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint8_t*>(row), static_cast<short>(0), nb & ~15, kRawBufferWord3);
             uint8_t* dst = dat + c * rowbytes;
             for (int k = 0; 256 * k < W; ++k) {
                 const int i = lane + 64 * k;     // 16-byte piece of the row
-                if (4 * i < W) {
-                    if (16 * static_cast<int64_t>(i) + 16 <= avail_b) {
-                        __builtin_amdgcn_global_load_lds(
-                            reinterpret_cast<const TX_GLOBAL void*>(row + 16 * i),
-                            to_lds(dst + 1024 * k), 16, 0, 0);
-                    } else {
-                        uint32_t d[5];
-                        load20(row, 16 * i, avail_b, d);
-                        *reinterpret_cast<uint4*>(dst + 16 * i) = make_uint4(d[0], d[1], d[2], d[3]);
-                    }
-                }
+                if (4 * i < W && i != part)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, to_lds(dst + 1024 * k), 16, 16 * i, 0, 0, 0);
             }
+            if (part >= 0 && (part & 63) == lane) {
+                const TX_GLOBAL uint8_t* src = to_global(row) + 16 * part;
+                uint32_t d[4] = {0u, 0u, 0u, 0u};
+                for (int b = 0; b < (nb & 15); ++b) d[b >> 2] |= static_cast<uint32_t>(src[b]) << (8 * (b & 3));
+                *reinterpret_cast<uint4*>(dst + 16 * part) = make_uint4(d[0], d[1], d[2], d[3]);
             }
         }
     };
@@ -569,10 +548,10 @@ static const Stage1Variant kS1[] = {{5, 4}, {7, 4}, {9, 4}, {5, 2}, {7, 2}, {9, 
 static const Stage2Variant kS2[] = {{1}, {3}, {5}};
 constexpr int kNS1 = sizeof(kS1) / sizeof(kS1[0]);
 constexpr int kNS2 = sizeof(kS2) / sizeof(kS2[0]);
-constexpr int kDefaultLds = 40 * 1024;    // first stage: a quarter of a CU's LDS, 4 workgroups per CU
+constexpr int kDefaultLds = 27296;        // first stage: a sixth of a CU's LDS (94 VGPRs hold it to 5 per CU)
 constexpr int kDefaultLds2 = 32 * 1024;   // second stage
 // Defaults: the fastest pair on the 4096-channel paper-scale block (first
-// stage 9 output dwords per lane x 4 trials per wavefront at 40 KB, second
+// stage 9 output dwords per lane x 4 trials per wavefront at 27296 bytes, second
 // stage 3 output dwords per lane at 32 KB); tx_plan_autotune measures per
 // plan.  Q is odd in both stages (bank-conflict-free lane stride).
 constexpr int kDefaultS1 = 2;
