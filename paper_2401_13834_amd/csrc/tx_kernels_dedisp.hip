@@ -315,7 +315,7 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
         const TX_GLOBAL int32_t* r = rT + static_cast<size_t>(s) * dp;
         sp = max(sp, r[il] - (r[i0] & ~7));
     }
-    sp = block_max(sp, red);
+    sp = uniform(block_max(sp, red));
     // A staged row is kept twice: copy 0 from the 8-element aligned start,
     // copy 1 one element later, so that every trial's window starts at a
     // dword of one of them (one aligned 4-byte read per output dword).  Copy 1
