@@ -325,18 +325,26 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
     const int W0 = W + 4;
     const int chb = 4 * (W0 + W);                  // bytes per staged sub-band row
 
-    // The workgroup's table, built once at the top of LDS: per (sub-band,
-    // trial) the byte offset of the trial's first dword within the row's
-    // two copies.  Staging rounds then wait only on their own rows.
-    const int tab_off = (a.lds_bytes - ((a.nsub * IWP * 4 + 15) & ~15)) & ~15;
-    int32_t* tab = reinterpret_cast<int32_t*>(lds + tab_off);   // [nsub][IWP]
-    for (int t = tid; t < a.nsub * IWP; t += kThreads) {
-        const int s = t / IWP, k = t - s * IWP;
-        const TX_GLOBAL int32_t* rr = rT + static_cast<size_t>(s) * dp;
-        const int e = rr[i0 + min(k, ni - 1)] - (rr[i0] & ~7);
-        tab[t] = (e & 1) * (4 * W0) + 4 * (e >> 1);   // copy (e & 1), dword e / 2
+    // The workgroup's table, built once at the top of LDS: per (trial,
+    // sub-band) the byte offset of the trial's first dword within the row's
+    // two copies.  Staging rounds then wait only on their own rows.  Trial
+    // major, so that the entries of a group of 4 (2) sub-bands are one
+    // aligned 16-byte (8-byte) read.
+    const int nsp = (a.nsub + 3) & ~3;
+    const int tab_off = (a.lds_bytes - IWP * nsp * 4) & ~15;
+    int32_t* tab = reinterpret_cast<int32_t*>(lds + tab_off);   // [IWP][nsp]
+    for (int t = tid; t < IWP * nsp; t += kThreads) {
+        const int k = t / nsp, s = t - k * nsp;
+        if (s < a.nsub) {
+            const TX_GLOBAL int32_t* rr = rT + static_cast<size_t>(s) * dp;
+            const int e = rr[i0 + min(k, ni - 1)] - (rr[i0] & ~7);
+            tab[t] = (e & 1) * (4 * W0) + 4 * (e >> 1);   // copy (e & 1), dword e / 2
+        }
     }
-    const int nsb = max(1, min(a.nsub, tab_off / chb));
+    // Sub-bands per staging round: a multiple of 4 (or 2) where that many
+    // fit, so that every group's table entries are aligned.
+    int nsb = max(1, min(a.nsub, tab_off / chb));
+    nsb = nsb >= 4 ? (nsb & ~3) : (nsb >= 2 ? 2 : 1);
     uint8_t* dat = lds;
 
     // Exact 32-bit sums of the low and high 16-bit outputs of each dword.
@@ -358,8 +366,20 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
         uint32_t xc[G][Q], xn[G][Q];
         int tn[G];                                   // table entries (uniform) of the next trial to read
         auto tab_read = [&](int ii) {
-#pragma unroll
-            for (int k = 0; k < G; ++k) tn[k] = tab[(sb + r + k) * IWP + ii];
+            const int32_t* tp = tab + ii * nsp + sb + r;
+            if constexpr (G == 4) {
+                const int4 v = *reinterpret_cast<const int4*>(tp);
+                tn[0] = v.x;
+                tn[1] = v.y;
+                tn[2] = v.z;
+                tn[3] = v.w;
+            } else if constexpr (G == 2) {
+                const int2 v = *reinterpret_cast<const int2*>(tp);
+                tn[0] = v.x;
+                tn[1] = v.y;
+            } else {
+                tn[0] = tp[0];
+            }
         };
         auto fetch = [&](uint32_t (&x)[G][Q]) {
 #pragma unroll
@@ -604,7 +624,7 @@ DedispGeom dedisp_geometry(const tx_plan_s* p, int64_t nt, const Tiles& want) {
     g.lds1 = std::max(g.tiles.s1_lds > 0 ? g.tiles.s1_lds : kDefaultLds, need1);
     const int sp2 = plan_spread2(p, g.iw) + 7;
     const int W2 = ((sp2 >> 1) + 256 * v2.q + 1 + 3) & ~3;
-    const int tabs2 = (p->nsub * iwp * 4 + 15) & ~15;                               // shift table
+    const int tabs2 = ((p->nsub + 3) & ~3) * iwp * 4;                                // shift table
     const int need2 = std::max(4 * (2 * W2 + 4) + tabs2 + 48, kWaves * 512 * v2.q);   // both copies of a row; output pass
     g.lds2 = std::max(g.tiles.s2_lds > 0 ? g.tiles.s2_lds : kDefaultLds2, need2);
     const int max_lds = device_max_lds();

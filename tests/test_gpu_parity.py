@@ -94,6 +94,29 @@ def test_dedisperse_exact_input_length_and_pitch():
     del torch
 
 
+@pytest.mark.parametrize("phase", range(16))
+def test_dedisperse_row_end_at_every_byte_phase(phase):
+    """One channel per sub-band and g = 1 (brute force): the highest trial
+    reads the last valid byte of the lowest channel.  Rows whose valid length
+    ends at every byte position of a 16-byte piece must stage their last
+    bytes exactly (a staging step that drops a partly valid piece changes
+    the result)."""
+    torch_cuda()
+    _say(f"row end phase={phase}")
+    freqs = synth.band_centres(1500.0, 1100.0, 16)
+    dms = np.linspace(0.0, 900.0, 9)
+    ref = oracle.make_plan(freqs, 5e-4, dms, 16, g=1)
+    plan = tx.tx_plan(freqs, 5e-4, dms, 16, dms_per_group=1)
+    assert ref.overlap == plan.overlap
+    nt = 600 + (phase - (600 + ref.overlap)) % 16
+    assert (nt + ref.overlap) % 16 == phase
+    x = synth.uniform_u8(16, nt + ref.overlap, 40 + phase)
+    x[:, -16:] |= 0x80                       # the row ends are never zero
+    want = oracle.dedisperse_subband(x, ref, nt)
+    got = gpu_dedisperse(plan, x, nt)
+    assert np.array_equal(got[:, :nt], want)
+
+
 def test_dedisperse_rejects_bad_arguments():
     torch = torch_cuda()
     freqs = synth.band_centres(1712.0, 856.0, 64)
