@@ -61,25 +61,27 @@ __device__ __forceinline__ V wave_sum(V v) {
     return v;
 }
 
-// Wavefront max / min of an int32 with DPP moves (quad, half-row and row
-// permutes, then the row broadcasts of 15 and 31); the result is read from
-// lane 63.
+// Wavefront max / min of an int32 with DPP (quad, half-row and row permutes,
+// then the row broadcasts of 15 and 31); the result is read from lane 63.
+// The moves' fallback value is the operation's identity, so each step
+// compiles to one v_max/v_min with a DPP source instead of a move and an op
+// (rows a broadcast does not write keep their value either way).
 __device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // row_mirror
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast15
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast31
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x140, 0xF, 0xF, false));  // row_mirror
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x142, 0xA, 0xF, false));  // row_bcast15
+    v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x143, 0xC, 0xF, false));  // row_bcast31
     return __builtin_amdgcn_readlane(v, 63);
 }
 __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0xB1, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x4E, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x141, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x140, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x142, 0xA, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x143, 0xC, 0xF, false));
     return __builtin_amdgcn_readlane(v, 63);
 }
 
