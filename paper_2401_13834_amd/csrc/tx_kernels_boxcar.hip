@@ -437,7 +437,11 @@ __device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShar
 
 // Single job: one workgroup per row.
 template <int NWT>
-__global__ __launch_bounds__(kThreads) void boxcar_kernel(BoxcarArgs a) {
+// Held to 5 waves per SIMD (at most 102 VGPRs): the compiler's own choice,
+// 113 VGPRs and 4 waves, ran 7% slower on the paper-scale block although it
+// spills nothing (the capped 10-width form keeps 3 dwords in scratch, saved
+// and restored once per tile of 4096 starts).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void boxcar_kernel(BoxcarArgs a) {
     __shared__ BoxShared<NWT> sh;
     const int row = static_cast<int>(blockIdx.x);        // grid = rows
     if (row < a.ndm) boxcar_row<NWT>(a, row, sh);
@@ -456,7 +460,7 @@ __device__ __forceinline__ int find_row_job(const int* __restrict__ prefix, int 
 // the grid may exceed the batch's rows (a captured graph is sized for the
 // largest batch) and workgroups past the last row exit at once.
 template <int NWT>
-__global__ __launch_bounds__(kThreads) void boxcar_batch_kernel(const BoxcarArgs* __restrict__ jobs,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void boxcar_batch_kernel(const BoxcarArgs* __restrict__ jobs,
                                                                 const int* __restrict__ prefix,
                                                                 const int* __restrict__ njobs_p) {
     __shared__ BoxShared<NWT> sh;
