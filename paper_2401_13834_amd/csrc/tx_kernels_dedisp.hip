@@ -447,7 +447,13 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
             uint32_t* c1 = reinterpret_cast<uint32_t*>(dat + r * chb) + W0;
             for (int i = lane; 4 * i < W; i += 64) {
                 const uint4 v = *reinterpret_cast<const uint4*>(c0 + 4 * i);
-                const uint32_t nx = c0[4 * i + 4];
+                // The dword after this piece starts the next lane's piece:
+                // take it with a wavefront shift (DPP wave_shl:1) rather than
+                // a read at a 16-byte lane stride, which conflicts 4 ways in
+                // the LDS banks.  The last lane of the wave and the last
+                // active lane read it.
+                uint32_t nx = __builtin_amdgcn_update_dpp(0u, v.x, 0x130, 0xF, 0xF, false);
+                if (lane == 63 || 4 * (i + 1) >= W) nx = c0[4 * i + 4];
                 *reinterpret_cast<uint4*>(c1 + 4 * i) = make_uint4(align_b32(v.y, v.x, 2), align_b32(v.z, v.y, 2),
                                                                    align_b32(v.w, v.z, 2), align_b32(nx, v.w, 2));
             }
