@@ -318,9 +318,12 @@ tx_status tx_ranges_destroy(tx_ranges_t r);
 typedef struct tx_tiles {
     int32_t stage1;      /* first-stage variant, 0..count-1, or -1 for the library's default */
     int32_t stage1_lds;  /* LDS bytes per first-stage workgroup, 0 = default (raised
-                            to what the plan's longest staged row needs) */
+                            to what one staged row of the plan's widest channel
+                            window plus the workgroup's shift tables need) */
     int32_t stage2;      /* second-stage variant, or -1 */
-    int32_t stage2_lds;  /* LDS bytes per second-stage workgroup, 0 = default */
+    int32_t stage2_lds;  /* LDS bytes per second-stage workgroup, 0 = default (raised
+                            likewise for one sub-band row, both copies, and the
+                            offset table) */
 } tx_tiles;
 
 /* Number of kernel variants of a stage (1 or 2). */
