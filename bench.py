@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -36,10 +37,14 @@ KERNEL_SOURCES = {"stage1": "tx_kernels_dedisp.hip", "stage2": "tx_kernels_dedis
 
 
 def kernel_source_hash(kernel):
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2401_13834_amd", "csrc", KERNEL_SOURCES[kernel]), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
+    """Hash of the kernel's source file without its comments and blank lines,
+    so that the stored counters stay valid across edits of comments only."""
+    with open(os.path.join(ROOT, "paper_2401_13834_amd", "csrc", KERNEL_SOURCES[kernel])) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    code = "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def load_traffic(kernel, workload):

@@ -75,10 +75,12 @@ __device__ __forceinline__ int block_max(int v, int* red) {
 // banks.  That is 1 + 1/Q dwords of LDS read per output dword, against 2 when
 // a lane reads words w and w + 1 of every output dword separately.  Channel
 // rows are staged starting at the row's shift for the first trial, rounded
-// down to 16 bytes; a per-(channel, trial) table holds the byte offset of the
-// first word and the remaining byte shift k.  v_alignbyte picks the 4 input
-// bytes of an output dword, a byte permute picks bytes 1 and 3 into 16-bit
-// lanes.
+// down to 16 bytes, with buffer loads straight into LDS, double-buffered so
+// that a round of rows loads while the previous one is summed; a
+// per-(channel, trial) table, built once per workgroup, holds the byte
+// offset of the first word and the remaining byte shift k.  v_alignbyte picks
+// the 4 input bytes of an output dword, a byte permute picks bytes 1 and 3
+// into 16-bit lanes.
 //
 // "full" accumulates the 4 bytes as one 32-bit word (carries cross bytes) and
 // "odd" accumulates bytes 1 and 3 as two 16-bit lanes; at the end
@@ -280,15 +282,19 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
 // owns the Q consecutive output dwords (two uint16 outputs each) from
 // w*64*Q + Q l, so one address add per (sub-band, trial) serves Q reads, which
 // pair into 8-byte reads; Q is odd, so the lanes' addresses fall in distinct
-// banks.  Sub-band rows are staged from the chunk's
-// first trial's shift rounded down to 8 elements, twice: as they are and one
-// element later, so that an even element shift reads whole dwords of the first
-// copy and an odd one whole dwords of the second (one aligned 4-byte read per
-// output dword, no byte joins); a per-(sub-band, trial) table holds the byte
-// offset of the trial's first dword.  Outputs are summed as packed 16-bit
-// lanes of one 32-bit word over groups of up to 4 sub-bands (exact while the
-// group is at most `flush` = floor(65535 / (255 m)) sub-bands), and each
-// group's sum is widened into two 32-bit totals.
+// banks.  Sub-band rows are staged, a round of them at a time, from the
+// chunk's first trial's shift rounded down to 8 elements, twice: as they are
+// and one element later, so that an even element shift reads whole dwords of
+// the first copy and an odd one whole dwords of the second (one aligned 4-byte
+// read per output dword, no byte joins).  The first copy loads straight from
+// global memory into LDS; each wave then builds the second copy of its own
+// rows from it.  A per-(trial, sub-band) table, built once per workgroup,
+// holds the byte offset of the trial's first dword.  Outputs are summed as
+// packed 16-bit lanes of one 32-bit word over groups of up to 4 sub-bands
+// (exact while the group is at most `flush` = floor(65535 / (255 m))
+// sub-bands), and each group's sum is widened into two 32-bit totals; the
+// trials of a group are software-pipelined (the next trial's words are read
+// while the current one is summed).
 // ---------------------------------------------------------------------------
 template <int IW, int Q>
 __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8_t* lds, int* red) {
