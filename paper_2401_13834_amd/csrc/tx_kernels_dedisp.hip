@@ -552,15 +552,20 @@ __global__ __launch_bounds__(kThreads) void stage1_batch_kernel(const Stage1Args
     stage1_tile<Q, JW>(a, t - prefix[jb], lds, red);
 }
 
+// The 16-trial, 3-dword variant is held to 4 waves per SIMD (128 VGPRs): left
+// alone it takes 131 and runs 3 waves; capped it keeps 3 dwords in scratch,
+// reloaded once per staging round.  Other variants are left to the compiler.
+#define TX_S2_WAVES(IW, Q) __attribute__((amdgpu_waves_per_eu((IW) == 16 && (Q) == 3 ? 4 : 1)))
+
 template <int IW, int Q>
-__global__ __launch_bounds__(kThreads) void stage2_kernel(Stage2Args a) {
+__global__ __launch_bounds__(kThreads) TX_S2_WAVES(IW, Q) void stage2_kernel(Stage2Args a) {
     extern __shared__ __align__(16) uint8_t lds[];
     int* red = reinterpret_cast<int*>(lds);   // block_max scratch, used before anything is staged
     stage2_tile<IW, Q>(a, xcd_tile(blockIdx.x, a.ngroups * a.n_ichunks * a.n_ttiles), lds, red);
 }
 
 template <int IW, int Q>
-__global__ __launch_bounds__(kThreads) void stage2_batch_kernel(const Stage2Args* __restrict__ jobs,
+__global__ __launch_bounds__(kThreads) TX_S2_WAVES(IW, Q) void stage2_batch_kernel(const Stage2Args* __restrict__ jobs,
                                                                 const int* __restrict__ prefix,
                                                                 const int* __restrict__ njobs_p) {
     extern __shared__ __align__(16) uint8_t lds[];
