@@ -121,17 +121,30 @@ __device__ __forceinline__ void scan_tile(const TX_GLOBAL int32_t* __restrict__ 
         for (int k = 0; k < kPer; ++k) v[k] = k < lim ? static_cast<uint32_t>(y[t + k]) : 0u;
     }
     if (COUNT) {
+        // The sums are used only when every sample is in [0, TX_MAX_VALUE)
+        // (then ps < 20 * 2^21 and y^2 < 2^42: no wrap), so out-of-range
+        // samples need only the flag, taken from the running maximum (as
+        // unsigned, a negative sample is out of range too).
         constexpr uint32_t kMask = static_cast<uint32_t>(TX_MAX_VALUE) - 1u;
         const int own = min(kPer, kBoxTile - e);       // samples of this tile (the rest belong to the next)
-        uint32_t ps = 0;                               // < 20 * 2^21: no wrap
+        uint32_t ps = 0, mx = 0;
+        if (own == kPer) {                             // all but the threads at the tile's end
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t x = k < own ? v[k] : 0u;
-            m.bad |= x > kMask ? 1u : 0u;
-            const uint32_t u = x & kMask;
-            ps += u;
-            m.s2 += static_cast<unsigned long long>(u) * u;
+            for (int k = 0; k < kPer; ++k) {
+                mx = max(mx, v[k]);
+                ps += v[k];
+                m.s2 += static_cast<unsigned long long>(v[k]) * v[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const uint32_t x = k < own ? v[k] : 0u;
+                mx = max(mx, x);
+                ps += x;
+                m.s2 += static_cast<unsigned long long>(x) * x;
+            }
         }
+        m.bad |= mx > kMask ? 1u : 0u;
         m.s1 += ps;
     }
     uint32_t run = 0;
@@ -437,10 +450,9 @@ __device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShar
 
 // Single job: one workgroup per row.
 template <int NWT>
-// Held to 5 waves per SIMD (at most 102 VGPRs): the compiler's own choice,
-// 113 VGPRs and 4 waves, ran 7% slower on the paper-scale block although it
-// spills nothing (the capped 10-width form keeps 3 dwords in scratch, saved
-// and restored once per tile of 4096 starts).
+// At least 5 waves per SIMD (at most 102 VGPRs).  When the kernel needed 113
+// VGPRs (4 waves) the cap made it 7% faster despite a 3-dword spill; the
+// current form needs 69 VGPRs with the cap (75 without) and spills nothing.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void boxcar_kernel(BoxcarArgs a) {
     __shared__ BoxShared<NWT> sh;
     const int row = static_cast<int>(blockIdx.x);        // grid = rows
