@@ -85,6 +85,20 @@ __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
     return __builtin_amdgcn_readlane(v, 63);
 }
 
+// Inclusive prefix sum over the wavefront's lanes with DPP: shifts of 1, 2,
+// 4 and 8 lanes within each row of 16 (lanes without a source add the
+// identity 0), then the row broadcasts of lanes 15 and 31 into the rows
+// above them.  Each step is one v_add with a DPP source; no LDS traffic.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x111, 0xF, 0xF, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x112, 0xF, 0xF, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x118, 0xF, 0xF, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x142, 0xA, 0xF, false);   // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x143, 0xC, 0xF, false);   // row_bcast:31 into rows 2, 3
+    return x;
+}
+
 // Moments of the samples a thread loaded (exact; a value >= 2^21 or < 0 flags
 // the row).
 struct Moments {
@@ -150,12 +164,7 @@ __device__ __forceinline__ void scan_tile(const TX_GLOBAL int32_t* __restrict__ 
     uint32_t run = 0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) run += v[k];
-    uint32_t incl = run;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t n = __shfl_up(incl, o);
-        if (lane >= o) incl += n;
-    }
+    const uint32_t incl = wave_incl_sum(run);
     if (lane == 63) wtot[wave] = incl;
     __syncthreads();
     uint32_t before = 0;
