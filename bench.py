@@ -418,8 +418,9 @@ def main():
                          "whose HBM counters scale the kernels' counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
-              "(beams shard across GPUs with no exchange; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the hot path on a single MI355X "
+              "(beams shard across GPUs with no exchange, so the one-GPU rate is the per-GPU rate).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

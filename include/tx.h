@@ -44,7 +44,7 @@ typedef enum tx_status {
     TX_EDEVICE = -3,    /* a HIP runtime call failed (no device, launch error, fault) */
     TX_ESTATE = -4,     /* the object is not in a state that allows this call */
     TX_EOVERFLOW = -5,  /* a delay or size does not fit the exact integer path */
-    TX_ENOTSUP = -6     /* the call is valid but this build does not support it */
+    TX_ENOTSUP = -6     /* the call is valid but the library does not support it */
 } tx_status;
 
 /* Human-readable name of a status code.  Never NULL. */

@@ -26,7 +26,7 @@ computes on its hot path:
 Where the paper is silent (the dispersion constant's value, the reference
 frequency, rounding of delays, how the coarse grid is chosen, the boxcar
 window for even widths, the noise estimator) the functions say which reading
-they take.  Every reading is listed in the repository's design notes.
+they take.
 
 Integer work is exact (int64).  Floating point is IEEE float64 evaluated in the
 order written, with no fused multiply-add.
