@@ -62,9 +62,10 @@ def load_traffic(kernel, workload):
     return ent.get("hbm_bytes_per_launch")
 
 
-def make_input(tx, plan, wl, synth):
-    """Seeded noise (pooled rows) with the workload's pulses."""
-    return synth.pooled_normal_u8(len(wl.freqs), wl.nt + plan.overlap, wl.seed, pulses=place_pulses(plan, wl, synth))
+def make_input(torch, plan, wl, synth, pitch):
+    """Seeded noise with the workload's pulses, drawn on the device: every
+    channel an independent N(128, 16^2) row, clipped and rounded to uint8."""
+    return synth.device_normal_u8(torch, len(wl.freqs), pitch, wl.seed, pulses=place_pulses(plan, wl, synth))
 
 
 def cpu_baseline(wl, x, g, seconds):
@@ -118,18 +119,7 @@ def cpu_baseline(wl, x, g, seconds):
 def place_pulses(plan, wl, synth):
     """(start[nchan], width, amplitude) of the workload's pulses, placed with
     the plan's own brute-force delays."""
-    nchan = len(wl.freqs)
-    out = []
-    for spec in wl.pulses:
-        kind, dm, t0, w = spec[0], spec[1], spec[2], spec[3]
-        start = t0 + plan.delays(dm).astype(np.int64)
-        if kind == "snr-index":
-            amp = synth.spectral_amplitudes(wl.freqs, 816.0, -1.5, 1.0)
-            amp = amp * (16.0 * spec[4] / np.sqrt(w) / amp.sum())
-        else:
-            amp = synth.pulse_amplitude(spec, w, nchan)
-        out.append((start, w, amp))
-    return out
+    return synth.place_pulses(wl, plan.delays)
 
 
 def transpose_leg(torch, tx, nchan, nt, overlap, launches=20):
@@ -430,10 +420,10 @@ def main():
     wl = synth.workload(args.workload)
     plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
     nchan, ndm, nt = len(wl.freqs), plan.ndm, wl.nt
-    x = make_input(tx, plan, wl, synth)
-    pitch = (x.shape[1] + 255) // 256 * 256
-    d_in = torch.zeros((nchan, pitch), dtype=torch.uint8, device="cuda")
-    d_in[:, :x.shape[1]] = torch.from_numpy(x).to("cuda")
+    pitch = (nt + plan.overlap + 255) // 256 * 256
+    d_in = make_input(torch, plan, wl, synth, pitch)
+    # host copy of the block for the CPU baseline (the same bytes)
+    x = None if args.no_cpu_baseline else d_in[:, :nt + plan.overlap].cpu().numpy()
     y = torch.empty((ndm, nt), dtype=torch.int32, device="cuda")
     cap = 1 << 20
     cands = torch.empty((cap, 3), dtype=torch.int64, device="cuda")

@@ -194,6 +194,45 @@ def spectral_amplitudes(freqs, f0, index, scale):
     return scale * (np.asarray(freqs, dtype=np.float64) / f0) ** index
 
 
+# The octave workload's pulse spectrum: flux proportional to f ** -1.5 around 816 MHz.
+SPECTRAL_F0_MHZ = 816.0
+SPECTRAL_INDEX = -1.5
+
+
+def index_pulse_amplitudes(freqs, width, snr, std=16.0, f0=SPECTRAL_F0_MHZ, index=SPECTRAL_INDEX):
+    """Per-channel amplitudes of a power-law pulse whose equal-weight
+    integrated S/N is ``snr``: amplitudes a_c proportional to (f_c/f0)**index,
+    scaled so that sum_c a_c = std * snr * sqrt(nchan) / sqrt(width).  (A
+    window of ``width`` samples then holds width * sum_c a_c of signal over a
+    noise of std * sqrt(nchan * width); with a flat spectrum this is
+    ``pulse_amplitude``'s a = std * snr / sqrt(nchan * width) per channel.)"""
+    freqs = np.asarray(freqs, dtype=np.float64)
+    shape = spectral_amplitudes(freqs, f0, index, 1.0)
+    return shape * (std * snr * np.sqrt(freqs.size) / np.sqrt(width) / shape.sum())
+
+
+def place_pulses(wl, delays):
+    """(start[nchan], width, amplitude) of every pulse of workload ``wl``, as
+    ``normal_u8`` and ``device_normal_u8`` take them.  ``delays(dm)`` returns
+    the per-channel delay in samples of a DM (from the caller's plan, so that
+    the injection uses the plan's own rounding); a pulse at time t starts at
+    t + delays(dm)[c] in channel c.  Specs: ``("amp", dm, t, w, a)`` a fixed
+    amplitude, ``("snr", dm, t, w, s)`` a flat spectrum of integrated S/N s,
+    ``("snr-index", dm, t, w, s)`` the power-law spectrum of
+    ``index_pulse_amplitudes`` with integrated S/N s."""
+    nchan = len(wl.freqs)
+    out = []
+    for spec in wl.pulses:
+        kind, dm, t0, w = spec[0], spec[1], spec[2], spec[3]
+        start = int(t0) + np.asarray(delays(dm), dtype=np.int64)
+        if kind == "snr-index":
+            amp = index_pulse_amplitudes(wl.freqs, w, spec[4])
+        else:
+            amp = pulse_amplitude(spec, w, nchan)
+        out.append((start, w, amp))
+    return out
+
+
 def device_normal_u8(torch, nchan, nsamp, seed, *, device="cuda", mean=128.0, std=16.0, pulses=(), rows=256):
     """Same recipe as ``normal_u8`` drawn on the device with torch's generator
     (a different sequence of numbers than ``normal_u8`` for the same seed),

@@ -87,6 +87,7 @@ BEAMS = [  # (nchan, nsub, ndm, dmmax, nt, f_top, f_bot, tsamp)
     (320, 32, 100, 1500.0, 5000, 1088.0, 544.0, 153.12e-6),
     (128, 4, 70, 200.0, 4100, 1500.0, 1100.0, 1e-3),
     (48, 48, 33, 900.0, 777, 1500.0, 1100.0, 5e-4),
+    (1024, 64, 100, 1000.0, 3000, 1712.0, 856.0, 153.12e-6),   # g = 14: 16 trials per second-stage workgroup
 ]
 
 
@@ -216,3 +217,74 @@ def test_batch_of_streams_equals_single_streams(graph):
         n = yb.shape[1]
         assert n == block * nblocks - ref.overlap
         assert np.array_equal(yb, oracle.dedisperse_subband(xs[q], ref, n))
+
+
+# One beam of each (channels, sub-bands, g) class of the uneven 64-beam batch,
+# at full shape: 1024 channels / 64 sub-bands / g = 14 (16 trials per
+# second-stage workgroup), 2048 / 128 / 26 and 4096 / 128 / 26 (13 per
+# workgroup).  Indices into synth.batched_beams().
+BATCHED_SAMPLE = [9, 1, 6, 0]
+
+
+def _sampled_rows(ref, wl):
+    rows = {0, 1, ref.g - 1, ref.g, ref.g + 1, ref.ndm // 2, ref.ndm - 1}
+    for spec in wl.pulses:
+        i = int(np.argmin(np.abs(ref.dms - spec[1])))
+        rows |= {max(i - 1, 0), i, min(i + 1, ref.ndm - 1)}
+    return sorted(rows)
+
+
+@pytest.mark.slow
+def test_batched_beams_full_shape_sampled_rows():
+    """Beams of the uneven batch at their real shapes (with their pulses), in
+    one graph-replayed batch launch: sampled rows against the oracle's
+    effective-offset sum, with the rows' peaks and candidates."""
+    torch = torch_cuda()
+    beams = synth.batched_beams()
+    jobs = []
+    for k in BATCHED_SAMPLE:
+        wl = beams[k]
+        plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, 0)
+        ref = oracle.make_plan(wl.freqs, wl.tsamp, wl.dms, plan.nsub)
+        assert (ref.g, ref.overlap) == (plan.g, plan.overlap)
+        _say(f"batched beam {k}: nchan={plan.nchan} nsub={plan.nsub} g={plan.g} ndm={plan.ndm} nt={wl.nt}")
+        pulses = synth.place_pulses(wl, lambda dm: oracle.delay_samples(dm, wl.freqs, ref.fref, wl.tsamp))
+        n = wl.nt + ref.overlap
+        d_in = synth.device_normal_u8(torch, plan.nchan, round_up(n, 256), wl.seed, pulses=pulses)
+        y = torch.full((plan.ndm, wl.nt), -3, dtype=torch.int32, device="cuda")
+        peaks = (torch.empty(plan.ndm, dtype=torch.float64, device="cuda"),
+                 torch.empty(plan.ndm, dtype=torch.int32, device="cuda"),
+                 torch.empty(plan.ndm, dtype=torch.int64, device="cuda"))
+        cands = torch.zeros((1 << 18, 3), dtype=torch.int64, device="cuda")
+        count = torch.zeros(1, dtype=torch.int64, device="cuda")
+        jobs.append(dict(k=k, wl=wl, plan=plan, ref=ref, d_in=d_in, y=y, peaks=peaks, cands=cands, count=count))
+    batch = tx.Batch(len(jobs), graph=True)
+    for j in jobs:
+        batch.add(j["plan"], j["d_in"], j["wl"].nt, j["y"], widths=j["wl"].widths, gamma=j["wl"].gamma,
+                  peaks=j["peaks"], cands=j["cands"], count=j["count"])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for rep in range(2):                      # capture, then a replay
+            _say(f"batched beams launch {rep}")
+            for j in jobs:
+                j["y"].fill_(-3)
+            batch.launch(s)
+            s.synchronize()
+    batch.close()
+    for j in jobs:
+        wl, ref = j["wl"], j["ref"]
+        rows = _sampled_rows(ref, wl)
+        _say(f"beam {j['k']}: oracle on rows {rows}")
+        x = j["d_in"][:, :wl.nt + ref.overlap].cpu().numpy()
+        want = oracle.dedisperse_offsets(x, ref.offsets[rows], wl.nt)
+        assert np.array_equal(j["y"][rows].cpu().numpy(), want)
+        ws, ww, wt = oracle.boxcar_peaks(want, wl.widths)
+        p = [t.cpu().numpy() for t in j["peaks"]]
+        assert np.array_equal(p[0][rows], ws)
+        assert np.array_equal(p[1][rows], ww) and np.array_equal(p[2][rows], wt)
+        n = int(j["count"].item())
+        assert n < (1 << 18)
+        wc = [(rows[d], t, w, v) for (d, t, w, v) in oracle.boxcar_candidates(want, wl.widths, wl.gamma)]
+        got = [c for c in as_tuples(tx.parse_candidates(j["cands"].cpu().numpy(), n)) if c[0] in set(rows)]
+        assert got == wc
+        del x
