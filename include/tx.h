@@ -59,7 +59,8 @@ tx_status tx_pool_trim(void);
 const char* tx_version(void);
 
 /* Text of the last HIP runtime error that made a call on this thread return
- * TX_EDEVICE or TX_ENOMEM ("" if none).  Owned by the library. */
+ * TX_EDEVICE or TX_ENOMEM, or of the reason tx_dedisperse_noalloc returned
+ * TX_ENOTSUP ("" if none).  Owned by the library. */
 const char* tx_last_error(void);
 
 /* ------------------------------------------------------------------------ */
@@ -199,6 +200,26 @@ tx_status tx_dedisperse(tx_plan_t plan, const uint8_t* d_in, int64_t in_pitch, i
 tx_status tx_dedisperse_ws(tx_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t nt,
                            int32_t* d_out, int64_t out_pitch, void* d_ws, int64_t ws_bytes,
                            hipStream_t stream);
+
+/*
+ * tx_dedisperse_noalloc: tx_dedisperse for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation during a run).  Same arguments, layout, result and
+ * errors as tx_dedisperse; it calls no allocator.  The first-stage series go
+ * to a scratch array of TX_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends, and the block is processed in
+ * chunks of output samples whose series fit it (so a large block takes
+ * several launches of each stage; the plan's first-stage tile may be swapped
+ * for a shorter one, which changes no result).  All calls on one GPU share
+ * that array: calls that overlap on one GPU (on other streams or threads)
+ * race and give wrong results; calls queued on one stream are ordered.
+ * Errors: those of tx_dedisperse, and TX_ENOTSUP when one chunk of the
+ * plan's series does not fit the array (tx_last_error gives the bytes it
+ * would need).
+ */
+#define TX_NOALLOC_SCRATCH_BYTES (256ll << 20)
+tx_status tx_dedisperse_noalloc(tx_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t nt,
+                                int32_t* d_out, int64_t out_pitch, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Time-major ingest (Sec. 2.3, Fig. "dedispersion_flow", "transpose" step)  */

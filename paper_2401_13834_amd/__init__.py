@@ -34,7 +34,7 @@ _c_dblp = ctypes.POINTER(ctypes.c_double)
 class TxError(RuntimeError):
     def __init__(self, status, what):
         detail = ""
-        if status in (-2, -3) and _lib is not None:
+        if status in (-2, -3, -6) and _lib is not None:
             detail = " (" + (_lib.tx_last_error() or b"").decode() + ")"
         super().__init__(f"{what}: {STATUS.get(status, status)}{detail}")
         self.status = status
@@ -76,6 +76,8 @@ _SIGS = {
     "tx_dedisperse_ws": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_void_p]),
+    "tx_dedisperse_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "tx_boxcar_snr": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _c_i32p,
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p]),
@@ -259,6 +261,16 @@ def tx_dedisperse(plan, d_in, nt, d_out, stream=None, ws=None):
         st = lib().tx_dedisperse_ws(plan.handle, _ptr(d_in), in_pitch, int(nt), _ptr(d_out), out_pitch,
                                     _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
     _check(st, "tx_dedisperse")
+
+
+TX_NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def tx_dedisperse_noalloc(plan, d_in, nt, d_out, stream=None):
+    """tx_dedisperse through the library's fixed scratch (no allocation)."""
+    in_pitch = d_in.stride(0) * d_in.element_size()
+    _check(lib().tx_dedisperse_noalloc(plan.handle, _ptr(d_in), in_pitch, int(nt), _ptr(d_out), d_out.stride(0),
+                                       _stream(stream)), "tx_dedisperse_noalloc")
 
 
 def tx_transpose_tf(d_tf, nchan, nt, d_ft, stream=None):

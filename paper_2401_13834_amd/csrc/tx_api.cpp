@@ -85,6 +85,8 @@ void tx::note_error(hipError_t e) {
     std::snprintf(t_last_error, sizeof(t_last_error), "%s (%d)", hipGetErrorString(e), static_cast<int>(e));
 }
 
+void tx::note_message(const char* msg) { std::snprintf(t_last_error, sizeof(t_last_error), "%s", msg); }
+
 tx_status tx::status_of(hipError_t e) {
     if (e == hipSuccess) return TX_OK;
     tx::note_error(e);
@@ -277,6 +279,30 @@ tx_status tx_dedisperse_ws(tx_plan_t p, const uint8_t* d_in, int64_t in_pitch, i
     if (!d_ws || ws_bytes < geo.ws_bytes || (reinterpret_cast<uintptr_t>(d_ws) & 255)) return TX_EINVAL;
     return from_hip(tx::launch_dedisperse(p, geo, d_in, in_pitch, nt, d_out, out_pitch,
                                           static_cast<uint16_t*>(d_ws), stream));
+}
+
+tx_status tx_dedisperse_noalloc(tx_plan_t p, const uint8_t* d_in, int64_t in_pitch, int64_t nt, int32_t* d_out,
+                                int64_t out_pitch, hipStream_t stream) {
+    tx_status st = check_device_plan(p);
+    if (st != TX_OK) return st;
+    st = check_dedisp_args(p, d_in, in_pitch, nt, d_out, out_pitch);
+    if (st != TX_OK || nt == 0) return st;
+    int64_t need = 0;
+    const hipError_t e = tx::launch_dedisperse_noalloc(p, current_tiles(p), d_in, in_pitch, nt, d_out, out_pitch,
+                                                       stream, p->device, &need);
+    if (e == hipErrorInvalidValue && need != 0) {
+        char msg[200];
+        if (need > 0)
+            std::snprintf(msg, sizeof(msg),
+                          "tx_dedisperse_noalloc: one chunk of this plan's first-stage series needs %lld bytes, "
+                          "more than the %lld-byte scratch", static_cast<long long>(need),
+                          static_cast<long long>(TX_NOALLOC_SCRATCH_BYTES));
+        else
+            std::snprintf(msg, sizeof(msg), "tx_dedisperse_noalloc: no tile of this plan fits the device's LDS");
+        tx::note_message(msg);
+        return TX_ENOTSUP;
+    }
+    return from_hip(e);
 }
 
 tx_status tx_dedisperse(tx_plan_t p, const uint8_t* d_in, int64_t in_pitch, int64_t nt, int32_t* d_out,

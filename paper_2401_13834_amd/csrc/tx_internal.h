@@ -234,6 +234,13 @@ hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const ui
                              int64_t nt, int32_t* d_out, int64_t out_pitch, uint16_t* d_B, hipStream_t stream,
                              int x_off = 0);
 hipError_t launch_boxcar(const BoxcarArgs& a, hipStream_t stream);
+// tx_dedisperse_noalloc: chunks of the block through the file-scope scratch
+// of device `dev` (current).  hipErrorInvalidValue with *need_bytes > 0 when
+// one chunk's first-stage series do not fit it (the smallest need), -1 when
+// no tile fits the device's LDS.
+hipError_t launch_dedisperse_noalloc(const tx_plan_s* p, const Tiles& want, const uint8_t* d_in, int64_t in_pitch,
+                                     int64_t nt, int32_t* d_out, int64_t out_pitch, hipStream_t stream, int dev,
+                                     int64_t* need_bytes);
 
 // Batch building blocks (tx_kernels_dedisp.hip, tx_kernels_boxcar.hip).
 void fill_stage_args(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d_in, int64_t in_pitch, int64_t nt,
@@ -260,6 +267,8 @@ hipError_t launch_zero_counts(const BoxcarArgs* d_jobs, const int* d_njobs, int 
 int device_max_lds();
 // Last HIP error seen by the C ABI on this thread (tx_api.cpp).
 void note_error(hipError_t e);
+// Replace this thread's last-error text (tx_last_error) with a message.
+void note_message(const char* msg);
 
 // Optional per-launch timing (tx_profile.cpp).  prof_begin returns -1 when
 // profiling is off; otherwise a slot whose end is recorded by prof_end.

@@ -814,4 +814,99 @@ hipError_t launch_stage2_batch(int iw, int variant, int lds, const Stage2Args* d
 
 int stage2_iw(int32_t g) { return pick_iw(g); }
 
+// ---------------------------------------------------------------------------
+// Dedispersion without allocation.  The first-stage series of one chunk of
+// output samples live in `scratch`, a file-scope device array that every GPU
+// the library runs on holds until the process ends; the block is dedispersed
+// chunk after chunk on the caller's stream (each chunk's two stages finish
+// reading the array before the next chunk's first stage writes it, by stream
+// order).  Every chunk reads its own window of the caller's rows (a 16-byte
+// aligned base and a byte offset of 0..15) and writes its own output columns,
+// so the result equals one tx_dedisperse of the whole block.  Calls that
+// overlap on one GPU (other streams, other threads) share the array and race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[TX_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on device `dev` (current): looked up once per
+// device with hipGetSymbolAddress, since in host code the array's name is a
+// host-side stand-in, not the device's copy.
+static hipError_t noalloc_scratch(int dev, void** ptr) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
+// Largest chunk (a multiple of the second-stage tile, at most nt) whose
+// first-stage series fit `bytes` with tiles `t`, or 0 if not even one tile's
+// do.  The scratch a chunk needs grows with its length.
+static int64_t largest_chunk(const tx_plan_s* p, int64_t nt, const Tiles& t, int64_t bytes) {
+    const DedispGeom g1 = dedisp_geometry(p, 1, t);
+    if (!g1.ok || g1.ws_bytes > bytes) return 0;
+    const int64_t tt2 = g1.tt2;
+    int64_t lo = 1, hi = (nt + tt2 - 1) / tt2;       // whole tiles: lo fits
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (dedisp_geometry(p, std::min(nt, mid * tt2), t).ws_bytes <= bytes) lo = mid; else hi = mid - 1;
+    }
+    return std::min(nt, lo * tt2);
+}
+
+hipError_t launch_dedisperse_noalloc(const tx_plan_s* p, const Tiles& want, const uint8_t* d_in, int64_t in_pitch,
+                                     int64_t nt, int32_t* d_out, int64_t out_pitch, hipStream_t stream, int dev,
+                                     int64_t* need_bytes) {
+    *need_bytes = 0;
+    const int64_t cap = TX_NOALLOC_SCRATCH_BYTES;
+    // The plan's tiles, else the first-stage variant (second stage kept) that
+    // gives the longest chunk: a shorter first-stage tile shortens the series.
+    Tiles best = want;
+    int64_t chunk = largest_chunk(p, nt, want, cap);
+    if (chunk < nt) {
+        for (int v = 0; v < kNS1; ++v) {
+            Tiles t = want;
+            t.s1 = v;
+            t.s1_lds = 0;
+            const int64_t c = largest_chunk(p, nt, t, cap);
+            if (c > chunk) {
+                chunk = c;
+                best = t;
+            }
+        }
+    }
+    if (chunk <= 0) {
+        int64_t smallest = INT64_MAX;
+        for (int v = 0; v < kNS1; ++v) {
+            Tiles t = want;
+            t.s1 = v;
+            t.s1_lds = 0;
+            const DedispGeom g = dedisp_geometry(p, 1, t);
+            if (g.ok) smallest = std::min(smallest, g.ws_bytes);
+        }
+        *need_bytes = smallest == INT64_MAX ? -1 : smallest;
+        return hipErrorInvalidValue;
+    }
+    void* ws = nullptr;
+    hipError_t e = noalloc_scratch(dev, &ws);
+    if (e != hipSuccess) return e;
+    for (int64_t c0 = 0; c0 < nt; c0 += chunk) {
+        const int64_t n = std::min(chunk, nt - c0);
+        const DedispGeom geo = dedisp_geometry(p, n, best);
+        if (!geo.ok || geo.ws_bytes > cap) return hipErrorInvalidValue;
+        e = launch_dedisperse(p, geo, d_in + (c0 & ~int64_t(15)), in_pitch, n, d_out + c0, out_pitch,
+                              static_cast<uint16_t*>(ws), stream, static_cast<int>(c0 & 15));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace tx
