@@ -12,6 +12,9 @@ computes on its hot path:
 * the cold-plasma delay (Sec. 2.3, Eq. 1) turned into integer sample delays;
 * per-channel power sums, skewness and kurtosis, and the channel mask of the
   narrow-band RFI filter (Sec. 2.2);
+* per-channel normalisation (Sec. 2.1: zero mean and unit variance, or
+  inverse-variance weights), dedispersion of the normalised block and the
+  matched filter of its float series;
 * the "transpose" of time-major blocks into channel rows (Sec. 2.3,
   Fig. "dedispersion_flow");
 * downsampling in time before a DM range of a dedispersion plan (Sec. 2.3);
@@ -57,4 +60,15 @@ from .ref import (  # noqa: F401
     channel_power_sums,
     channel_moments,
     skf_mask,
+    WEIGHT_UNIT,
+    WEIGHT_INVERSE_VAR,
+    channel_mean_var,
+    norm_weights,
+    normalise,
+    dedisperse_subband_norm,
+    norm_abs_bound,
+    float_stats,
+    boxcar_snr_series_float,
+    boxcar_peaks_float,
+    boxcar_candidates_float,
 )

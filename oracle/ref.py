@@ -575,3 +575,145 @@ def skf_mask(sums, nt, threshold):
         mask[c] = 0 if bad[i] else 1
     return mask
 
+
+
+# ---------------------------------------------------------------------------
+# Normalisation (Sec. 2.1) and dedispersion of normalised data
+# ---------------------------------------------------------------------------
+
+WEIGHT_UNIT = 0          # scale a channel by 1 / sigma: zero mean, unit variance
+WEIGHT_INVERSE_VAR = 1   # scale a channel by 1 / sigma^2: each channel weighted by its inverse variance
+
+
+def channel_mean_var(sums, nt):
+    """Mean and population variance of each channel from its exact sums
+    (sum x, sum x^2, ...) over nt samples: mean = S1 / n and
+    var = (n S2 - S1^2) / n^2, the numerator an exact integer, each turned
+    to float64 once."""
+    n = int(nt)
+    out = []
+    for row in np.asarray(sums).tolist():
+        s1, s2 = int(row[0]), int(row[1])
+        out.append((float(s1) / float(n), float(n * s2 - s1 * s1) / float(n * n)))
+    return out
+
+
+def norm_weights(sums, nt, weighting=WEIGHT_UNIT):
+    """Per-channel normalisation of Sec. 2.1 as (scale, offset) pairs, so
+    that a channel's normalised sample is scale * x - offset:
+      * WEIGHT_UNIT: scale = 1 / sigma, offset = mean / sigma (mean zero and
+        unit variance in every channel; the paper's "adjusting the data to a
+        mean of zero and unity variance");
+      * WEIGHT_INVERSE_VAR: scale = 1 / sigma^2, offset = mean / sigma^2 (the
+        reading of its "reweighting ... with the reciprocal of its variance"
+        as inverse-variance weights).
+    A channel of zero variance gets (0, 0): it adds nothing.  Computed in
+    float64 and rounded to float32 once (the values both the oracle and the
+    device kernels then use), returned as float64 arrays holding those
+    float32 values."""
+    scale = np.zeros(len(sums), dtype=np.float64)
+    offset = np.zeros(len(sums), dtype=np.float64)
+    for c, (mean, var) in enumerate(channel_mean_var(sums, nt)):
+        if not var > 0.0:
+            continue
+        s = 1.0 / math.sqrt(var) if weighting == WEIGHT_UNIT else 1.0 / var
+        scale[c] = float(np.float32(s))
+        offset[c] = float(np.float32(s * mean))
+    return scale, offset
+
+
+def normalise(x, scale, offset):
+    """The normalised block: scale[c] * x[c][t] - offset[c], float64 (exact
+    for float32 scale and offset and uint8 samples but for one rounding)."""
+    x = np.asarray(x).astype(np.float64)
+    return x * np.asarray(scale, dtype=np.float64)[:, None] - np.asarray(offset, dtype=np.float64)[:, None]
+
+
+def dedisperse_subband_norm(x, plan: Plan, nt, scale, offset):
+    """Two-stage sub-band dedispersion (Sec. 2.3) of the normalised block,
+    in float64: stage 1 at the coarse DMs per sub-band, stage 2 at the fine
+    DMs, the same plan and offsets as the integer path."""
+    return dedisperse_subband(normalise(x, scale, offset), plan, nt)
+
+
+def norm_abs_bound(x, plan: Plan, nt, scale, offset):
+    """Per output, the sum over channels of |normalised sample| it adds:
+    sum_ch |scale x - offset| at the sample's effective offset.  A float32
+    evaluation that rounds every channel term once and sums m terms per
+    sub-band then nsub per trial errs by at most (m + nsub + 1) 2^-24 times
+    this (the recursive-summation bound); the tests use it as the tolerance."""
+    a = np.abs(normalise(x, scale, offset))
+    return dedisperse_offsets(a, plan.offsets, nt)
+
+
+def float_stats(y):
+    """Noise statistics of one float series for the matched filter: the
+    population mean and variance of its T values, from their float64 sums,
+    var = S2 / T - (S1 / T)^2.  Returns (mean, var)."""
+    y = np.asarray(y, dtype=np.float64)
+    T = float(y.shape[0])
+    s1 = float(np.sum(y))
+    s2 = float(np.sum(y * y))
+    mean = s1 / T
+    return mean, s2 / T - mean * mean
+
+
+def boxcar_snr_series_float(y, w):
+    """S/N of every window [t, t + w) of a float series (Sec. 2.4, Eq. 5):
+    (S - w mean) / (sigma sqrt(w)), S from a float64 running sum."""
+    y = np.asarray(y, dtype=np.float64)
+    T = y.shape[0]
+    mean, var = float_stats(y)
+    if not var > 0.0 or w > T:
+        return np.zeros(max(T - w + 1, 0))
+    p = np.zeros(T + 1, dtype=np.float64)
+    np.cumsum(y, out=p[1:])
+    S = p[w:T + 1] - p[0:T - w + 1]
+    return (S - w * mean) / (math.sqrt(var) * math.sqrt(float(w)))
+
+
+def boxcar_peaks_float(Y, widths):
+    """Per row: (snr, width, start) of the largest S/N over widths and
+    starts (per width the earliest start with the largest window sum; ties
+    across widths to the smaller width); (0, widths[0], 0) for a row of zero
+    variance."""
+    widths = sorted(int(v) for v in widths)
+    out = []
+    for d in range(Y.shape[0]):
+        y = np.asarray(Y[d], dtype=np.float64)
+        mean, var = float_stats(y)
+        best = None
+        if var > 0.0:
+            for w in widths:
+                if w > y.shape[0]:
+                    continue
+                s = boxcar_snr_series_float(y, w)
+                t = int(np.argmax(s))
+                if best is None or s[t] > best[0]:
+                    best = (float(s[t]), w, t)
+        out.append(best if best is not None else (0.0, widths[0], 0))
+    return (np.array([o[0] for o in out]), np.array([o[1] for o in out], dtype=np.int32),
+            np.array([o[2] for o in out], dtype=np.int64))
+
+
+def boxcar_candidates_float(Y, widths, gamma):
+    """The thresholded DM-time plane (Sec. 2.5) of float series: (d, t,
+    width, snr) for every start whose best width (ties to the smaller) has
+    S/N >= gamma, sorted by (d, t)."""
+    widths = sorted(int(v) for v in widths)
+    out = []
+    for d in range(Y.shape[0]):
+        y = np.asarray(Y[d], dtype=np.float64)
+        T = y.shape[0]
+        _, var = float_stats(y)
+        if not var > 0.0:
+            continue
+        grid = np.full((len(widths), T), -np.inf)
+        for k, w in enumerate(widths):
+            if w <= T:
+                grid[k, :T - w + 1] = boxcar_snr_series_float(y, w)
+        kb = np.argmax(grid, axis=0)
+        sb = grid[kb, np.arange(T)]
+        for t in np.nonzero(sb >= gamma)[0]:
+            out.append((d, int(t), widths[int(kb[t])], float(sb[t])))
+    return out
