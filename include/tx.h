@@ -556,23 +556,27 @@ tx_status tx_stream_restore(tx_stream_t s, const uint8_t* host_hist, int64_t hel
 tx_status tx_stream_close(tx_stream_t s);
 
 /* ------------------------------------------------------------------------ */
-/* Batches: many beams of uneven shape in one set of persistent launches     */
+/* Batches: many beams of uneven shape in one set of launches                */
 /* ------------------------------------------------------------------------ */
 
 /*
  * A batch holds up to max_jobs jobs.  A job is one block of one beam: its
- * plan (channels, DM grid and sample time may differ between jobs), its input
- * (a device block, or a stream plus the next host/device block), its DM x
- * time output and, optionally, its boxcar peaks and candidates.
- * tx_batch_launch runs the first stage of every job in one persistent launch,
- * then the second stage of every job (one launch per distinct trials-per-
- * workgroup shape), then the boxcar of every job in one launch; each result is
- * bit-identical to the job run alone.  With TX_BATCH_GRAPH the kernel launches
- * are captured into a HIP graph on the first launch and replayed afterwards;
- * the job table lives in device memory and is refreshed before every replay,
- * so later launches may carry other jobs as long as every job's plan uses the
- * same tile variant and fits the captured LDS sizes and grids (else
- * TX_ESTATE; tx_batch_reserve sizes a graph for the largest launch).
+ * plan (channels, DM grid, sample time and tile variants may differ between
+ * jobs), its input (a device block, or a stream plus the next host/device
+ * block), its DM x time output and, optionally, its boxcar peaks and
+ * candidates.  tx_batch_launch runs persistent launches: the first stage of
+ * every job (one launch per first-stage tile variant in use), then the second
+ * stage (one launch per trials-per-workgroup and variant class in use), then
+ * the boxcar of every job; each launch is a grid of as many workgroups as the
+ * device holds at once, and its workgroups take tile after tile (row after
+ * row) from work counters in device memory.  Each result is bit-identical to
+ * the job run alone.  With TX_BATCH_GRAPH the launches are captured into a
+ * HIP graph on the first launch and replayed afterwards; the job table and
+ * work counters live in device memory and are uploaded before every replay,
+ * so later launches may carry any number of other jobs, of any size, as long
+ * as their kernel classes and LDS sizes are among those captured (else
+ * TX_ESTATE before anything is queued; tx_batch_reserve adds classes to a
+ * graph not yet captured).
  */
 typedef struct tx_batch_s* tx_batch_t;
 
@@ -614,19 +618,13 @@ tx_status tx_batch_add_stream_tf(tx_batch_t b, tx_stream_t s, const uint8_t* blo
 tx_status tx_batch_stream_output(tx_batch_t b, int32_t job, int64_t* nt_out);
 
 /* Declare, before the first launch, that jobs may use `plan` with at most
- * max_nt output samples and at most nw boxcar widths (0: no boxcar).  Once a
- * plan is reserved, graphs are kept per size class: a launch of n jobs
- * replays (capturing on first use) the graph of the class c = the next power
- * of two >= n (at most max_jobs), whose kernels and LDS sizes are the union
- * over all reservations and whose grids are c times the largest grid of one
- * reserved job.  So every later launch whose jobs stay within the
- * reservations replays without TX_ESTATE, and small launches replay small
- * grids.  count (1..max_jobs) is checked but does not change the sizing,
- * which already covers max_jobs jobs of the largest reservation.  All
- * reserved plans must use the same tile variants (else TX_EINVAL); the first
- * reserved plan's variants then apply to every job.  Errors: TX_EINVAL,
- * TX_ESTATE (plan on another device), TX_ENOTSUP (capacity beyond 2^31 - 1
- * tiles). */
+ * max_nt output samples and at most nw boxcar widths (0: no boxcar): the
+ * graph captured by the first launch then also holds that plan's kernel
+ * classes and LDS sizes (with its tile variants at reservation time), so
+ * later launches with its jobs replay without TX_ESTATE.  count (1..max_jobs)
+ * is checked only: persistent grids hold any number of jobs.  Errors:
+ * TX_EINVAL, TX_ESTATE (plan on another device), TX_ENOTSUP (a tile does not
+ * fit the device's LDS). */
 tx_status tx_batch_reserve(tx_batch_t b, tx_plan_t plan, int32_t nw, int64_t max_nt, int32_t count);
 
 /* Queue all jobs on `stream`.  The job table is uploaded on `stream` and the
@@ -636,6 +634,15 @@ tx_status tx_batch_reserve(tx_batch_t b, tx_plan_t plan, int32_t nw, int64_t max
  * TX_EINVAL (no jobs), TX_ESTATE (a job does not fit a captured graph),
  * TX_ENOMEM, TX_EDEVICE. */
 tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream);
+
+/* Completion of the batch's last launch (all its kernels, copies and stream
+ * shifts): tx_batch_wait blocks the host until that work has finished and
+ * returns TX_EDEVICE (text in tx_last_error) if the device reported an error
+ * for it; tx_batch_query sets *done to 1 when it has finished, 0 while it
+ * runs, without blocking.  Before the first launch both report completion.
+ * Errors: TX_EINVAL, TX_EDEVICE. */
+tx_status tx_batch_wait(tx_batch_t b);
+tx_status tx_batch_query(tx_batch_t b, int32_t* done);
 
 tx_status tx_batch_destroy(tx_batch_t b);
 

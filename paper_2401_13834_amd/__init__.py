@@ -482,6 +482,8 @@ _SIGS2 = {
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "tx_pool_trim": (ctypes.c_int, []),
     "tx_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "tx_batch_wait": (ctypes.c_int, [ctypes.c_void_p]),
+    "tx_batch_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "tx_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 _SIGS.update(_SIGS2)
@@ -629,6 +631,16 @@ class Batch:
 
     def launch(self, stream=None):
         _check(lib().tx_batch_launch(self._h, _stream(stream)), "tx_batch_launch")
+
+    def wait(self):
+        """Block until the last launch has finished (raises on a device error)."""
+        _check(lib().tx_batch_wait(self._h), "tx_batch_wait")
+
+    def done(self):
+        """True once the last launch has finished (no blocking)."""
+        d = ctypes.c_int32()
+        _check(lib().tx_batch_query(self._h, ctypes.byref(d)), "tx_batch_query")
+        return bool(d.value)
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -1,7 +1,12 @@
 // Batches: the jobs of many beams (uneven channel counts, block lengths and DM
-// grids) run as one persistent launch per stage, optionally captured in a HIP
-// graph.  The job tables live in device memory and are refreshed before every
-// launch, so a captured graph can be replayed over a different set of jobs.
+// grids, each with its own plan's tile variants) run as persistent launches:
+// one per first-stage variant, one per (second-stage trials per workgroup,
+// variant) class and one for the boxcar of every job, each a grid of what the
+// device holds at once whose workgroups take tile after tile from work
+// counters in device memory.  Optionally the launches are captured in a HIP
+// graph.  The job tables and counters live in device memory and are uploaded
+// before every launch, so a captured graph can be replayed over a different
+// set of jobs.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -13,12 +18,17 @@ namespace {
 
 constexpr int kIWs[] = {16, 13, 8, 4, 2, 1};
 constexpr int kNIW = 6;
+constexpr int kQueues = 8;           // work counters per launch (one per XCD's eighth of the items)
 
 int iw_index(int iw) {
     for (int k = 0; k < kNIW; ++k)
         if (kIWs[k] == iw) return k;
     return -1;
 }
+
+int n_s1() { return tx::stage1_variant_count(); }
+int n_s2() { return kNIW * tx::stage2_variant_count(); }   // classes (iw, variant)
+int s2_class(int iw, int variant) { return iw_index(iw) * tx::stage2_variant_count() + variant; }
 
 struct Job {
     tx_plan_s* plan = nullptr;
@@ -35,33 +45,48 @@ struct Job {
     int64_t nt_out = 0;                // outputs produced by the last launch
 };
 
-// Layout of the integer table: prefix sums and job counts of every launch.
+// Layout of the integer table, for max_jobs M: per launch class its info
+// (jobs, first job, first prefix entry), the tile prefix sums of each stage
+// (a class's segment holds its jobs + 1 entries) and the work counters.
 struct IntLayout {
-    int max_jobs;
-    int p1() const { return 0; }
-    int n1() const { return max_jobs + 1; }
-    int p2(int g) const { return max_jobs + 2 + g * (max_jobs + 2); }
-    int n2(int g) const { return p2(g) + max_jobs + 1; }
-    int pb() const { return p2(kNIW); }
-    int nb() const { return pb() + max_jobs + 1; }
-    int size() const { return nb() + 1; }
+    int M = 0, C1 = 0, C2 = 0;
+    int info1(int c) const { return 3 * c; }
+    int info2(int c) const { return 3 * (C1 + c); }
+    int infob() const { return 3 * (C1 + C2); }
+    int pre1() const { return infob() + 3; }
+    int pre2() const { return pre1() + M + C1; }
+    int preb() const { return pre2() + M + C2; }
+    int q1(int c) const { return preb() + M + 1 + kQueues * c; }
+    int q2(int c) const { return q1(C1) + kQueues * c; }
+    int qb() const { return q2(C2); }
+    int size() const { return qb() + kQueues; }
 };
 
 struct Signature {            // what a captured graph bakes in
-    int s1 = -1, lds1 = 0, s2 = -1, lds2 = 0;
-    bool groups[kNIW] = {};
-    int nwt = 0;
+    std::vector<int> lds1;    // per first-stage class: dynamic LDS (0 = not launched)
+    std::vector<int> lds2;    // per second-stage class
+    int nwt = 0;              // boxcar instance (0 = no boxcar)
     int ldsb = 0;             // boxcar dynamic LDS (per-(tile, width) maxima)
-    bool any_box = false;
-    // grids: first-stage tiles, second-stage tiles per group, boxcar rows
-    int64_t g1 = 0, g2[kNIW] = {}, gb = 0;
-};
-
-struct GraphSlot {
-    int cap_jobs = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    Signature sig;
+    void init() {
+        lds1.assign(static_cast<size_t>(n_s1()), 0);
+        lds2.assign(static_cast<size_t>(n_s2()), 0);
+        nwt = 0;
+        ldsb = 0;
+    }
+    void merge(const Signature& o) {
+        for (size_t c = 0; c < lds1.size(); ++c) lds1[c] = std::max(lds1[c], o.lds1[c]);
+        for (size_t c = 0; c < lds2.size(); ++c) lds2[c] = std::max(lds2[c], o.lds2[c]);
+        nwt = std::max(nwt, o.nwt);
+        ldsb = std::max(ldsb, o.ldsb);
+    }
+    // Every kernel of `need` is in this signature with at least its LDS.
+    bool holds(const Signature& need) const {
+        for (size_t c = 0; c < lds1.size(); ++c)
+            if (need.lds1[c] > 0 && lds1[c] < need.lds1[c]) return false;
+        for (size_t c = 0; c < lds2.size(); ++c)
+            if (need.lds2[c] > 0 && lds2[c] < need.lds2[c]) return false;
+        return need.nwt == 0 || nwt >= need.nwt;
+    }
 };
 
 }  // namespace
@@ -71,43 +96,35 @@ struct tx_batch_s {
     int max_jobs = 0;
     uint32_t flags = 0;
     std::vector<Job> jobs;
-    IntLayout L{0};
+    IntLayout L;
     // device tables and their pinned host mirror (one contiguous block)
     size_t off_s1 = 0, off_s2 = 0, off_bx = 0, off_int = 0, table_bytes = 0;
     uint8_t* d_tab = nullptr;
     uint8_t* h_tab = nullptr;
     hipEvent_t uploaded = nullptr;     // the last upload from h_tab has been consumed
     bool upload_pending = false;
+    hipEvent_t finished = nullptr;     // recorded after the last launch's work
+    bool launched = false;
     // first-stage series of every job of a launch
     void* scratch = nullptr;
     int64_t scratch_bytes = 0;
-    // captured graphs, one per size class (jobs per launch, a power of two,
-    // when plans were reserved; a single class otherwise)
-    std::vector<GraphSlot> graphs;
+    // the captured graph (TX_BATCH_GRAPH) and the kernels it holds
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Signature captured;
     // plans declared ahead of the first launch (tx_batch_reserve): the union
-    // of their kernels and LDS sizes, and the largest grids of one job
+    // of their kernels and LDS sizes
     bool reserved = false;
     Signature floor;
-    tx::Tiles tiles{};
 };
 
 namespace {
 
-void destroy_graphs(tx_batch_s* b) {
-    for (GraphSlot& g : b->graphs) {
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        if (g.graph) (void)hipGraphDestroy(g.graph);
-    }
-    b->graphs.clear();
-}
-
-// Size class of a launch of n jobs: the next power of two (at most max_jobs)
-// when plans were reserved, so that small launches replay small grids.
-int size_class(const tx_batch_s* b, int n) {
-    if (!b->reserved) return b->max_jobs;
-    int c = 1;
-    while (c < n) c <<= 1;
-    return std::min(c, b->max_jobs);
+void destroy_graph(tx_batch_s* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
 }
 
 tx_status fill_box(const tx_batch_boxcar* box, tx::BoxcarArgs* a) {
@@ -130,29 +147,59 @@ tx_status fill_box(const tx_batch_boxcar* box, tx::BoxcarArgs* a) {
     return TX_OK;
 }
 
-// Kernel launches of one batch launch (captured or direct).
-hipError_t run_kernels(tx_batch_s* b, const Signature& sig, hipStream_t st) {
-    const int* ints = reinterpret_cast<const int*>(b->d_tab + b->off_int);
-    const tx::Stage1Args* s1 = reinterpret_cast<const tx::Stage1Args*>(b->d_tab + b->off_s1);
-    const tx::Stage2Args* s2 = reinterpret_cast<const tx::Stage2Args*>(b->d_tab + b->off_s2);
-    const tx::BoxcarArgs* bx = reinterpret_cast<const tx::BoxcarArgs*>(b->d_tab + b->off_bx);
+// Kernels a job of `plan` with `nt` outputs (nw boxcar widths, 0 for none)
+// needs: its first- and second-stage classes and their LDS, its boxcar.
+tx_status job_needs(const tx_plan_s* plan, int64_t nt, int nw, Signature* need, tx::DedispGeom* geo_out) {
+    const tx::DedispGeom g = tx::dedisp_geometry(plan, std::max<int64_t>(nt, 1), tx::plan_tiles(plan));
+    if (!g.ok) return TX_ENOTSUP;
+    need->lds1[static_cast<size_t>(g.tiles.s1)] = std::max(need->lds1[static_cast<size_t>(g.tiles.s1)], g.lds1);
+    const int c2 = s2_class(g.iw, g.tiles.s2);
+    need->lds2[static_cast<size_t>(c2)] = std::max(need->lds2[static_cast<size_t>(c2)], g.lds2);
+    if (nw > 0) {
+        need->nwt = std::max(need->nwt, tx::boxcar_nwt(nw));
+        need->ldsb = std::max(need->ldsb, tx::boxcar_tmax_bytes(need->nwt, nt));
+    }
+    if (geo_out) *geo_out = g;
+    return TX_OK;
+}
+
+// Kernel launches of one batch launch (captured or direct).  tiles*: work
+// items per launch class, for direct launches (a graph passes none and gets
+// grids that hold any number).
+hipError_t run_kernels(tx_batch_s* b, const Signature& sig, hipStream_t st, const std::vector<int64_t>* t1,
+                       const std::vector<int64_t>* t2, int64_t tb) {
+    int* ints = reinterpret_cast<int*>(b->d_tab + b->off_int);
+    const auto* s1 = reinterpret_cast<const tx::Stage1Args*>(b->d_tab + b->off_s1);
+    const auto* s2 = reinterpret_cast<const tx::Stage2Args*>(b->d_tab + b->off_s2);
+    const auto* bx = reinterpret_cast<const tx::BoxcarArgs*>(b->d_tab + b->off_bx);
+    uint32_t* q = reinterpret_cast<uint32_t*>(ints);
+    const IntLayout& L = b->L;
     hipError_t e = hipSuccess;
-    if (sig.any_box) {
-        e = tx::launch_zero_counts(bx, ints + b->L.nb(), b->max_jobs, st);
+    if (sig.nwt > 0) {
+        e = tx::launch_zero_counts(bx, ints + L.infob(), b->max_jobs, st);
         if (e != hipSuccess) return e;
     }
-    e = tx::launch_stage1_batch(sig.s1, sig.lds1, s1, ints + b->L.p1(), ints + b->L.n1(), static_cast<int>(sig.g1),
-                                st);
-    if (e != hipSuccess) return e;
-    for (int g = 0; g < kNIW; ++g) {
-        if (!sig.groups[g]) continue;
-        e = tx::launch_stage2_batch(kIWs[g], sig.s2, sig.lds2, s2 + static_cast<size_t>(g) * b->max_jobs,
-                                    ints + b->L.p2(g), ints + b->L.n2(g), static_cast<int>(sig.g2[g]), st);
+    for (int c = 0; c < L.C1; ++c) {
+        if (sig.lds1[static_cast<size_t>(c)] <= 0) continue;
+        const int64_t tiles = t1 ? (*t1)[static_cast<size_t>(c)] : 0;
+        if (t1 && tiles == 0) continue;
+        const tx::BatchRefs r{s1, ints + L.pre1(), ints + L.info1(c), q + L.q1(c)};
+        e = tx::launch_stage1_batch(c, sig.lds1[static_cast<size_t>(c)], r, tiles, st);
         if (e != hipSuccess) return e;
     }
-    if (sig.any_box)
-        e = tx::launch_boxcar_batch(sig.nwt, sig.ldsb, bx, ints + b->L.pb(), ints + b->L.nb(), static_cast<int>(sig.gb),
-                                    st);
+    const int nv2 = tx::stage2_variant_count();
+    for (int c = 0; c < L.C2; ++c) {
+        if (sig.lds2[static_cast<size_t>(c)] <= 0) continue;
+        const int64_t tiles = t2 ? (*t2)[static_cast<size_t>(c)] : 0;
+        if (t2 && tiles == 0) continue;
+        const tx::BatchRefs r{s2, ints + L.pre2(), ints + L.info2(c), q + L.q2(c)};
+        e = tx::launch_stage2_batch(kIWs[c / nv2], c % nv2, sig.lds2[static_cast<size_t>(c)], r, tiles, st);
+        if (e != hipSuccess) return e;
+    }
+    if (sig.nwt > 0 && (!t1 || tb > 0)) {
+        const tx::BatchRefs r{bx, ints + L.preb(), ints + L.infob(), q + L.qb()};
+        e = tx::launch_boxcar_batch(sig.nwt, sig.ldsb, r, t1 ? tb : 0, st);
+    }
     return e;
 }
 
@@ -170,20 +217,27 @@ tx_status tx_batch_create(int32_t max_jobs, uint32_t flags, tx_batch_t* out) {
     b->device = dev;
     b->max_jobs = max_jobs;
     b->flags = flags;
-    b->L = IntLayout{max_jobs};
+    b->L.M = max_jobs;
+    b->L.C1 = n_s1();
+    b->L.C2 = n_s2();
+    b->captured.init();
+    b->floor.init();
     auto align = [](size_t v) { return (v + 255) / 256 * 256; };
     b->off_s1 = 0;
     b->off_s2 = align(sizeof(tx::Stage1Args) * max_jobs);
-    b->off_bx = b->off_s2 + align(sizeof(tx::Stage2Args) * max_jobs * kNIW);
+    b->off_bx = b->off_s2 + align(sizeof(tx::Stage2Args) * max_jobs);
     b->off_int = b->off_bx + align(sizeof(tx::BoxcarArgs) * max_jobs);
     b->table_bytes = b->off_int + align(sizeof(int) * b->L.size());
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->d_tab), b->table_bytes);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_tab), b->table_bytes);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->finished, hipEventDisableTiming);
     if (e != hipSuccess) {
         tx_batch_destroy(b);
         return tx::status_of(e);
     }
+    // Zero, and the work counters stay zero in the mirror: every upload
+    // resets them on the device.
     std::memset(b->h_tab, 0, b->table_bytes);
     b->jobs.reserve(static_cast<size_t>(max_jobs));
     *out = b;
@@ -273,34 +327,11 @@ tx_status tx_batch_reserve(tx_batch_t b, tx_plan_t plan, int32_t nw, int64_t max
         count > b->max_jobs)
         return TX_EINVAL;
     if (!plan->on_device || plan->device != b->device) return TX_ESTATE;
-    const tx::Tiles t = tx::plan_tiles(plan);
-    if (b->reserved && (t.s1 != b->tiles.s1 || t.s2 != b->tiles.s2)) return TX_EINVAL;
-    const tx::DedispGeom g = tx::dedisp_geometry(plan, max_nt, t);
-    if (!g.ok) return TX_ENOTSUP;
-    tx::Stage1Args a1;
-    tx::Stage2Args a2;
-    tx::fill_stage_args(plan, g, nullptr, max_nt + plan->overlap, max_nt, nullptr, max_nt + 1, nullptr, &a1, &a2);
-    Signature f = b->floor;
-    f.s1 = g.tiles.s1;
-    f.s2 = g.tiles.s2;
-    f.lds1 = std::max(f.lds1, g.lds1);
-    f.lds2 = std::max(f.lds2, g.lds2);
-    const int gi = iw_index(g.iw);
-    f.groups[gi] = true;
-    // grids of one job (a launch of n jobs is sized n times these)
-    f.g1 = std::max(f.g1, tx::stage1_tiles(a1));
-    f.g2[gi] = std::max(f.g2[gi], tx::stage2_tiles(a2));
-    if (nw > 0) {
-        f.any_box = true;
-        f.nwt = std::max(f.nwt, tx::boxcar_nwt(nw));
-        f.ldsb = std::max(f.ldsb, tx::boxcar_tmax_bytes(f.nwt, max_nt));
-        f.gb = std::max<int64_t>(f.gb, plan->ndm);
-    }
-    const int64_t m = b->max_jobs;
-    if (f.g1 * m > INT32_MAX || f.g2[gi] * m > INT32_MAX || f.gb * m > INT32_MAX) return TX_ENOTSUP;
-    (void)count;
-    b->floor = f;
-    b->tiles = t;
+    Signature need;
+    need.init();
+    const tx_status st = job_needs(plan, max_nt, nw, &need, nullptr);
+    if (st != TX_OK) return st;
+    b->floor.merge(need);
     b->reserved = true;
     return TX_OK;
 }
@@ -317,14 +348,28 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
     if (hipGetDevice(&dev) != hipSuccess) return TX_EDEVICE;
     if (dev != b->device) return TX_ESTATE;
     const int n = static_cast<int>(b->jobs.size());
+    const bool use_graph = (b->flags & TX_BATCH_GRAPH) && stream != nullptr;
 
-    // Tile choice: the reserved plans, else the first job's plan, decide the
-    // variants; every job's LDS need (and every reserved plan's) raises the
-    // batch's LDS sizes.
-    const tx::Tiles t0 = b->reserved ? b->tiles : tx::plan_tiles(b->jobs[0].plan);
-    Signature sig = b->reserved ? b->floor : Signature{};
-    std::vector<tx::DedispGeom> geo(static_cast<size_t>(n));
-    // Stream jobs: copy the blocks behind the held histories first.
+    // Kernels and LDS this launch needs (each job with its plan's own tiles;
+    // a graph about to be captured also covers stream jobs at their largest
+    // block and the reserved plans).
+    Signature need;
+    need.init();
+    for (const Job& j : b->jobs) {
+        const int64_t nt_cap = j.stream ? j.stream->max_block : j.nt;
+        const tx_status st = job_needs(j.plan, nt_cap, j.has_box ? j.box.nw : 0, &need, nullptr);
+        if (st != TX_OK) return st;
+    }
+    Signature sig;
+    if (use_graph && b->exec) {
+        if (!b->captured.holds(need)) return TX_ESTATE;      // before anything is queued
+        sig = b->captured;
+    } else {
+        sig = need;
+        if (use_graph) sig.merge(b->floor);
+    }
+
+    // Stream jobs: copy each block behind its history (this fixes nt_out).
     for (Job& j : b->jobs) {
         j.nt_out = j.nt;
         if (j.stream) {
@@ -336,96 +381,17 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
             j.nt_out = n_out;
         }
     }
-    int64_t scratch_need = 0;
+    std::vector<tx::DedispGeom> geo(static_cast<size_t>(n));
     std::vector<int64_t> scratch_off(static_cast<size_t>(n), 0);
+    int64_t scratch_need = 0;
     for (int k = 0; k < n; ++k) {
         Job& j = b->jobs[static_cast<size_t>(k)];
-        geo[static_cast<size_t>(k)] = tx::dedisp_geometry(j.plan, std::max<int64_t>(j.nt_out, 1), t0);
-        const tx::DedispGeom& g = geo[static_cast<size_t>(k)];
-        if (!g.ok) return TX_ENOTSUP;
-        sig.s1 = g.tiles.s1;
-        sig.s2 = g.tiles.s2;
-        sig.lds1 = std::max(sig.lds1, g.lds1);
-        sig.lds2 = std::max(sig.lds2, g.lds2);
-        sig.groups[iw_index(g.iw)] = true;   // by plan, so a graph captured while priming still fits
-        if (j.has_box) {
-            sig.any_box = true;
-            sig.nwt = std::max(sig.nwt, tx::boxcar_nwt(j.box.nw));
-        }
+        geo[static_cast<size_t>(k)] = tx::dedisp_geometry(j.plan, std::max<int64_t>(j.nt_out, 1), tx::plan_tiles(j.plan));
+        if (!geo[static_cast<size_t>(k)].ok) return TX_ENOTSUP;
         if (j.nt_out > 0) {
             scratch_off[static_cast<size_t>(k)] = scratch_need;
-            scratch_need += g.ws_bytes;
+            scratch_need += geo[static_cast<size_t>(k)].ws_bytes;
         }
-    }
-    // Grids: the tiles and rows of this launch.
-    int64_t tot1 = 0, tot2[kNIW] = {}, totb = 0;
-    for (int k = 0; k < n; ++k) {
-        const Job& j = b->jobs[static_cast<size_t>(k)];
-        if (j.nt_out <= 0) continue;
-        tx::Stage1Args a1;
-        tx::Stage2Args a2;
-        tx::fill_stage_args(j.plan, geo[static_cast<size_t>(k)], nullptr, 0, j.nt_out, nullptr, 0, nullptr, &a1, &a2);
-        tot1 += tx::stage1_tiles(a1);
-        tot2[iw_index(geo[static_cast<size_t>(k)].iw)] += tx::stage2_tiles(a2);
-        if (j.has_box) totb += j.plan->ndm;
-    }
-    // Boxcar dynamic LDS: the per-(tile, width) maxima of the longest row that
-    // fits (longer rows rescan their tiles instead).
-    int ldsb = 0;
-    for (const Job& j : b->jobs)
-        if (j.has_box && j.nt_out > 0) ldsb = std::max(ldsb, tx::boxcar_tmax_bytes(sig.nwt, j.nt_out));
-    const bool use_graph = (b->flags & TX_BATCH_GRAPH) && stream != nullptr;
-    const int cls = size_class(b, n);
-    GraphSlot* slot = nullptr;
-    if (use_graph)
-        for (GraphSlot& g : b->graphs)
-            if (g.cap_jobs == cls) slot = &g;
-    if (slot) {
-        // A captured graph fixes the kernels, grids and LDS sizes.
-        Signature want = slot->sig;
-        bool fits = sig.s1 == want.s1 && sig.s2 == want.s2 && sig.lds1 <= want.lds1 && sig.lds2 <= want.lds2 &&
-                    sig.nwt <= want.nwt && (!sig.any_box || want.any_box) && tot1 <= want.g1 && totb <= want.gb;
-        for (int g = 0; g < kNIW; ++g)
-            if ((sig.groups[g] && !want.groups[g]) || tot2[g] > want.g2[g]) fits = false;
-        if (!fits) return TX_ESTATE;
-        sig = want;
-    } else {
-        // Direct launches use the exact grids.  A graph captured now is sized
-        // for its size class from the reserved plans (else for this launch,
-        // with every stream job counted at its largest block).
-        Signature f = b->floor;
-        f.g1 *= cls;
-        f.gb *= cls;
-        for (int g = 0; g < kNIW; ++g) f.g2[g] *= cls;
-        if (use_graph && !b->reserved) {
-            int64_t c1 = 0, c2[kNIW] = {}, cb = 0;
-            for (int k = 0; k < n; ++k) {
-                const Job& j = b->jobs[static_cast<size_t>(k)];
-                const int64_t nt_cap = j.stream ? std::max(j.stream->max_block, j.nt_out) : j.nt_out;
-                if (nt_cap <= 0) continue;
-                const tx::DedispGeom gc = tx::dedisp_geometry(j.plan, nt_cap, t0);
-                if (!gc.ok) return TX_ENOTSUP;
-                tx::Stage1Args a1;
-                tx::Stage2Args a2;
-                tx::fill_stage_args(j.plan, gc, nullptr, 0, nt_cap, nullptr, 0, nullptr, &a1, &a2);
-                c1 += tx::stage1_tiles(a1);
-                c2[iw_index(gc.iw)] += tx::stage2_tiles(a2);
-                if (j.has_box) {
-                    cb += j.plan->ndm;
-                    ldsb = std::max(ldsb, tx::boxcar_tmax_bytes(sig.nwt, nt_cap));
-                }
-            }
-            tot1 = std::max(tot1, c1);
-            totb = std::max(totb, cb);
-            for (int g = 0; g < kNIW; ++g) tot2[g] = std::max(tot2[g], c2[g]);
-        }
-        sig.g1 = std::max(tot1, use_graph ? f.g1 : 0);
-        sig.gb = std::max(totb, use_graph ? f.gb : 0);
-        sig.ldsb = std::max(ldsb, use_graph ? f.ldsb : 0);
-        for (int g = 0; g < kNIW; ++g) sig.g2[g] = std::max(tot2[g], use_graph ? f.g2[g] : 0);
-        if (sig.g1 > INT32_MAX || sig.gb > INT32_MAX) return TX_ENOTSUP;
-        for (int g = 0; g < kNIW; ++g)
-            if (sig.g2[g] > INT32_MAX) return TX_ENOTSUP;
     }
     // First-stage scratch of every job (stream-ordered, so in-flight work
     // keeps the old buffer until it is done).
@@ -441,21 +407,52 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
         }
         b->scratch_bytes = scratch_need;
     }
-    // Job tables into the pinned mirror (after the previous upload was consumed).
+    // Job tables into the pinned mirror (after the previous upload was
+    // consumed), grouped by launch class.
     if (b->upload_pending) {
         const hipError_t e = hipEventSynchronize(b->uploaded);
         if (e != hipSuccess) return tx::status_of(e);
         b->upload_pending = false;
     }
+    const IntLayout& L = b->L;
     auto* h1 = reinterpret_cast<tx::Stage1Args*>(b->h_tab + b->off_s1);
     auto* h2 = reinterpret_cast<tx::Stage2Args*>(b->h_tab + b->off_s2);
     auto* hb = reinterpret_cast<tx::BoxcarArgs*>(b->h_tab + b->off_bx);
     int* hi = reinterpret_cast<int*>(b->h_tab + b->off_int);
-    int n1 = 0, nb = 0;
-    int n2[kNIW] = {};
-    hi[b->L.p1()] = 0;
-    for (int g = 0; g < kNIW; ++g) hi[b->L.p2(g)] = 0;
-    hi[b->L.pb()] = 0;
+    std::vector<int> cls1(static_cast<size_t>(n), -1), cls2(static_cast<size_t>(n), -1);
+    std::vector<int> cnt1(static_cast<size_t>(L.C1), 0), cnt2(static_cast<size_t>(L.C2), 0);
+    for (int k = 0; k < n; ++k) {
+        if (b->jobs[static_cast<size_t>(k)].nt_out <= 0) continue;
+        const tx::DedispGeom& g = geo[static_cast<size_t>(k)];
+        cls1[static_cast<size_t>(k)] = g.tiles.s1;
+        cls2[static_cast<size_t>(k)] = s2_class(g.iw, g.tiles.s2);
+        ++cnt1[static_cast<size_t>(g.tiles.s1)];
+        ++cnt2[static_cast<size_t>(cls2[static_cast<size_t>(k)])];
+    }
+    std::vector<int64_t> tiles1(static_cast<size_t>(L.C1), 0), tiles2(static_cast<size_t>(L.C2), 0);
+    std::vector<int> fill1(static_cast<size_t>(L.C1), 0), fill2(static_cast<size_t>(L.C2), 0);
+    {
+        int off = 0;
+        for (int c = 0; c < L.C1; ++c) {
+            hi[L.info1(c)] = cnt1[static_cast<size_t>(c)];
+            hi[L.info1(c) + 1] = off;
+            hi[L.info1(c) + 2] = off + c;
+            hi[L.pre1() + off + c] = 0;
+            fill1[static_cast<size_t>(c)] = off;
+            off += cnt1[static_cast<size_t>(c)];
+        }
+        off = 0;
+        for (int c = 0; c < L.C2; ++c) {
+            hi[L.info2(c)] = cnt2[static_cast<size_t>(c)];
+            hi[L.info2(c) + 1] = off;
+            hi[L.info2(c) + 2] = off + c;
+            hi[L.pre2() + off + c] = 0;
+            fill2[static_cast<size_t>(c)] = off;
+            off += cnt2[static_cast<size_t>(c)];
+        }
+    }
+    int nb = 0;
+    hi[L.preb()] = 0;
     for (int k = 0; k < n; ++k) {
         Job& j = b->jobs[static_cast<size_t>(k)];
         if (j.nt_out <= 0) continue;
@@ -469,15 +466,21 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
         uint16_t* ws = reinterpret_cast<uint16_t*>(static_cast<uint8_t*>(b->scratch) + scratch_off[static_cast<size_t>(k)]);
         tx::fill_stage_args(j.plan, g, in, in_pitch, j.nt_out, j.out, j.out_pitch, ws, &a1, &a2);
         a1.x_off = x_off;
-        a1.lds_bytes = sig.lds1;
-        a2.lds_bytes = sig.lds2;
-        h1[n1] = a1;
-        hi[b->L.p1() + n1 + 1] = hi[b->L.p1() + n1] + static_cast<int>(tx::stage1_tiles(a1));
-        ++n1;
-        const int gi = iw_index(g.iw);
-        h2[static_cast<size_t>(gi) * b->max_jobs + n2[gi]] = a2;
-        hi[b->L.p2(gi) + n2[gi] + 1] = hi[b->L.p2(gi) + n2[gi]] + static_cast<int>(tx::stage2_tiles(a2));
-        ++n2[gi];
+        const int c1 = cls1[static_cast<size_t>(k)], c2 = cls2[static_cast<size_t>(k)];
+        a1.lds_bytes = sig.lds1[static_cast<size_t>(c1)];
+        a2.lds_bytes = sig.lds2[static_cast<size_t>(c2)];
+        {
+            const int pos = fill1[static_cast<size_t>(c1)]++;          // job slot; prefix entry pos + c1 + 1
+            h1[pos] = a1;
+            hi[L.pre1() + pos + c1 + 1] = hi[L.pre1() + pos + c1] + static_cast<int>(tx::stage1_tiles(a1));
+            tiles1[static_cast<size_t>(c1)] += tx::stage1_tiles(a1);
+        }
+        {
+            const int pos = fill2[static_cast<size_t>(c2)]++;
+            h2[pos] = a2;
+            hi[L.pre2() + pos + c2 + 1] = hi[L.pre2() + pos + c2] + static_cast<int>(tx::stage2_tiles(a2));
+            tiles2[static_cast<size_t>(c2)] += tx::stage2_tiles(a2);
+        }
         if (j.has_box) {
             tx::BoxcarArgs bx = j.box;
             bx.y = j.out;
@@ -485,16 +488,20 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
             bx.ndm = j.plan->ndm;
             bx.nt = static_cast<int32_t>(j.nt_out);
             tx::boxcar_fit(&bx, j.box.widths, j.box.nw, j.nt_out);
-            const int need = tx::boxcar_tmax_bytes(sig.nwt, j.nt_out);
-            bx.tmax_ok = (need > 0 && need <= sig.ldsb) ? 1 : 0;
+            const int need_b = tx::boxcar_tmax_bytes(sig.nwt, j.nt_out);
+            bx.tmax_ok = (need_b > 0 && need_b <= sig.ldsb) ? 1 : 0;
             hb[nb] = bx;
-            hi[b->L.pb() + nb + 1] = hi[b->L.pb() + nb] + bx.ndm;
+            hi[L.preb() + nb + 1] = hi[L.preb() + nb] + bx.ndm;
             ++nb;
         }
     }
-    hi[b->L.n1()] = n1;
-    for (int g = 0; g < kNIW; ++g) hi[b->L.n2(g)] = n2[g];
-    hi[b->L.nb()] = nb;
+    hi[L.infob()] = nb;
+    hi[L.infob() + 1] = 0;
+    hi[L.infob() + 2] = 0;
+    for (int c = 0; c < L.C1; ++c)
+        if (tiles1[static_cast<size_t>(c)] > INT32_MAX) return TX_ENOTSUP;
+    for (int c = 0; c < L.C2; ++c)
+        if (tiles2[static_cast<size_t>(c)] > INT32_MAX) return TX_ENOTSUP;
     hipError_t e = hipMemcpyAsync(b->d_tab, b->h_tab, b->table_bytes, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipEventRecord(b->uploaded, stream);
     if (e != hipSuccess) return tx::status_of(e);
@@ -502,34 +509,31 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
 
     // Kernels.
     if (use_graph) {
-        if (!slot) {
-            GraphSlot ns;
-            ns.cap_jobs = cls;
-            ns.sig = sig;
+        if (!b->exec) {
             e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                const hipError_t ek = run_kernels(b, sig, stream);
+                const hipError_t ek = run_kernels(b, sig, stream, nullptr, nullptr, 0);
                 hipGraph_t g = nullptr;
                 e = hipStreamEndCapture(stream, &g);
                 if (ek != hipSuccess) e = ek;
                 if (e == hipSuccess) {
-                    ns.graph = g;
-                    e = hipGraphInstantiate(&ns.exec, g, nullptr, nullptr, 0);
+                    b->graph = g;
+                    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
                 } else if (g) {
                     (void)hipGraphDestroy(g);
                 }
             }
             if (e != hipSuccess) {
-                if (ns.exec) (void)hipGraphExecDestroy(ns.exec);
-                if (ns.graph) (void)hipGraphDestroy(ns.graph);
+                destroy_graph(b);
                 return tx::status_of(e);
             }
-            b->graphs.push_back(ns);
-            slot = &b->graphs.back();
+            b->captured = sig;
         }
-        e = hipGraphLaunch(slot->exec, stream);
+        e = hipGraphLaunch(b->exec, stream);
     } else {
-        e = run_kernels(b, sig, stream);
+        int64_t rows = 0;
+        for (int k = 0; k < nb; ++k) rows += hb[k].ndm;
+        e = run_kernels(b, sig, stream, &tiles1, &tiles2, rows);
     }
     if (e != hipSuccess) return tx::status_of(e);
     // Stream jobs: keep the last `overlap` samples.
@@ -538,13 +542,38 @@ tx_status tx_batch_launch(tx_batch_t b, hipStream_t stream) {
         const tx_status st = tx::stream_advance(j.stream, j.nt, stream);
         if (st != TX_OK) return st;
     }
+    e = hipEventRecord(b->finished, stream);
+    if (e != hipSuccess) return tx::status_of(e);
+    b->launched = true;
     return TX_OK;
+}
+
+tx_status tx_batch_wait(tx_batch_t b) {
+    if (!b) return TX_EINVAL;
+    if (!b->launched) return TX_OK;
+    return tx::status_of(hipEventSynchronize(b->finished));
+}
+
+tx_status tx_batch_query(tx_batch_t b, int32_t* done) {
+    if (!b || !done) return TX_EINVAL;
+    if (!b->launched) {
+        *done = 1;
+        return TX_OK;
+    }
+    const hipError_t e = hipEventQuery(b->finished);
+    if (e == hipErrorNotReady) {
+        (void)hipGetLastError();
+        *done = 0;
+        return TX_OK;
+    }
+    *done = e == hipSuccess ? 1 : 0;
+    return tx::status_of(e);
 }
 
 tx_status tx_batch_destroy(tx_batch_t b) {
     if (!b) return TX_OK;
     if (b->upload_pending) (void)hipEventSynchronize(b->uploaded);
-    destroy_graphs(b);
+    destroy_graph(b);
     if (b->scratch) {
         (void)hipDeviceSynchronize();
         (void)hipFreeAsync(b->scratch, nullptr);
@@ -553,6 +582,7 @@ tx_status tx_batch_destroy(tx_batch_t b) {
     if (b->d_tab) (void)hipFree(b->d_tab);
     if (b->h_tab) (void)hipHostFree(b->h_tab);
     if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+    if (b->finished) (void)hipEventDestroy(b->finished);
     delete b;
     return TX_OK;
 }

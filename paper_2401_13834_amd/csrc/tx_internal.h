@@ -25,6 +25,35 @@ template <typename T>
 __device__ __forceinline__ TX_GLOBAL T* to_global(T* p) {
     return (TX_GLOBAL T*)(p);
 }
+
+// Work items [0, total) of a persistent launch, taken one at a time by whole
+// workgroups from 8 counters in device memory (zero at the launch), counter x
+// handing out the x-th contiguous eighth of the items.  A workgroup starts
+// with the eighth of its own XCD (workgroup ids are dealt to the 8 XCDs in
+// turn), so neighbouring items, which read the same input rows, share an L2,
+// then helps with the others.  Every workgroup leaves once all 8 are spent.
+template <typename F>
+__device__ __forceinline__ void for_each_claimed(int total, uint32_t* queue, F&& f) {
+    __shared__ int s_claim;
+    const int x0 = static_cast<int>(blockIdx.x) & 7;
+    const int q = total >> 3, r = total & 7;
+    for (int k = 0; k < 8; ++k) {
+        const int x = (x0 + k) & 7;
+        const int lo = x * q + (x < r ? x : r);
+        const int n = q + (x < r ? 1 : 0);
+        for (;;) {
+            if (threadIdx.x == 0) s_claim = static_cast<int>(atomicAdd(queue + x, 1u));
+            __syncthreads();
+            // uniform (a scalar register): the job lookup and its arguments
+            // then stay scalar too
+            const int c = __builtin_amdgcn_readfirstlane(s_claim);
+            __syncthreads();
+            if (c >= n) break;
+            f(lo + c);
+            __syncthreads();
+        }
+    }
+}
 #endif
 
 namespace tx {
@@ -248,19 +277,29 @@ void fill_stage_args(const tx_plan_s* p, const DedispGeom& geo, const uint8_t* d
 int64_t stage1_tiles(const Stage1Args& a);
 int64_t stage2_tiles(const Stage2Args& a);
 int stage2_iw(int32_t g);
-// Batch launches: `grid` workgroups (at least the batch's tiles / rows; 0
-// skips the launch).
-hipError_t launch_stage1_batch(int variant, int lds, const Stage1Args* d_jobs, const int* d_prefix,
-                               const int* d_njobs, int grid, hipStream_t stream);
-hipError_t launch_stage2_batch(int iw, int variant, int lds, const Stage2Args* d_jobs, const int* d_prefix,
-                               const int* d_njobs, int grid, hipStream_t stream);
+// Device references of one batch launch (one kernel variant): its jobs start
+// at jobs + info[1], their tile prefix sums at prefix + info[2] (info[0] + 1
+// entries), info[0] jobs; queue holds the launch's 8 work counters.
+struct BatchRefs {
+    const void* jobs;
+    const int* prefix;
+    const int* info;
+    uint32_t* queue;
+};
+// Persistent batch launches: as many workgroups as the device holds at once
+// (fewer if `tiles` > 0 is smaller; 0 sizes a graph for any number of tiles).
+hipError_t launch_stage1_batch(int variant, int lds, const BatchRefs& r, int64_t tiles, hipStream_t stream);
+hipError_t launch_stage2_batch(int iw, int variant, int lds, const BatchRefs& r, int64_t tiles, hipStream_t stream);
 // Boxcar over many row sets: rows of all jobs, job of a row by prefix sums.
-hipError_t launch_boxcar_batch(int nwt, int lds, const BoxcarArgs* d_jobs, const int* d_prefix, const int* d_njobs,
-                               int grid, hipStream_t stream);
+hipError_t launch_boxcar_batch(int nwt, int lds, const BatchRefs& r, int64_t rows, hipStream_t stream);
+// Workgroups of kernel `fn` the device holds at once with `lds` bytes of
+// dynamic LDS (0 if unknown).
+int resident_grid(const void* fn, int lds);
 // Dynamic LDS bytes for the per-(tile, width) maxima of a row of nt samples
 // with nwt widths, or 0 when they do not fit (the kernel then rescans every
 // tile for candidates).
 int boxcar_tmax_bytes(int nwt, int64_t nt);
+
 hipError_t launch_zero_counts(const BoxcarArgs* d_jobs, const int* d_njobs, int max_jobs, hipStream_t stream);
 
 // Largest dynamic LDS per workgroup the current device allows (capped at kMaxLds).

@@ -284,16 +284,13 @@ __device__ __forceinline__ void cand_tile(const BoxcarArgs& a, BoxShared<NWT>& s
     }
 }
 
+// Widths and 1/sqrt(w) of the row's job into LDS, the wavefronts' per-width
+// best cleared, and the per-(tile, width) maxima table reset.
 template <int NWT>
-__device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
+__device__ __forceinline__ void row_setup(const BoxcarArgs& a, int ntiles, bool keep_tmax, BoxShared<NWT>& sh) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int T = a.nt;
-    const TX_GLOBAL int32_t* __restrict__ y = to_global(a.y) + static_cast<size_t>(row) * a.pitch;
-    const bool vec = ((reinterpret_cast<uintptr_t>(a.y) + static_cast<uintptr_t>(row) * a.pitch * 4) & 15) == 0;
-    const int ntiles = (T + kBoxTile - 1) / kBoxTile;
-    const bool keep_tmax = a.tmax_ok != 0;
     if (tid < NWT) {
         int32_t w = 0;
         double r = 0.0;
@@ -316,11 +313,21 @@ __device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShar
     if (keep_tmax)
         for (int k = tid; k < ntiles * NWT; k += kThreads) tx_box_tmax[k] = INT32_MIN;
     __syncthreads();
+}
 
-    // ---- one pass over the row: running sums, moments, peaks ------------------
+// Tiles [tlo, thi) of a row: running sums, exact moments (wavefront sums left
+// in sh.red*), per-width best of every wavefront (sh.wS / sh.wT) and the
+// per-(tile, width) maxima.
+template <int NWT>
+__device__ __forceinline__ void row_scan(const BoxcarArgs& a, int tlo, int thi, bool keep_tmax,
+                                         const TX_GLOBAL int32_t* __restrict__ y, bool vec, BoxShared<NWT>& sh) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int T = a.nt;
     const int L = kBoxTile + a.wmax;
     Moments m;
-    for (int tile = 0; tile < ntiles; ++tile) {
+    for (int tile = tlo; tile < thi; ++tile) {
         const int t0 = tile * kBoxTile;
         // The thread index, made opaque to the compiler in every tile: else it
         // hoists dozens of lane-dependent masks and addresses out of this loop
@@ -334,19 +341,25 @@ __device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShar
         }
         __syncthreads();
     }
-
-    // ---- statistics ----------------------------------------------------------------
-    {
-        const unsigned long long s1 = wave_sum(m.s1);
-        const unsigned long long s2 = wave_sum(m.s2);
-        const int bad = __any(m.bad != 0) ? 1 : 0;
-        if (lane == 0) {
-            sh.red1[wave] = s1;
-            sh.red2[wave] = s2;
-            sh.redbad[wave] = bad;
-        }
+    const unsigned long long s1 = wave_sum(m.s1);
+    const unsigned long long s2 = wave_sum(m.s2);
+    const int bad = __any(m.bad != 0) ? 1 : 0;
+    if (lane == 0) {
+        sh.red1[wave] = s1;
+        sh.red2[wave] = s2;
+        sh.redbad[wave] = bad;
     }
     __syncthreads();
+}
+
+// Statistics, the row's peak and (when asked) its candidates, from the state
+// row_scan left in LDS.
+template <int NWT>
+__device__ __forceinline__ void row_finish(const BoxcarArgs& a, int row, int ntiles, bool keep_tmax,
+                                           const TX_GLOBAL int32_t* __restrict__ y, bool vec, BoxShared<NWT>& sh) {
+    const int tid = threadIdx.x;
+    const int T = a.nt;
+    const int L = kBoxTile + a.wmax;
     if (tid == 0) {
         unsigned long long S1 = 0, S2 = 0;
         int B = 0;
@@ -457,6 +470,18 @@ __device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShar
     __syncthreads();
 }
 
+
+template <int NWT>
+__device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
+    const TX_GLOBAL int32_t* __restrict__ y = to_global(a.y) + static_cast<size_t>(row) * a.pitch;
+    const bool vec = ((reinterpret_cast<uintptr_t>(a.y) + static_cast<uintptr_t>(row) * a.pitch * 4) & 15) == 0;
+    const int ntiles = (a.nt + kBoxTile - 1) / kBoxTile;
+    const bool keep_tmax = a.tmax_ok != 0;
+    row_setup<NWT>(a, ntiles, keep_tmax, sh);
+    row_scan<NWT>(a, 0, ntiles, keep_tmax, y, vec, sh);
+    row_finish<NWT>(a, row, ntiles, keep_tmax, y, vec, sh);
+}
+
 // Single job: one workgroup per row.
 template <int NWT>
 // At least 5 waves per SIMD (at most 102 VGPRs).  When the kernel needed 113
@@ -477,20 +502,21 @@ __device__ __forceinline__ int find_row_job(const int* __restrict__ prefix, int 
     return lo;
 }
 
-// Batch form: one workgroup per row of all jobs (job of a row by prefix sums);
-// the grid may exceed the batch's rows (a captured graph is sized for the
-// largest batch) and workgroups past the last row exit at once.
+// Batch form: persistent workgroups taking rows of all jobs (job of a row by
+// prefix sums) from the launch's work counters.
 template <int NWT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void boxcar_batch_kernel(const BoxcarArgs* __restrict__ jobs,
-                                                                const int* __restrict__ prefix,
-                                                                const int* __restrict__ njobs_p) {
+                                                                const int* __restrict__ prefix_base,
+                                                                const int* __restrict__ info, uint32_t* queue) {
     __shared__ BoxShared<NWT> sh;
-    const int njobs = *njobs_p;
-    const int total = prefix[njobs];
-    const int v = static_cast<int>(blockIdx.x);
-    if (v >= total) return;
-    const int jb = find_row_job(prefix, njobs, v);
-    boxcar_row<NWT>(jobs[jb], v - prefix[jb], sh);
+    const int njobs = info[0];
+    if (njobs <= 0) return;
+    const BoxcarArgs* cj = jobs + info[1];
+    const int* prefix = prefix_base + info[2];
+    for_each_claimed(prefix[njobs], queue, [&](int v) {
+        const int jb = find_row_job(prefix, njobs, v);
+        boxcar_row<NWT>(cj[jb], v - prefix[jb], sh);
+    });
 }
 
 __global__ void zero_u64_kernel(unsigned long long* p) {
@@ -535,19 +561,25 @@ hipError_t launch_boxcar(const BoxcarArgs& a_in, hipStream_t stream) {
     return e;
 }
 
-hipError_t launch_boxcar_batch(int nwt, int lds, const BoxcarArgs* d_jobs, const int* d_prefix, const int* d_njobs,
-                               int grid, hipStream_t stream) {
-    if (grid <= 0) return hipSuccess;
-    const int prof = prof_begin(TX_KERNEL_BOXCAR, stream);
+hipError_t launch_boxcar_batch(int nwt, int lds, const BatchRefs& r, int64_t rows, hipStream_t stream) {
+    const BoxcarArgs* jobs = static_cast<const BoxcarArgs*>(r.jobs);
+    void* args[] = {&jobs, const_cast<const int**>(&r.prefix), const_cast<const int**>(&r.info),
+                    const_cast<uint32_t**>(&r.queue)};
+    const void* fn;
     switch (boxcar_nwt(nwt)) {
-        case 4: hipLaunchKernelGGL(boxcar_batch_kernel<4>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
-        case 8: hipLaunchKernelGGL(boxcar_batch_kernel<8>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
-        case 10: hipLaunchKernelGGL(boxcar_batch_kernel<10>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
-        case 12: hipLaunchKernelGGL(boxcar_batch_kernel<12>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
-        case 16: hipLaunchKernelGGL(boxcar_batch_kernel<16>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
-        default: hipLaunchKernelGGL(boxcar_batch_kernel<32>, dim3(grid), dim3(kThreads), lds, stream, d_jobs, d_prefix, d_njobs); break;
+        case 4: fn = reinterpret_cast<const void*>(&boxcar_batch_kernel<4>); break;
+        case 8: fn = reinterpret_cast<const void*>(&boxcar_batch_kernel<8>); break;
+        case 10: fn = reinterpret_cast<const void*>(&boxcar_batch_kernel<10>); break;
+        case 12: fn = reinterpret_cast<const void*>(&boxcar_batch_kernel<12>); break;
+        case 16: fn = reinterpret_cast<const void*>(&boxcar_batch_kernel<16>); break;
+        default: fn = reinterpret_cast<const void*>(&boxcar_batch_kernel<32>); break;
     }
-    const hipError_t e = hipGetLastError();
+    int grid = resident_grid(fn, lds);
+    if (grid <= 0) grid = 256 * 5;
+    if (rows > 0 && rows < grid) grid = static_cast<int>(rows);
+    const int prof = prof_begin(TX_KERNEL_BOXCAR, stream);
+    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, static_cast<size_t>(lds), stream);
+    if (e == hipSuccess) e = hipGetLastError();
     prof_end(prof, stream);
     return e;
 }

@@ -89,7 +89,7 @@ __device__ __forceinline__ int block_max(int v, int* red) {
 // contributions and the accumulator meet in one 3-input add.
 // ---------------------------------------------------------------------------
 template <int Q, int JW>
-__device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8_t* lds, int* red) {
+__device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8_t* lds, int* red, int tid) {
     constexpr int J = JW * kWaves;
     constexpr int TT = 256 * Q;
     constexpr uint32_t kOdd = 0x0C030C01u;   // bytes 1 and 3 into 16-bit lanes
@@ -100,7 +100,6 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
     const int j0 = jc * J;
     const int jl = min(j0 + J, a.ngroups) - 1;
     const int u0 = tt * TT;
-    const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = uniform(tid >> 6);
     const int ch0 = s * a.m;
@@ -297,7 +296,7 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
 // while the current one is summed).
 // ---------------------------------------------------------------------------
 template <int IW, int Q>
-__device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8_t* lds, int* red) {
+__device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8_t* lds, int* red, int tid) {
     constexpr int IWP = (IW + 3) & ~3;
     constexpr int TT = 512 * Q;
     const int ic = tile % a.n_ichunks;
@@ -310,7 +309,6 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
     if (ni <= 0) return;
     const int il = i0 + ni - 1;
     const int t0 = tt * TT;
-    const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = uniform(tid >> 6);
     const TX_GLOBAL int32_t* __restrict__ rT = to_global(a.rT);
@@ -505,12 +503,12 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
 }
 
 // ---------------------------------------------------------------------------
-// Kernels: one job (arguments by value), or a batch of jobs whose argument
-// table, tile prefix sums and job count are read from device memory, so that a
-// captured graph can be replayed over another set of jobs.  Both forms run one
-// workgroup per tile; a batch grid may be larger than the batch (a captured
-// graph is sized for the largest batch it will see) and workgroups past the
-// last tile exit at once.
+// Kernels: one job (arguments by value, one workgroup per tile), or a batch
+// of jobs of one tile variant.  A batch launch is persistent: a grid sized to
+// what the device holds at once, each workgroup taking tile after tile from
+// work counters in device memory until they run out.  The job arguments,
+// tile prefix sums, job count and counters are read from the batch's device
+// table, so a captured graph can be replayed over another set of jobs.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int find_job(const int* __restrict__ prefix, int njobs, int t) {
     int lo = 0, hi = njobs;                 // prefix[lo] <= t < prefix[hi]
@@ -521,35 +519,32 @@ __device__ __forceinline__ int find_job(const int* __restrict__ prefix, int njob
     return lo;
 }
 
-// Tile of this workgroup in a batch of `total` tiles, or -1.  Tiles are dealt
-// to the XCDs in contiguous ranges, as in the single-job form.
-__device__ __forceinline__ int batch_tile(int total) {
-    const int total8 = (total + 7) & ~7;
-    const int bid = static_cast<int>(blockIdx.x);
-    if (bid >= total8) return -1;
-    const int t = xcd_tile(bid, total8);
-    return t < total ? t : -1;
-}
-
 template <int Q, int JW>
 __global__ __launch_bounds__(kThreads) void stage1_kernel(Stage1Args a) {
     extern __shared__ __align__(16) uint8_t lds[];
     int* red = reinterpret_cast<int*>(lds);   // block_max scratch, used before anything is staged
-    stage1_tile<Q, JW>(a, xcd_tile(blockIdx.x, a.nsub * a.n_ttiles * a.n_jchunks), lds, red);
+    stage1_tile<Q, JW>(a, xcd_tile(blockIdx.x, a.nsub * a.n_ttiles * a.n_jchunks), lds, red, threadIdx.x);
 }
 
 template <int Q, int JW>
 __global__ __launch_bounds__(kThreads) void stage1_batch_kernel(const Stage1Args* __restrict__ jobs,
-                                                                const int* __restrict__ prefix,
-                                                                const int* __restrict__ njobs_p) {
+                                                                const int* __restrict__ prefix_base,
+                                                                const int* __restrict__ info, uint32_t* queue) {
     extern __shared__ __align__(16) uint8_t lds[];
-    int* red = reinterpret_cast<int*>(lds);   // block_max scratch, used before anything is staged
-    const int njobs = *njobs_p;
-    const int t = batch_tile(prefix[njobs]);
-    if (t < 0) return;
-    const int jb = find_job(prefix, njobs, t);
-    const Stage1Args a = jobs[jb];
-    stage1_tile<Q, JW>(a, t - prefix[jb], lds, red);
+    int* red = reinterpret_cast<int*>(lds);
+    const int njobs = info[0];
+    if (njobs <= 0) return;
+    const Stage1Args* cj = jobs + info[1];
+    const int* prefix = prefix_base + info[2];
+    for_each_claimed(prefix[njobs], queue, [&](int t) {
+        const int jb = find_job(prefix, njobs, t);
+        const Stage1Args a = cj[jb];
+        // The thread index, opaque to the compiler in every tile: else it
+        // keeps lane-dependent values of the tile body live across tiles.
+        int tv = static_cast<int>(threadIdx.x);
+        asm volatile("" : "+v"(tv));
+        stage1_tile<Q, JW>(a, t - prefix[jb], lds, red, tv);
+    });
 }
 
 // The 16-trial, 3-dword variant is held to 4 waves per SIMD (128 VGPRs): left
@@ -561,21 +556,26 @@ template <int IW, int Q>
 __global__ __launch_bounds__(kThreads) TX_S2_WAVES(IW, Q) void stage2_kernel(Stage2Args a) {
     extern __shared__ __align__(16) uint8_t lds[];
     int* red = reinterpret_cast<int*>(lds);   // block_max scratch, used before anything is staged
-    stage2_tile<IW, Q>(a, xcd_tile(blockIdx.x, a.ngroups * a.n_ichunks * a.n_ttiles), lds, red);
+    stage2_tile<IW, Q>(a, xcd_tile(blockIdx.x, a.ngroups * a.n_ichunks * a.n_ttiles), lds, red, threadIdx.x);
 }
 
 template <int IW, int Q>
 __global__ __launch_bounds__(kThreads) TX_S2_WAVES(IW, Q) void stage2_batch_kernel(const Stage2Args* __restrict__ jobs,
-                                                                const int* __restrict__ prefix,
-                                                                const int* __restrict__ njobs_p) {
+                                                                const int* __restrict__ prefix_base,
+                                                                const int* __restrict__ info, uint32_t* queue) {
     extern __shared__ __align__(16) uint8_t lds[];
-    int* red = reinterpret_cast<int*>(lds);   // block_max scratch, used before anything is staged
-    const int njobs = *njobs_p;
-    const int t = batch_tile(prefix[njobs]);
-    if (t < 0) return;
-    const int jb = find_job(prefix, njobs, t);
-    const Stage2Args a = jobs[jb];
-    stage2_tile<IW, Q>(a, t - prefix[jb], lds, red);
+    int* red = reinterpret_cast<int*>(lds);
+    const int njobs = info[0];
+    if (njobs <= 0) return;
+    const Stage2Args* cj = jobs + info[1];
+    const int* prefix = prefix_base + info[2];
+    for_each_claimed(prefix[njobs], queue, [&](int t) {
+        const int jb = find_job(prefix, njobs, t);
+        const Stage2Args a = cj[jb];
+        int tv = static_cast<int>(threadIdx.x);
+        asm volatile("" : "+v"(tv));
+        stage2_tile<IW, Q>(a, t - prefix[jb], lds, red, tv);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -784,30 +784,56 @@ hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const ui
     return e;
 }
 
-// batch_tile deals tiles over round_up(total, 8) workgroup ids, so the grid
-// must cover every id below that: round it up to the 8 XCDs.
-static int batch_grid(int tiles) { return (tiles + 7) / 8 * 8; }
+// Workgroups of a kernel the device holds at once with `lds` bytes of dynamic
+// LDS (0 if unknown), cached per (kernel, LDS size).
+int resident_grid(const void* fn, int lds) {
+    static std::mutex mu;
+    static std::vector<std::pair<std::pair<const void*, int>, int>> done;
+    std::lock_guard<std::mutex> lock(mu);
+    for (auto& d : done)
+        if (d.first.first == fn && d.first.second == lds) return d.second;
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, lds) != hipSuccess || cus <= 0 || per <= 0) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    done.push_back({{fn, lds}, cus * per});
+    return cus * per;
+}
 
-hipError_t launch_stage1_batch(int variant, int lds, const Stage1Args* d_jobs, const int* d_prefix, const int* d_njobs,
-                               int grid, hipStream_t stream) {
+// A persistent batch launch: as many workgroups as the device holds at once,
+// or `tiles` if fewer (0 = a graph that may later see any number of tiles).
+static hipError_t launch_persistent(const void* fn, int lds, void** args, int64_t tiles, hipStream_t stream) {
+    allow_lds(fn, lds);
+    int grid = resident_grid(fn, lds);
+    if (grid <= 0) grid = 256 * 4;
+    if (tiles > 0 && tiles < grid) grid = static_cast<int>(tiles);
+    const hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, static_cast<size_t>(lds), stream);
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_stage1_batch(int variant, int lds, const BatchRefs& r, int64_t tiles, hipStream_t stream) {
     if (variant < 0 || variant >= kNS1) return hipErrorInvalidValue;
-    if (grid <= 0) return hipSuccess;
     const void* fn = kS1Fn[variant].batch;
-    void* a[] = {&d_jobs, &d_prefix, &d_njobs};
+    const Stage1Args* jobs = static_cast<const Stage1Args*>(r.jobs);
+    void* a[] = {&jobs, const_cast<const int**>(&r.prefix), const_cast<const int**>(&r.info),
+                 const_cast<uint32_t**>(&r.queue)};
     const int prof = prof_begin(TX_KERNEL_STAGE1, stream);
-    const hipError_t e = launch(fn, batch_grid(grid), lds, a, stream);
+    const hipError_t e = launch_persistent(fn, lds, a, tiles, stream);
     prof_end(prof, stream);
     return e;
 }
 
-hipError_t launch_stage2_batch(int iw, int variant, int lds, const Stage2Args* d_jobs, const int* d_prefix,
-                               const int* d_njobs, int grid, hipStream_t stream) {
+hipError_t launch_stage2_batch(int iw, int variant, int lds, const BatchRefs& r, int64_t tiles, hipStream_t stream) {
     const KernelPair* k = (variant >= 0 && variant < kNS2) ? s2_pair(iw, variant) : nullptr;
     if (!k) return hipErrorInvalidValue;
-    if (grid <= 0) return hipSuccess;
-    void* a[] = {&d_jobs, &d_prefix, &d_njobs};
+    const Stage2Args* jobs = static_cast<const Stage2Args*>(r.jobs);
+    void* a[] = {&jobs, const_cast<const int**>(&r.prefix), const_cast<const int**>(&r.info),
+                 const_cast<uint32_t**>(&r.queue)};
     const int prof = prof_begin(TX_KERNEL_STAGE2, stream);
-    const hipError_t e = launch(k->batch, batch_grid(grid), lds, a, stream);
+    const hipError_t e = launch_persistent(k->batch, lds, a, tiles, stream);
     prof_end(prof, stream);
     return e;
 }

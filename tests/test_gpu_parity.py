@@ -174,6 +174,40 @@ def test_boxcar_peaks_match_oracle(nt, seed):
     assert np.array_equal(tim, want[2])
 
 
+@pytest.mark.parametrize("nt", [8197, 4 * 4096, 70001])
+def test_boxcar_ties_and_candidates_across_tiles_match_oracle(nt):
+    """Long rows with equal maxima in the first and the last tile (the
+    earliest start must be reported) and candidates in every tile (all must
+    be listed)."""
+    torch = torch_cuda()
+    _say(f"boxcar split nt={nt}")
+    rng = np.random.default_rng(nt)
+    rows = 40
+    Y = rng.integers(0, 50, size=(rows, nt)).astype(np.int32)
+    for r in range(0, rows, 3):                   # equal width-4 sums in the first and last tiles
+        Y[r, 100:104] += 900
+        Y[r, nt - 300:nt - 296] = Y[r, 100:104]
+    for r in range(1, rows, 3):                   # a spike in the last tile only
+        Y[r, nt - 50] += 2500
+    for r in range(2, rows, 6):                   # spikes in every tile
+        Y[r, ::4096] += 700
+    Y[5] = 9                                      # zero variance
+    widths = [1, 2, 4, 8, 16, 32, 64]
+    d = torch.from_numpy(Y).to("cuda")
+    snr, wid, tim = gpu_peaks(d, nt, widths)
+    want = oracle.boxcar_peaks(Y, widths)
+    _assert_snr(snr, want[0])
+    assert np.array_equal(wid, want[1]) and np.array_equal(tim, want[2])
+    n, rec, peaks = gpu_candidates(d, nt, widths, 5.0, with_peaks=True)
+    wc = oracle.boxcar_candidates(Y, widths, 5.0)
+    assert n == len(wc) and len(wc) > 0
+    got = as_tuples(rec)
+    assert [c[:3] for c in got] == [c[:3] for c in wc]
+    _assert_snr([c[3] for c in got], [c[3] for c in wc])
+    _assert_snr(peaks[0], want[0])
+    assert np.array_equal(peaks[1], want[1]) and np.array_equal(peaks[2], want[2])
+
+
 def test_boxcar_out_of_range_rows_are_flagged():
     torch = torch_cuda()
     Y = np.random.default_rng(3).integers(0, 100, size=(3, 500)).astype(np.int32)

@@ -129,6 +129,8 @@ def test_batch_of_uneven_beams_matches_oracle(graph):
     for b in beams:
         batch.add(b["plan"], b["d_in"], b["nt"], b["y"], widths=widths, gamma=gamma, peaks=b["peaks"],
                   cands=b["cands"], count=b["count"])
+    assert batch.done()                            # nothing launched yet
+    batch.wait()
     with torch.cuda.stream(s):
         for rep in range(3):
             _say(f"batch launch graph={graph} rep={rep}")
@@ -136,7 +138,8 @@ def test_batch_of_uneven_beams_matches_oracle(graph):
                 b["y"].fill_(-5)
                 b["count"].fill_(-1)
             batch.launch(s)
-            s.synchronize()
+            batch.wait()                           # the batch's own completion, not the stream's
+            assert batch.done()
             for b in beams:
                 _check_beam(b, widths, gamma)
             # new data for the next replay, written by eager work on the same stream
