@@ -13,14 +13,16 @@ between blocks.  Blocks arrive at host-clock times.  The loop:
 * copies host blocks to device staging slots on a copy stream, so uploads
   overlap the kernels of lanes already queued;
 * runs each lane as one ``tx.Batch`` launch (persistent kernels over a device
-  job table, replayed as a HIP graph) on the compute stream, then copies the
-  lane's peaks and candidate lists back in one transfer;
+  job table, replayed as a HIP graph) on the lane's own compute stream, then
+  copies the lane's peaks and candidate lists back in one transfer;
 * harvests lanes in completion order; a block's latency runs from its arrival
   to the moment its candidates are host-visible.
 
-Lanes are queued back to back on one compute stream, so a block that arrives
-while other lanes run is admitted into the next free lane and its work
-follows theirs on the device without waiting for a fixed batch boundary.
+Every lane has its own compute stream, so the work of lanes admitted while
+others run overlaps on the device.  One beam's blocks must still update its
+overlap history in order: a lane whose beam's previous block is in another
+lane still in flight waits for that lane's kernels (a per-beam event) before
+its own start, and only then.
 """
 
 import collections
@@ -70,7 +72,8 @@ class ServeStats:
     mean_batch: float
     dm_samples: int
     wall_s: float
-    gpu_s: float
+    gpu_s: float            # time with at least one lane's work on the device
+    lane_s: float           # summed time of the lanes' work (exceeds gpu_s when lanes overlap)
     p50_s: float
     p99_s: float
     max_s: float
@@ -101,11 +104,12 @@ class Server:
     source:    "host" (blocks arrive in host memory and are uploaded on a copy
                stream) or "device" (blocks are already in device memory).
     keep:      which per-block results to keep: any of "peaks", "cands",
-               "dmt" (the last copies the DM x time array back: tests only).
+               "dmt" (the last copies the DM x time array back: tests only;
+               ``dmt_rows`` limits it to those trial rows).
     """
 
     def __init__(self, plans, block_nt, widths, *, gamma=6.0, cap=4096, lanes=2, max_slots=32, mem_budget=None,
-                 mem_reserve=4 << 30, graph=True, source="host", keep=("peaks", "cands")):
+                 mem_reserve=4 << 30, graph=True, source="host", keep=("peaks", "cands"), dmt_rows=None):
         torch = _torch()
         if source not in ("host", "device"):
             raise ValueError("source must be 'host' or 'device'")
@@ -118,6 +122,7 @@ class Server:
         self.cap = int(cap)
         self.source = source
         self.keep = set(keep)
+        self.dmt_rows = None if dmt_rows is None else [int(r) for r in dmt_rows]
         self.graph = bool(graph)
         dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
@@ -147,11 +152,12 @@ class Server:
             raise MemoryError(f"device memory admits no block: {per_slot} bytes per slot, budget {mem_budget}")
         self.slots = slots
         self.per_slot_bytes = per_slot
-        self.compute = torch.cuda.Stream(device=dev)
         self.copy = torch.cuda.Stream(device=dev) if source == "host" else None
         self.lanes = []
+        self.beam_event = {}     # beam -> event after the kernels of its latest launched block
         for _ in range(int(lanes)):
             ln = _Lane()
+            ln.stream = torch.cuda.Stream(device=dev)
             ln.batch = tx.Batch(slots, graph=self.graph)
             for p in uniq:
                 ln.batch.reserve(p, len(self.widths), self.block_nt, slots)
@@ -182,6 +188,7 @@ class Server:
         torch = self.torch
         ln.jobs = jobs
         blocks = []
+        st = ln.stream
         if self.source == "host":
             with torch.cuda.stream(self.copy):
                 for s, (_, beam, k) in enumerate(jobs):
@@ -191,22 +198,34 @@ class Server:
                     dst.copy_(src, non_blocking=True)
                     blocks.append(dst)
                 ln.uploaded.record(self.copy)
-            self.compute.wait_event(ln.uploaded)
+            st.wait_event(ln.uploaded)
         else:
             blocks = [data_fn(beam, k) for (_, beam, k) in jobs]
+        # One beam's blocks in order: wait for the kernels of each beam's
+        # previous block where it ran on another lane's stream.
+        waited = set()
+        for (_, beam, _) in jobs:
+            ev = self.beam_event.get(beam)
+            if ev is not None and ev[0] is not ln and id(ev[1]) not in waited:
+                st.wait_event(ev[1])
+                waited.add(id(ev[1]))
         ln.batch.clear()
         for s, (_, beam, k) in enumerate(jobs):
             plan = self.plans[beam]
             peaks, cands, cnt = self._views(ln, s, plan.ndm)
             ln.batch.add_stream(self.streams[beam], blocks[s], self.block_nt, ln.out[s, :plan.ndm],
                                 widths=self.widths, gamma=self.gamma, peaks=peaks, cands=cands, count=cnt)
-        ln.start.record(self.compute)
-        ln.batch.launch(self.compute)
+        ln.start.record(st)
+        ln.batch.launch(st)
+        kern = torch.cuda.Event()
+        kern.record(st)
+        for (_, beam, _) in jobs:
+            self.beam_event[beam] = (ln, kern)
         ln.n_out = [ln.batch.stream_output(s) for s in range(len(jobs))]
         used = len(jobs) * self.slot_bytes
-        with torch.cuda.stream(self.compute):
+        with torch.cuda.stream(st):
             ln.host[:used].copy_(ln.res[:used], non_blocking=True)
-        ln.done.record(self.compute)
+        ln.done.record(st)
 
     def _harvest(self, ln, now):
         out = []
@@ -227,9 +246,11 @@ class Server:
                     r.cands = tx.parse_candidates(raw[base + self._o_cands: base + self._o_cands + 24 * self.cap],
                                                   r.count)
                 if "dmt" in self.keep:
-                    r.dmt = ln.out[s, :ndm, :n_out].cpu().numpy()
+                    rows = slice(0, ndm) if self.dmt_rows is None else self.dmt_rows
+                    r.dmt = ln.out[s, rows, :n_out].cpu().numpy()
             out.append(r)
         ln.gpu_s = ln.start.elapsed_time(ln.done) * 1e-3
+        ln.span = (self._t_ref.elapsed_time(ln.start) * 1e-3, self._t_ref.elapsed_time(ln.done) * 1e-3)
         ln.jobs = []
         return out
 
@@ -256,18 +277,23 @@ class Server:
         batches = 0
         gpu_s = 0.0
         torch = self.torch
+        spans = []
         torch.cuda.synchronize()
+        self._t_ref = torch.cuda.Event(enable_timing=True)
+        self._t_ref.record(self.lanes[0].stream)
+        self.beam_event = {}
         t0 = time.perf_counter()
         while len(results) < total:
             now = time.perf_counter() - t0
             while nxt < total and order[nxt][0] <= now:
                 ready.append(order[nxt])
                 nxt += 1
-            while inflight and inflight[0].done.query():
-                ln = inflight.popleft()
+            for ln in [x for x in inflight if x.done.query()]:
+                inflight.remove(ln)
                 done_t = time.perf_counter() - t0
                 got = self._harvest(ln, done_t)
                 gpu_s += ln.gpu_s
+                spans.append(ln.span)
                 results.extend(got)
                 if on_result is not None:
                     for r in got:
@@ -294,11 +320,21 @@ class Server:
             else:
                 time.sleep(poll_s)
         torch.cuda.synchronize()
+        busy = 0.0                                  # time with at least one lane on the device
+        end = -np.inf
+        for a, b in sorted(spans):
+            if a > end:
+                busy += b - a
+                end = b
+            elif b > end:
+                busy += b - end
+                end = b
         lat = np.array([r.latency for r in results])
         first = order[0][0] if order else 0.0
         last = max((r.done for r in results), default=first)
         stats = ServeStats(blocks=total, batches=batches, mean_batch=total / max(batches, 1),
-                           dm_samples=int(sum(r.ndm * r.n_out for r in results)), wall_s=last - first, gpu_s=gpu_s,
+                           dm_samples=int(sum(r.ndm * r.n_out for r in results)), wall_s=last - first, gpu_s=busy,
+                           lane_s=gpu_s,
                            p50_s=float(np.percentile(lat, 50)) if total else 0.0,
                            p99_s=float(np.percentile(lat, 99)) if total else 0.0,
                            max_s=float(lat.max()) if total else 0.0, slots=self.slots, lanes=len(self.lanes))

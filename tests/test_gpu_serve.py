@@ -138,3 +138,76 @@ def test_served_blocks_same_alone_and_in_mix(beams, graph, source, lanes, slots,
         ws, ww, wt = oracle.boxcar_peaks(blk, WIDTHS)
         assert np.array_equal(last.snr, ws) and np.array_equal(last.width, ww) and np.array_equal(last.time, wt)
         assert as_tuples(last.cands) == oracle.boxcar_candidates(blk, WIDTHS, GAMMA)
+
+
+OCT_BLOCKS = 7          # 343278 samples of history prime the first 5.2 blocks
+
+
+@pytest.mark.slow
+def test_octave_beams_served_alone_and_oracle():
+    """Two multi-octave beams (8192 channels over 544-1088 MHz, 8192 trials
+    to DM 5000, 65536-sample blocks, widths to 1024) served at Poisson
+    arrivals on two lanes: every block's sampled rows, peaks and candidates
+    equal the beam pushed alone through its own stream, and the sampled rows
+    of the concatenated output equal the oracle (the C oracle on the coarse
+    groups that hold them)."""
+    from oracle import c_oracle as co
+    torch = torch_cuda()
+    wl = synth.workload("octave-8192")
+    plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    nchan, nt, g = plan.nchan, wl.nt, plan.g
+    groups = [0, 4095 // g, plan.ngroups - 2]                     # low DM, near DM 2500, high DM
+    rows = sorted(j * g + i for j in groups for i in (0, g // 2, g - 1))
+    beams = []
+    for k in range(2):
+        d = synth.device_normal_u8(torch, nchan, nt * OCT_BLOCKS, 900 + k)
+        beams.append([d[:, j * nt:(j + 1) * nt] for j in range(OCT_BLOCKS)])
+    srv = serve.Server([plan, plan], nt, wl.widths, gamma=wl.gamma, cap=1 << 16, lanes=2, max_slots=2, graph=True,
+                       source="device", keep=("peaks", "cands", "dmt"), dmt_rows=rows)
+    arrivals = synth.poisson_arrivals(2, OCT_BLOCKS, 0.05, 2.0, 57)
+    _say(f"octave serve: slots {srv.slots}, rows {rows}")
+    results, stats = srv.run(arrivals, lambda b, j: beams[b][j])
+    srv.close()
+    assert stats.blocks == 2 * OCT_BLOCKS
+    by_beam = {}
+    for r in results:
+        by_beam.setdefault(r.beam, []).append(r)
+    for b in range(2):
+        rs = by_beam[b]
+        st = tx.Stream(plan, nt)
+        outs = []
+        for j, r in enumerate(rs):
+            d = torch.empty((plan.ndm, nt), dtype=torch.int32, device="cuda")
+            n = st.push(beams[b][j], nt, d)
+            assert r.n_out == n
+            if n == 0:
+                continue
+            peaks = (torch.empty(plan.ndm, dtype=torch.float64, device="cuda"),
+                     torch.empty(plan.ndm, dtype=torch.int32, device="cuda"),
+                     torch.empty(plan.ndm, dtype=torch.int64, device="cuda"))
+            raw = torch.zeros((1 << 16, 3), dtype=torch.int64, device="cuda")
+            cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+            tx.tx_candidates(d[:, :n], n, wl.widths, wl.gamma, raw, cnt, peaks=peaks)
+            torch.cuda.synchronize()
+            assert np.array_equal(r.dmt, d[rows, :n].cpu().numpy())
+            assert np.array_equal(r.snr, peaks[0].cpu().numpy()) and np.array_equal(r.width, peaks[1].cpu().numpy())
+            assert np.array_equal(r.time, peaks[2].cpu().numpy())
+            c = int(cnt.item())
+            assert r.count == c
+            assert as_tuples(r.cands) == as_tuples(tx.parse_candidates(raw.cpu().numpy(), c))
+            outs.append(r.dmt)
+            del d, raw
+        st.close()
+        y = np.concatenate(outs, axis=1)
+        total = nt * OCT_BLOCKS - plan.overlap
+        assert y.shape[1] == total
+        _say(f"octave beam {b}: C oracle on groups {groups}")
+        x = torch.cat(beams[b], dim=1).cpu().numpy()
+        for jg in groups:
+            want = co.dedisperse_subband(x, wl.freqs, wl.tsamp, wl.dms[jg * g:(jg + 1) * g], wl.nsub, g, total)
+            for i in range(g):
+                row = jg * g + i
+                if row in rows:
+                    assert np.array_equal(y[rows.index(row)], want[i]), row
+        del x
+    torch.cuda.empty_cache()
