@@ -267,68 +267,166 @@ def cluster_leg(torch, tx, synth, sizes=(1000, 10000, 100000, 1000000), radii=(4
             "runs": rows}
 
 
-def batched_leg(torch, tx, synth, steps):
-    """64 beams of uneven shape (channels 1024-4096, blocks 16384-65536, 512-4096
-    DM trials up to DM 3000, sub-band count chosen by each plan) dedispersed
-    with peaks and candidates in one batch launch replayed as a HIP graph;
-    against the same jobs run one beam per launch."""
-    beams = synth.batched_beams()
-    jobs = []
-    for wl in beams:
-        plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, 0)
-        nchan, ndm, nt = len(wl.freqs), plan.ndm, wl.nt
-        pitch = (nt + plan.overlap + 255) // 256 * 256
-        d_in = synth.device_normal_u8(torch, nchan, pitch, wl.seed, pulses=place_pulses(plan, wl, synth))
-        y = torch.empty((ndm, nt), dtype=torch.int32, device="cuda")
-        peaks = (torch.empty(ndm, dtype=torch.float64, device="cuda"),
-                 torch.empty(ndm, dtype=torch.int32, device="cuda"),
-                 torch.empty(ndm, dtype=torch.int64, device="cuda"))
-        cands = torch.empty((1 << 16, 3), dtype=torch.int64, device="cuda")
-        count = torch.zeros(1, dtype=torch.int64, device="cuda")
-        jobs.append(dict(wl=wl, plan=plan, d_in=d_in, y=y, peaks=peaks, cands=cands, count=count))
-    dm_samples = sum(j["plan"].ndm * j["wl"].nt for j in jobs)
-    stream = torch.cuda.Stream()
-    batch = tx.Batch(len(jobs), graph=True)
-    for j in jobs:
-        batch.add(j["plan"], j["d_in"], j["wl"].nt, j["y"], widths=j["wl"].widths, gamma=j["wl"].gamma,
-                  peaks=j["peaks"], cands=j["cands"], count=j["count"])
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        batch.launch(stream)                       # captures the graph
-        stream.synchronize()
-        ev0.record(stream)
-        for _ in range(steps):
-            batch.launch(stream)
-        ev1.record(stream)
-        stream.synchronize()
-        t_batch = ev0.elapsed_time(ev1) * 1e-3 / steps
-        ncand = sum(int(j["count"].item()) for j in jobs)
+def plan_adds(plan, nt):
+    """Additions of one block: N_c * N_f * T (first stage) + N_DM * nsub * T (second)."""
+    return plan.ngroups * plan.nchan * nt + plan.ndm * plan.nsub * nt
 
-        def plain_round():
+
+def plan_alg_bytes(plan, nt):
+    """Algorithmic HBM bytes of one block through dedispersion and the boxcar:
+    the input read once (N_f (T + O) bytes), the DM x time array written once
+    and read once by the boxcar (2 * 4 N_DM T)."""
+    return plan.nchan * (nt + plan.overlap) + 8 * plan.ndm * nt
+
+
+def tuned_classes(tx, tune, beams, effort, path):
+    """Per (channels, DM range) class of the uneven batch: the sub-band count
+    and tiles tune.plan_autotuned picks on the class's largest DM grid at
+    16384 samples; every beam of the class then uses them."""
+    classes = {}
+    for wl in beams:
+        key = (len(wl.freqs), float(wl.dms[-1]))
+        if key not in classes or len(wl.dms) > len(classes[key].dms):
+            classes[key] = wl
+    out = {}
+    for key, wl in sorted(classes.items()):
+        plan, times = tune.plan_autotuned(wl.freqs, wl.tsamp, wl.dms, 16384, effort=effort, path=path)
+        out[key] = (plan.nsub, plan.get_tiles(), times)
+    return out
+
+
+def batched_leg(torch, tx, synth, steps, tune_effort=0):
+    """64 beams of uneven shape (channels 1024-4096, blocks 16384-65536, 512-4096
+    DM trials up to DM 3000) dedispersed with peaks and candidates in one batch
+    launch (persistent kernels) replayed as a HIP graph; against the same jobs
+    run one beam per launch, whose outputs the batch's must equal.  Run twice:
+    with each plan's own sub-band count and default tiles, and with the
+    sub-band count and tiles autotuned per (channels, DM range) class."""
+    import tempfile
+    from paper_2401_13834_amd import tune
+    beams = synth.batched_beams()
+    inputs = []
+    for wl in beams:
+        plan0 = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, 0)
+        nchan, nt = len(wl.freqs), wl.nt
+        pitch = (nt + plan0.overlap + 255) // 256 * 256
+        # the largest overlap over the sub-band counts tried is below DM_max's brute-force reach + 16
+        pitch = max(pitch, (nt + plan0.brute_reach + 512 + 255) // 256 * 256)
+        d_in = synth.device_normal_u8(torch, nchan, pitch, wl.seed, pulses=place_pulses(plan0, wl, synth))
+        inputs.append(d_in)
+    stream = torch.cuda.Stream()
+    t_tune = time.perf_counter()
+    with tempfile.TemporaryDirectory() as tmp:
+        with torch.cuda.stream(stream):
+            classes = tuned_classes(tx, tune, beams, tune_effort, os.path.join(tmp, "tiles.json"))
+    t_tune = time.perf_counter() - t_tune
+
+    def run(tuned):
+        jobs = []
+        for wl, d_in in zip(beams, inputs):
+            if tuned:
+                nsub, tiles, _ = classes[(len(wl.freqs), float(wl.dms[-1]))]
+                plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, nsub)
+                plan.set_tiles(*tiles)
+            else:
+                plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, 0)
+            ndm, nt = plan.ndm, wl.nt
+            assert d_in.shape[1] >= nt + plan.overlap
+            mk = lambda: dict(y=torch.empty((ndm, nt), dtype=torch.int32, device="cuda"),
+                              peaks=(torch.empty(ndm, dtype=torch.float64, device="cuda"),
+                                     torch.empty(ndm, dtype=torch.int32, device="cuda"),
+                                     torch.empty(ndm, dtype=torch.int64, device="cuda")),
+                              cands=torch.empty((1 << 16, 3), dtype=torch.int64, device="cuda"),
+                              count=torch.zeros(1, dtype=torch.int64, device="cuda"))
+            jobs.append(dict(wl=wl, plan=plan, d_in=d_in, b=mk(), p=mk()))
+        batch = tx.Batch(len(jobs), graph=True)
+        for j in jobs:
+            o = j["b"]
+            batch.add(j["plan"], j["d_in"], j["wl"].nt, o["y"], widths=j["wl"].widths, gamma=j["wl"].gamma,
+                      peaks=o["peaks"], cands=o["cands"], count=o["count"])
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            batch.launch(stream)                   # captures the graph
+            batch.wait()
+            ev0.record(stream)
+            for _ in range(steps):
+                batch.launch(stream)
+            ev1.record(stream)
+            batch.wait()
+            t_batch = ev0.elapsed_time(ev1) * 1e-3 / steps
+
+            def plain_round():
+                for j in jobs:
+                    o = j["p"]
+                    tx.tx_dedisperse(j["plan"], j["d_in"], j["wl"].nt, o["y"], stream=stream)
+                    tx.tx_candidates(o["y"], j["wl"].nt, j["wl"].widths, j["wl"].gamma, o["cands"], o["count"],
+                                     peaks=o["peaks"], stream=stream)
+            plain_round()
+            stream.synchronize()
+            ev0.record(stream)
+            plain_round()
+            ev1.record(stream)
+            stream.synchronize()
+            t_plain = ev0.elapsed_time(ev1) * 1e-3
+            # per-kernel times of one direct (not captured) launch of the same batch
+            direct = tx.Batch(len(jobs), graph=False)
             for j in jobs:
-                tx.tx_dedisperse(j["plan"], j["d_in"], j["wl"].nt, j["y"], stream=stream)
-                tx.tx_candidates(j["y"], j["wl"].nt, j["wl"].widths, j["wl"].gamma, j["cands"], j["count"],
-                                 peaks=j["peaks"], stream=stream)
-        plain_round()
-        stream.synchronize()
-        ev0.record(stream)
-        plain_round()
-        ev1.record(stream)
-        stream.synchronize()
-        t_plain = ev0.elapsed_time(ev1) * 1e-3
-    nsubs = {}
-    for j in jobs:
-        nsubs[str(j["plan"].nsub)] = nsubs.get(str(j["plan"].nsub), 0) + 1
-    batch.close()
-    del jobs
-    torch.cuda.synchronize()
+                o = j["b"]
+                direct.add(j["plan"], j["d_in"], j["wl"].nt, o["y"], widths=j["wl"].widths, gamma=j["wl"].gamma,
+                           peaks=o["peaks"], cands=o["cands"], count=o["count"])
+            direct.launch(stream)
+            direct.wait()
+            for k in (tx.TX_KERNEL_STAGE1, tx.TX_KERNEL_STAGE2, tx.TX_KERNEL_BOXCAR):
+                tx.tx_profile_collect(k)
+            tx.tx_profile_enable(True)
+            direct.launch(stream)
+            direct.wait()
+            tx.tx_profile_enable(False)
+            kern = {}
+            for name, k in (("stage1", tx.TX_KERNEL_STAGE1), ("stage2", tx.TX_KERNEL_STAGE2),
+                            ("boxcar", tx.TX_KERNEL_BOXCAR)):
+                ms, n = tx.tx_profile_collect(k)
+                kern[name] = {"ms": ms, "launches": n}
+            direct.close()
+        same = all(torch.equal(j["b"]["y"], j["p"]["y"]) and
+                   all(torch.equal(a, b) for a, b in zip(j["b"]["peaks"], j["p"]["peaks"])) and
+                   int(j["b"]["count"].item()) == int(j["p"]["count"].item()) for j in jobs)
+        dm_samples = sum(j["plan"].ndm * j["wl"].nt for j in jobs)
+        adds = sum(plan_adds(j["plan"], j["wl"].nt) for j in jobs)
+        alg = sum(plan_alg_bytes(j["plan"], j["wl"].nt) for j in jobs)
+        ncand = sum(int(j["b"]["count"].item()) for j in jobs)
+        nsubs = {}
+        for j in jobs:
+            nsubs[str(j["plan"].nsub)] = nsubs.get(str(j["plan"].nsub), 0) + 1
+        batch.close()
+        del jobs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        tx.tx_pool_trim()
+        return {"value": dm_samples / t_batch, "ms_per_launch": t_batch * 1e3, "launches": steps,
+                "plain_value": dm_samples / t_plain, "plain_ms": t_plain * 1e3,
+                "speedup_vs_plain": t_plain / t_batch, "same_as_plain": bool(same),
+                "dm_samples_per_launch": dm_samples, "nsub_chosen": nsubs, "candidates": ncand,
+                "kernels_ms_direct_launch": kern,
+                "roofline": {"bound": "alu", "achieved": round(adds / t_batch / 1e12, 3),
+                             "peak": round(PEAK_ADD16 / 1e12, 3), "unit": "Tadd/s",
+                             "frac": round(adds / t_batch / PEAK_ADD16, 4), "adds_per_launch": adds,
+                             "alg_hbm_bytes_per_launch": alg, "alg_hbm_GBps": round(alg / t_batch / 1e9, 1),
+                             "alg_hbm_frac": round(alg / t_batch / 8e12, 4)}}
+
+    plain_plans = run(False)
+    print(f"batched (plan defaults): {json.dumps(plain_plans)}", file=sys.stderr, flush=True)
+    tuned = run(True)
+    print(f"batched (autotuned): {json.dumps(tuned)}", file=sys.stderr, flush=True)
+    del inputs
     torch.cuda.empty_cache()
-    tx.tx_pool_trim()
-    return {"workload": "batched-64", "beams": len(beams), "value": dm_samples / t_batch,
-            "unit": "DM-trial samples/s", "ms_per_launch": t_batch * 1e3, "launches": steps, "graph": True,
-            "plain_value": dm_samples / t_plain, "plain_ms": t_plain * 1e3,
-            "speedup_vs_plain": t_plain / t_batch, "dm_samples_per_launch": dm_samples, "nsub_chosen": nsubs,
-            "candidates": ncand}
+    out = {"workload": "batched-64", "beams": len(beams), "graph": True, "persistent": True}
+    out.update(plain_plans)
+    out["autotuned"] = dict(tuned, classes={f"{k[0]}ch-dm{int(k[1])}": {"nsub": v[0], "tiles": list(v[1]),
+                                                                         "ms_by_nsub": v[2]}
+                                            for k, v in classes.items()},
+                            tune_seconds=round(t_tune, 1), gain_vs_plan_defaults=tuned["value"] / plain_plans["value"])
+    return out
 
 
 def served_leg(torch, tx, synth, serve, runs_spec, lanes, max_slots):
@@ -368,6 +466,7 @@ def served_leg(torch, tx, synth, serve, runs_spec, lanes, max_slots):
                          "mean_batch": round(stats.mean_batch, 2), "p50_ms": stats.p50_s * 1e3,
                          "p99_ms": stats.p99_s * 1e3, "max_ms": stats.max_s * 1e3, "value": stats.throughput,
                          "gpu_busy": stats.gpu_s / stats.wall_s if stats.wall_s > 0 else None,
+                         "lane_overlap": stats.lane_s / stats.gpu_s if stats.gpu_s > 0 else None,
                          "p99_below_block": stats.p99_s < t_blk})
             print(f"served: {json.dumps(runs[-1])}", file=sys.stderr, flush=True)
         srv.close()
@@ -382,6 +481,128 @@ def served_leg(torch, tx, synth, serve, runs_spec, lanes, max_slots):
             "block_duration_ms": t_blk * 1e3, "unit": "DM-trial samples/s", "runs": runs,
             "max_host_speed_p99_below_block": max(ok) if ok else None,
             "value": max(dev) if dev else None, "value_host_pcie_inclusive": max(host) if host else None}
+
+
+def octave_served_leg(torch, tx, synth, serve, runs_spec, lanes, max_slots, nbeams=32):
+    """The multi-octave workload served and batched: 32 beams of 8192-channel
+    blocks over 544-1088 MHz (65536 samples, 10.03 s each, 8192 trials to
+    DM 5000, widths to 1024) at Poisson arrivals, each beam's 343278-sample
+    overlap history resident on the device (3.35 GB per beam), admission
+    bounded by the device memory left; blocks already in device memory.  The
+    first 5.2 blocks of a beam only fill its history."""
+    wl = synth.workload("octave-8192")
+    plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    nchan, nt = plan.nchan, wl.nt
+    t_blk = nt * wl.tsamp
+    pool = [synth.device_normal_u8(torch, nchan, nt, 5000 + i) for i in range(4)]
+    srv = serve.Server([plan] * nbeams, nt, wl.widths, gamma=wl.gamma, cap=4096, lanes=lanes, max_slots=max_slots,
+                       graph=True, source="device", keep=())
+    runs = []
+    for speed, nblocks in runs_spec:
+        for st in srv.streams:
+            st.reset()
+        arr = synth.poisson_arrivals(nbeams, nblocks, t_blk, speed, 50 + speed)
+        _, stats = srv.run(arr, lambda b, k: pool[(b * 5 + k) % len(pool)])
+        emitted = stats.dm_samples
+        runs.append({"speed": speed, "blocks": stats.blocks, "batches": stats.batches,
+                     "mean_batch": round(stats.mean_batch, 2), "p50_ms": stats.p50_s * 1e3,
+                     "p99_ms": stats.p99_s * 1e3, "max_ms": stats.max_s * 1e3, "value": stats.throughput,
+                     "dm_samples": emitted, "gpu_busy": stats.gpu_s / stats.wall_s if stats.wall_s > 0 else None,
+                     "lane_overlap": stats.lane_s / stats.gpu_s if stats.gpu_s > 0 else None,
+                     "p99_below_block": stats.p99_s < t_blk})
+        print(f"octave served: {json.dumps(runs[-1])}", file=sys.stderr, flush=True)
+    slots = srv.slots
+    srv.close()
+    del pool, srv
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    tx.tx_pool_trim()
+    return {"workload": "octave-8192 served", "beams": nbeams, "lanes": lanes, "slots": slots,
+            "block_duration_ms": t_blk * 1e3, "unit": "DM-trial samples/s", "source": "device", "runs": runs,
+            "value": max(r["value"] for r in runs) if runs else None,
+            "p99_below_block_all": all(r["p99_below_block"] for r in runs)}
+
+
+def latency_leg(torch, tx, synth, reps=200):
+    """The single-beam configuration at its small size (plain-256: 256
+    channels, 128 trials, 8192 samples of 306.24 us): one block's latency
+    from launch to peaks and candidate count in host memory, through
+    tx_dedisperse and tx_candidates on a resident block (launch-bound at this
+    size)."""
+    wl = synth.workload("plain-256")
+    plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    nt = wl.nt
+    pitch = (nt + plan.overlap + 255) // 256 * 256
+    d_in = synth.device_normal_u8(torch, plan.nchan, pitch, wl.seed, pulses=place_pulses(plan, wl, synth))
+    y = torch.empty((plan.ndm, nt), dtype=torch.int32, device="cuda")
+    cands = torch.empty((1 << 14, 3), dtype=torch.int64, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    peaks = (torch.empty(plan.ndm, dtype=torch.float64, device="cuda"),
+             torch.empty(plan.ndm, dtype=torch.int32, device="cuda"),
+             torch.empty(plan.ndm, dtype=torch.int64, device="cuda"))
+    host_snr = torch.empty(plan.ndm, dtype=torch.float64, pin_memory=True)
+    host_cnt = torch.empty(1, dtype=torch.int64, pin_memory=True)
+    stream = torch.cuda.current_stream()
+    lat = []
+    for k in range(reps + 10):
+        t = time.perf_counter()
+        tx.tx_dedisperse(plan, d_in, nt, y, stream=stream)
+        tx.tx_candidates(y, nt, wl.widths, wl.gamma, cands, count, peaks=peaks, stream=stream)
+        host_snr.copy_(peaks[0], non_blocking=True)
+        host_cnt.copy_(count, non_blocking=True)
+        stream.synchronize()
+        if k >= 10:
+            lat.append(time.perf_counter() - t)
+    lat = np.array(lat) * 1e3
+    best = int(np.argmax(host_snr.numpy()))
+    return {"workload": "plain-256", "reps": reps, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "min_ms": float(lat.min()),
+            "block_duration_ms": nt * wl.tsamp * 1e3, "dm_trial_samples_per_s": plan.ndm * nt / (np.median(lat) * 1e-3),
+            "peak_dm_index": best, "peak_snr": float(host_snr[best]), "candidates": int(host_cnt.item())}
+
+
+def cpu_baseline_extra(seconds):
+    """The C oracle (as it is) at 1 thread and at every host thread, on
+    bounded samples of the single-beam, paper-scale, served and multi-octave
+    blocks (the first coarse groups of each DM grid, all of plain-256's;
+    seeded uniform bytes, since the time of integer sums does not depend on
+    the values): DM-trial samples/s of dedispersion + peaks + candidates.
+    Context for the paper's one-core figure."""
+    import oracle
+    import synth
+    from oracle import c_oracle as co
+    nproc = co.max_threads()
+    out = []
+    for name, groups in (("plain-256", None), ("paper-4096", 1), ("served-4096", 2), ("octave-8192", 1)):
+        wl = synth.workload(name)
+        ref_g = oracle.group_size_rule(wl.freqs, wl.nsub, len(wl.dms))
+        ntr = len(wl.dms) if groups is None else groups * ref_g
+        dms = wl.dms[:ntr]
+        ref = oracle.make_plan(wl.freqs, wl.tsamp, dms, wl.nsub, g=ref_g)
+        nt = wl.nt
+        x = synth.uniform_u8(len(wl.freqs), nt + ref.overlap, wl.seed)
+        for threads in (1, nproc):
+            t = time.perf_counter()
+            reps = 0
+            while True:
+                y = co.dedisperse_subband(x, wl.freqs, wl.tsamp, dms, wl.nsub, ref_g, nt, threads=threads)
+                co.boxcar_peaks(y, wl.widths, threads=threads)
+                co.boxcar_candidates(y, wl.widths, wl.gamma, threads=threads)
+                reps += 1
+                dt = time.perf_counter() - t
+                if dt > seconds / 8 or reps >= 50:
+                    break
+            out.append({"workload": name, "threads": threads, "trials": ntr, "of_trials": len(wl.dms),
+                        "samples": nt, "reps": reps, "seconds": round(dt, 2),
+                        "value": reps * ntr * nt / dt, "unit": "DM-trial samples/s"})
+            print(f"cpu: {json.dumps(out[-1])}", file=sys.stderr, flush=True)
+        del x
+    return {"kind": "oracle", "runs": out, "host_threads": nproc}
+
+
+def serve_mod():
+    from paper_2401_13834_amd import serve
+    return serve
 
 
 def main():
@@ -403,6 +624,12 @@ def main():
     ap.add_argument("--no-ranges", action="store_true", help="skip the multi-range (downsampled) plan leg")
     ap.add_argument("--no-cluster", action="store_true", help="skip the DM-time clustering leg")
     ap.add_argument("--no-stats", action="store_true", help="skip the channel statistics leg")
+    ap.add_argument("--no-octave", action="store_true", help="skip the served multi-octave leg")
+    ap.add_argument("--octave-runs", default="8:9,24:9",
+                    help="speed:blocks-per-beam of the served multi-octave runs")
+    ap.add_argument("--no-latency", action="store_true", help="skip the plain-256 latency leg")
+    ap.add_argument("--no-cpu-extra", action="store_true",
+                    help="skip the CPU oracle at 1 thread and on the other workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy the DM x time array once (a plain copy of known size "
                          "whose HBM counters scale the kernels' counters)")
@@ -534,15 +761,28 @@ def main():
         out["batched"] = batched_leg(torch, tx, synth, args.batched_steps)
         print(f"batched: {json.dumps(out['batched'])}", file=sys.stderr, flush=True)
     if not args.no_served:
-        from paper_2401_13834_amd import serve
+        serve = serve_mod()
         spec = []
         for item in args.served_runs.split(","):
             if item:
                 src, sp, nb = item.split(":")
                 spec.append((src, int(sp), int(nb)))
         out["served"] = served_leg(torch, tx, synth, serve, spec, args.served_lanes, args.served_slots)
+    if not args.no_octave:
+        spec = []
+        for item in args.octave_runs.split(","):
+            if item:
+                sp, nb = item.split(":")
+                spec.append((int(sp), int(nb)))
+        out["octave_served"] = octave_served_leg(torch, tx, synth, serve_mod(), spec, args.served_lanes,
+                                                 args.served_slots)
+    if not args.no_latency:
+        out["latency_plain256"] = latency_leg(torch, tx, synth)
+        print(f"latency: {json.dumps(out['latency_plain256'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, x, plan.g, args.cpu_seconds)
+        if not args.no_cpu_extra:
+            out["cpu_baseline"]["extra"] = cpu_baseline_extra(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -1,6 +1,7 @@
 // Measured peaks of the units the dedispersion kernels use, on the current
-// GPU: HBM copy bandwidth, 32-bit and packed 16-bit integer add rates, byte
-// permute / align rates, and LDS read bandwidth.  Prints one JSON object.
+// GPU: HBM copy bandwidth, 32-bit and packed 16-bit integer add rates, the
+// issue rates of the three-operand add, byte-align and byte-permute
+// instructions, and LDS read bandwidth.  Prints one JSON object.
 //
 //   tx_peaks [--quick]
 #include <hip/hip_runtime.h>
@@ -72,6 +73,30 @@ __global__ __launch_bounds__(kThreads) void perm_add_kernel(const uint32_t* in, 
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int k = 0; k < kAcc; ++k) a[k] += __builtin_amdgcn_perm(a[(k + 1) % kAcc], a[k] ^ x, sel);
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) r ^= a[k];
+    out[blockIdx.x * kThreads + threadIdx.x] = r;
+}
+
+// Issue rates of the three-operand (VOP3) instructions of the first stage's
+// inner loop, one instruction per step, 16 independent chains per lane:
+// v_add3_u32 (kind 0), v_alignbyte_b32 (kind 1), v_perm_b32 (kind 2).
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void vop3_kernel(const uint32_t* in, uint32_t* out, int iters) {
+    uint32_t a[kAcc];
+    const uint32_t x = in[threadIdx.x & 63];
+    const uint32_t sel = KIND == 1 ? (in[1] & 3u) : 0x0C030C01u + (in[0] & 3u) * 0x00010001u;
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) a[k] = x ^ (k * 0x01010101u);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < kAcc; ++k) {
+            if constexpr (KIND == 0) a[k] = a[k] + a[(k + 1) % kAcc] + x;
+            else if constexpr (KIND == 1) a[k] = __builtin_amdgcn_alignbyte(a[(k + 1) % kAcc], a[k], sel);
+            else a[k] = __builtin_amdgcn_perm(a[(k + 1) % kAcc], a[k], sel);
+        }
     }
     uint32_t r = 0;
 #pragma unroll
@@ -157,6 +182,13 @@ int main(int argc, char** argv) {
     float t_perm = time_ms([&] { hipLaunchKernelGGL(perm_add_kernel, dim3(blocks), dim3(kThreads), 0, 0, in, out, iters); }, 3);
     const double perm_add = lanes * iters * kAcc / (t_perm * 1e-3);   // (perm + add) pairs per second
 
+    float t_v3[3];
+    t_v3[0] = time_ms([&] { hipLaunchKernelGGL(vop3_kernel<0>, dim3(blocks), dim3(kThreads), 0, 0, in, out, iters); }, 3);
+    t_v3[1] = time_ms([&] { hipLaunchKernelGGL(vop3_kernel<1>, dim3(blocks), dim3(kThreads), 0, 0, in, out, iters); }, 3);
+    t_v3[2] = time_ms([&] { hipLaunchKernelGGL(vop3_kernel<2>, dim3(blocks), dim3(kThreads), 0, 0, in, out, iters); }, 3);
+    double v3_rate[3];
+    for (int k = 0; k < 3; ++k) v3_rate[k] = lanes * iters * kAcc / (t_v3[k] * 1e-3) / cus / clk_hz;
+
     const int lit = quick ? 2000 : 20000;
     float t_l4 = time_ms([&] { hipLaunchKernelGGL(lds_kernel<4>, dim3(blocks), dim3(kThreads), 0, 0, out, lit); }, 3);
     float t_l8 = time_ms([&] { hipLaunchKernelGGL(lds_kernel<8>, dim3(blocks), dim3(kThreads), 0, 0, out, lit); }, 3);
@@ -177,10 +209,11 @@ int main(int argc, char** argv) {
                 "\"add32_per_clk_per_cu\": %.2f, \"add16_per_clk_per_cu\": %.2f, "
                 "\"lds_b32_bytes_per_s\": %.4e, \"lds_b64_bytes_per_s\": %.4e, \"lds_b128_bytes_per_s\": %.4e, "
                 "\"lds_b128_bytes_per_clk_per_cu\": %.1f, \"lds_b32_bytes_per_clk_per_cu\": %.1f, "
+                "\"add3_per_clk_per_cu\": %.2f, \"alignbyte_per_clk_per_cu\": %.2f, \"perm_per_clk_per_cu\": %.2f, "
                 "\"hbm_copy_bytes_per_s\": %.4e}\n",
                 prop.name, cus, clk_hz / 1e6, add32, add16, perm_add, add32 / cus / clk_hz, add16 / cus / clk_hz,
                 lds_bw(t_l4, 4), lds_bw(t_l8, 8), lds_bw(t_l16, 16), lds_bw(t_l16, 16) / cus / clk_hz,
-                lds_bw(t_l4, 4) / cus / clk_hz, copy_bw);
+                lds_bw(t_l4, 4) / cus / clk_hz, v3_rate[0], v3_rate[1], v3_rate[2], copy_bw);
     CHECK(hipFree(src));
     CHECK(hipFree(dst));
     CHECK(hipFree(in));
