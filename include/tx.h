@@ -281,6 +281,55 @@ tx_status tx_channel_power_sums(const uint8_t* d_in, int64_t in_pitch, int32_t n
 tx_status tx_skf_mask(const uint64_t* sums, int32_t nchan, int64_t nt, double threshold, uint8_t* mask);
 
 /* ------------------------------------------------------------------------ */
+/* Normalisation (Sec. 2.1) and the floating-point variant of the path        */
+/* ------------------------------------------------------------------------ */
+
+#define TX_WEIGHT_UNIT 0          /* scale by 1/sigma: zero mean, unit variance per channel */
+#define TX_WEIGHT_INVERSE_VAR 1   /* scale by 1/sigma^2: inverse-variance weights */
+
+/*
+ * tx_norm_weights (host): per-channel normalisation (Sec. 2.1) from exact
+ * power sums of nt samples per channel (host array, 4*nchan values as
+ * tx_channel_power_sums writes them; 1 <= nt <= 2^32).  Per channel the mean
+ * S1/n and the population variance (n S2 - S1^2)/n^2 (exact integer
+ * numerator, one rounding to float64); a normalised sample is
+ * scale[c] * x - offset[c] with
+ *   TX_WEIGHT_UNIT:        scale = 1/sigma,   offset = mean/sigma
+ *                          (zero mean and unit variance in every channel);
+ *   TX_WEIGHT_INVERSE_VAR: scale = 1/sigma^2, offset = mean/sigma^2
+ *                          (each channel weighted by its inverse variance),
+ * computed in float64 and rounded to float32 once.  A channel of zero
+ * variance gets scale = offset = 0 (it adds nothing).  scale, offset: host
+ * arrays of nchan floats.  Errors: TX_EINVAL (bad argument, or sums that
+ * cannot belong to one channel).
+ */
+tx_status tx_norm_weights(const uint64_t* sums, int32_t nchan, int64_t nt, int32_t weighting, float* scale,
+                          float* offset);
+
+/*
+ * tx_dedisperse_norm: two-stage sub-band dedispersion of the normalised block
+ * (Sec. 2.1 then Sec. 2.3), in float32.  Arguments as tx_dedisperse, plus
+ * d_scale, d_offset (device float[nchan], 4-byte aligned): channel c's sample
+ * x enters as scale[c] * x - offset[c], rounded to float32 once (a fused
+ * multiply-add); d_out is float32, ndm rows of out_pitch elements (>= nt,
+ * 4-byte aligned).  Y[i][t] = sum over s of B[j][s][t + D(dm_i,f_s) -
+ * D(c_j,f_s)], B[j][s][u] = sum over ch in s of the normalised samples at
+ * u + D(c_j, f_ch) (the plan's offsets).  Summed in float32 in that order, a
+ * value differs from the exact sum by at most (m + nsub + 1) * 2^-24 times
+ * the sum of the absolute normalised samples it adds (m = channels per
+ * sub-band).  Scratch (4 bytes per first-stage sample) comes from the
+ * device's stream-ordered pool.  The plan's channel mask and tiles do not
+ * apply (a dropped channel is one with scale = offset = 0).  Errors:
+ * TX_EINVAL, TX_ESTATE, TX_ENOMEM, TX_ENOTSUP (a staged row does not fit the
+ * device's LDS), TX_EDEVICE.
+ */
+tx_status tx_dedisperse_norm(tx_plan_t plan, const uint8_t* d_in, int64_t in_pitch, int64_t nt,
+                             const float* d_scale, const float* d_offset, float* d_out, int64_t out_pitch,
+                             hipStream_t stream);
+/* Bytes of scratch tx_dedisperse_norm takes from the pool for nt outputs. */
+tx_status tx_dedisperse_norm_ws_size(tx_plan_t plan, int64_t nt, int64_t* bytes);
+
+/* ------------------------------------------------------------------------ */
 /* DM ranges with downsampling (Sec. 2.3, dedispersion plans)                 */
 /* ------------------------------------------------------------------------ */
 
@@ -444,6 +493,22 @@ tx_status tx_candidates(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64_t p
                         const int32_t* widths, int32_t nw, double gamma,
                         tx_cand* d_out, int64_t cap, int64_t* d_count,
                         double* d_snr, int32_t* d_width, int64_t* d_time, hipStream_t stream);
+
+/*
+ * tx_boxcar_snr_f32 / tx_candidates_f32: tx_boxcar_snr and tx_candidates for
+ * a float32 DM x time array (Sec. 2.4 Eq. 5, Sec. 2.5), evaluated in float64:
+ * per row the mean and population variance S2/T - (S1/T)^2 of its T values;
+ * the window [t, t+w) inside the row has sum S (float64 running sums) and
+ * snr = ((S - w * mean) / sigma) / sqrt(w).  Per width the earliest start of
+ * the largest S/N, across widths the largest (ties to the smaller width); a
+ * row of zero variance gives (0.0, widths[0], 0) and no candidates.  Other
+ * arguments, limits and errors as the integer calls (no value-range flag).
+ */
+tx_status tx_boxcar_snr_f32(const float* d_dmt, int32_t ndm, int64_t nt, int64_t pitch, const int32_t* widths,
+                            int32_t nw, double* d_snr, int32_t* d_width, int64_t* d_time, hipStream_t stream);
+tx_status tx_candidates_f32(const float* d_dmt, int32_t ndm, int64_t nt, int64_t pitch, const int32_t* widths,
+                            int32_t nw, double gamma, tx_cand* d_out, int64_t cap, int64_t* d_count,
+                            double* d_snr, int32_t* d_width, int64_t* d_time, hipStream_t stream);
 
 /*
  * tx_cluster: DBSCAN of thresholded DM-time points (Sec. 2.5) to remove

@@ -263,6 +263,70 @@ def tx_dedisperse(plan, d_in, nt, d_out, stream=None, ws=None):
     _check(st, "tx_dedisperse")
 
 
+TX_WEIGHT_UNIT, TX_WEIGHT_INVERSE_VAR = 0, 1
+
+_SIGS3 = {
+    "tx_norm_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "tx_dedisperse_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_void_p]),
+    "tx_dedisperse_norm_ws_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "tx_boxcar_snr_f32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _c_i32p,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "tx_candidates_f32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _c_i32p,
+                                         ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+}
+_SIGS.update(_SIGS3)
+
+
+def _setup_norm():
+    L = lib()
+    for name, (res, args) in _SIGS3.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+def tx_norm_weights(sums, nt, weighting=TX_WEIGHT_UNIT):
+    """Per-channel (scale, offset) float32 arrays from power sums [nchan, 4] (host)."""
+    s = np.ascontiguousarray(sums, dtype=np.uint64)
+    nchan = s.shape[0]
+    scale = np.empty(nchan, dtype=np.float32)
+    offset = np.empty(nchan, dtype=np.float32)
+    _check(_setup_norm().tx_norm_weights(s.ctypes.data, nchan, int(nt), int(weighting), scale.ctypes.data,
+                                         offset.ctypes.data), "tx_norm_weights")
+    return scale, offset
+
+
+def tx_dedisperse_norm(plan, d_in, nt, d_scale, d_offset, d_out, stream=None):
+    """d_in uint8 [nchan, pitch]; d_scale, d_offset float32 [nchan]; d_out float32 [ndm, pitch]."""
+    in_pitch = d_in.stride(0) * d_in.element_size()
+    _check(_setup_norm().tx_dedisperse_norm(plan.handle, _ptr(d_in), in_pitch, int(nt), _ptr(d_scale),
+                                            _ptr(d_offset), _ptr(d_out), d_out.stride(0), _stream(stream)),
+           "tx_dedisperse_norm")
+
+
+def tx_boxcar_snr_f32(dmt, nt, widths, snr, width, time, stream=None):
+    w, wp = _widths(widths)
+    _check(_setup_norm().tx_boxcar_snr_f32(_ptr(dmt), dmt.shape[0], int(nt), dmt.stride(0), wp, len(w), _ptr(snr),
+                                           _ptr(width), _ptr(time), _stream(stream)), "tx_boxcar_snr_f32")
+
+
+def tx_candidates_f32(dmt, nt, widths, gamma, cands, count, peaks=None, stream=None):
+    """As tx_candidates, for a float32 DM x time tensor."""
+    w, wp = _widths(widths)
+    cap = (cands.numel() * cands.element_size()) // CAND_DTYPE.itemsize
+    p = (ctypes.c_void_p(0),) * 3 if peaks is None else tuple(_ptr(t) for t in peaks)
+    _check(_setup_norm().tx_candidates_f32(_ptr(dmt), dmt.shape[0], int(nt), dmt.stride(0), wp, len(w),
+                                           float(gamma), _ptr(cands), cap, _ptr(count), *p,
+                                           _stream(stream)), "tx_candidates_f32")
+
+
 TX_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 

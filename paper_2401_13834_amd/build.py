@@ -22,9 +22,9 @@ PEAKS = os.path.join(HERE, "tx_peaks")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["tx_kernels_dedisp.hip", "tx_kernels_boxcar.hip", "tx_kernels_transpose.hip",
-               "tx_kernels_downsample.hip", "tx_kernels_cluster.hip", "tx_kernels_stats.hip"]
+               "tx_kernels_downsample.hip", "tx_kernels_cluster.hip", "tx_kernels_stats.hip", "tx_kernels_norm.hip"]
 HOST_SOURCES = ["tx_plan.cpp", "tx_api.cpp", "tx_profile.cpp", "tx_stream.cpp", "tx_batch.cpp", "tx_autotune.cpp",
-                "tx_ranges.cpp", "tx_cluster.cpp", "tx_mask.cpp"]
+                "tx_ranges.cpp", "tx_cluster.cpp", "tx_mask.cpp", "tx_norm.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-result"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -131,6 +131,73 @@ struct BoxcarArgs {
     unsigned long long* count;
 };
 
+// Dedispersion of normalised data and the float matched filter
+// (tx_kernels_norm.hip).  Stage 1: workgroups of kNormJ coarse trials and
+// kNormTT1 outputs (8 per lane); stage 2: kNormIW fine trials and kNormTT2
+// outputs (4 per lane).
+constexpr int kNormJ = 4;
+constexpr int kNormTT1 = 2048;
+constexpr int kNormIW = 16;
+constexpr int kNormTT2 = 1024;
+constexpr int kNormLds = 32 * 1024;
+
+struct Stage1NormArgs {
+    const uint8_t* x;       // input rows (16-byte aligned)
+    int64_t x_pitch;
+    int64_t x_len;          // valid samples per row (nt + overlap)
+    const float* scale;     // [nchan] normalised sample = scale x - offset
+    const float* offset;
+    float* B;               // [ngroups][nsub][B_pitch]
+    int64_t B_pitch;
+    const int32_t* dT;
+    int32_t gpad;
+    int32_t nsub, m, ngroups;
+    int32_t n_jchunks, n_ttiles;
+    int32_t lds_bytes;
+};
+
+struct Stage2NormArgs {
+    const float* B;
+    int64_t B_pitch;
+    float* Y;
+    int64_t y_pitch;
+    int64_t nt;
+    const int32_t* rT;
+    int32_t dpad;
+    int32_t ndm, nsub, g, ngroups;
+    int32_t n_ichunks, n_ttiles;
+    int32_t lds_bytes;
+};
+
+struct BoxcarNormArgs {
+    const float* y;
+    int64_t pitch;
+    int32_t ndm;
+    int32_t nt;
+    int32_t ne;             // widths <= nt
+    int32_t wmax;
+    int32_t w_first;
+    int32_t widths[TX_MAX_WIDTHS];
+    double rsw[TX_MAX_WIDTHS];
+    double gamma;
+    int32_t want_peaks;
+    int32_t want_cands;
+    double* snr;
+    int32_t* width;
+    int64_t* time;
+    tx_cand* cands;
+    int64_t cap;
+    unsigned long long* count;
+};
+
+struct NormGeom {
+    int64_t B_pitch;        // floats per first-stage series
+    int64_t ws_bytes;       // scratch bytes
+    int32_t n_ttiles1, n_ttiles2, n_jchunks, n_ichunks;
+    int32_t lds1, lds2;
+    bool ok;
+};
+
 // Tile variants (tx_kernels_dedisp.hip).  Stage 1: Q1 consecutive dwords (odd Q1, 4 outputs each)
 // per lane, JW coarse trials per wave, 4 waves sharing one time tile of
 // 256*Q1 outputs.  Stage 2: Q2 dwords (2 outputs each) per lane, the 4 waves
@@ -263,6 +330,11 @@ hipError_t launch_dedisperse(const tx_plan_s* p, const DedispGeom& geo, const ui
                              int64_t nt, int32_t* d_out, int64_t out_pitch, uint16_t* d_B, hipStream_t stream,
                              int x_off = 0);
 hipError_t launch_boxcar(const BoxcarArgs& a, hipStream_t stream);
+NormGeom norm_geometry(const tx_plan_s* p, int64_t nt);
+hipError_t launch_dedisperse_norm(const tx_plan_s* p, const NormGeom& g, const uint8_t* d_in, int64_t in_pitch,
+                                  int64_t nt, const float* scale, const float* offset, float* d_out,
+                                  int64_t out_pitch, float* d_B, hipStream_t stream);
+hipError_t launch_boxcar_norm(const BoxcarNormArgs& a, hipStream_t stream);
 // tx_dedisperse_noalloc: chunks of the block through the file-scope scratch
 // of device `dev` (current).  hipErrorInvalidValue with *need_bytes > 0 when
 // one chunk's first-stage series do not fit it (the smallest need), -1 when

@@ -169,3 +169,22 @@ def test_skf_mask_host_function_matches_oracle():
         want = oracle.skf_mask(sums, nt, 3.5)
         got = tx.tx_skf_mask(sums.astype(np.uint64), nt, 3.5)
         assert np.array_equal(got, want), trial
+
+
+@pytest.mark.parametrize("weighting", [0, 1])
+def test_norm_weights_host_call_equals_oracle(weighting):
+    """tx_norm_weights (host code) gives the oracle's float32 weights bit for
+    bit, including a zero-variance channel and very unequal channels."""
+    rng = np.random.default_rng(5 + weighting)
+    nchan, n = 40, 3001
+    mu = rng.uniform(20.0, 230.0, size=nchan)
+    sig = rng.uniform(0.3, 60.0, size=nchan)
+    x = np.clip(np.rint(mu[:, None] + sig[:, None] * rng.standard_normal((nchan, n))), 0, 255).astype(np.uint8)
+    x[7] = 42
+    sums = oracle.channel_power_sums(x)
+    scale, offset = tx.tx_norm_weights(sums, n, weighting)
+    ws, wo = oracle.norm_weights(sums, n, weighting)
+    assert np.array_equal(scale.astype(np.float64), ws) and np.array_equal(offset.astype(np.float64), wo)
+    assert scale[7] == 0.0 and offset[7] == 0.0
+    with pytest.raises(tx.TxError):
+        tx.tx_norm_weights(sums, n, 2)
