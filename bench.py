@@ -27,6 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_ADD16 = 256 * 4 * 16 * 2 * 2.4e9   # 16-bit integer adds/s: 256 CUs x 64 lanes x 2 (packed) x 2.4 GHz
+# Three-operand (VOP3) instructions per clock per CU measured by tx_peaks on
+# MI355X (v_add3_u32 59.9, v_alignbyte_b32 58.7, v_perm_b32 59.7).
+MEASURED_VOP3_PER_CLK_CU = 59.4
 PAPER_DM_SAMPLES_PER_S = 4096 / 153e-6  # real time on one CPU core, 4096 channels and trials, 153 us
 
 
@@ -703,6 +706,7 @@ def main():
     # reads at the 110 B/clk/CU measured on this part.
     q1 = tx.tx_tile_variants(1)[plan.resolved_tiles(nt)[0]][0] // 256
     valu_ceiling = 256 * 4 * 16 * 2.4e9 * 4 / 3 / 1e12
+    valu_ceiling_measured = 256 * MEASURED_VOP3_PER_CLK_CU * 2.4e9 * 4 / 3 / 1e12
     lds_ceiling = 110.0 * 256 * 2.4e9 / ((q1 + 1) / q1) / 1e12
     loop_ceiling = min(valu_ceiling, lds_ceiling)
     roofline = {"bound": "alu", "kernel": "stage1", "achieved": round(achieved, 3),
@@ -713,7 +717,9 @@ def main():
                 "hbm_frac": None if traffic is None else round(traffic / t1 / 8e12, 4),
                 "loop_ceiling_Tadd_s": round(loop_ceiling, 2),
                 "loop_bound": "valu" if valu_ceiling <= lds_ceiling else "lds",
-                "loop_ceiling_frac": round(achieved / loop_ceiling, 4)}
+                "loop_ceiling_frac": round(achieved / loop_ceiling, 4),
+                "loop_ceiling_measured_Tadd_s": round(min(valu_ceiling_measured, lds_ceiling), 2),
+                "loop_ceiling_measured_frac": round(achieved / min(valu_ceiling_measured, lds_ceiling), 4)}
 
     out = {
         "metric": "dedispersed DM-trial samples/s (plain one-beam-per-launch path)",
