@@ -298,7 +298,7 @@ def tuned_classes(tx, tune, beams, effort, path):
     return out
 
 
-def batched_leg(torch, tx, synth, steps, tune_effort=0):
+def batched_leg(torch, tx, synth, steps, tune_effort=0, tune=True):
     """64 beams of uneven shape (channels 1024-4096, blocks 16384-65536, 512-4096
     DM trials up to DM 3000) dedispersed with peaks and candidates in one batch
     launch (persistent kernels) replayed as a HIP graph; against the same jobs
@@ -306,7 +306,7 @@ def batched_leg(torch, tx, synth, steps, tune_effort=0):
     with each plan's own sub-band count and default tiles, and with the
     sub-band count and tiles autotuned per (channels, DM range) class."""
     import tempfile
-    from paper_2401_13834_amd import tune
+    from paper_2401_13834_amd import tune as tune_mod
     beams = synth.batched_beams()
     inputs = []
     for wl in beams:
@@ -319,9 +319,11 @@ def batched_leg(torch, tx, synth, steps, tune_effort=0):
         inputs.append(d_in)
     stream = torch.cuda.Stream()
     t_tune = time.perf_counter()
-    with tempfile.TemporaryDirectory() as tmp:
-        with torch.cuda.stream(stream):
-            classes = tuned_classes(tx, tune, beams, tune_effort, os.path.join(tmp, "tiles.json"))
+    classes = {}
+    if tune:
+        with tempfile.TemporaryDirectory() as tmp:
+            with torch.cuda.stream(stream):
+                classes = tuned_classes(tx, tune_mod, beams, tune_effort, os.path.join(tmp, "tiles.json"))
     t_tune = time.perf_counter() - t_tune
 
     def run(tuned):
@@ -419,16 +421,18 @@ def batched_leg(torch, tx, synth, steps, tune_effort=0):
 
     plain_plans = run(False)
     print(f"batched (plan defaults): {json.dumps(plain_plans)}", file=sys.stderr, flush=True)
-    tuned = run(True)
-    print(f"batched (autotuned): {json.dumps(tuned)}", file=sys.stderr, flush=True)
-    del inputs
-    torch.cuda.empty_cache()
     out = {"workload": "batched-64", "beams": len(beams), "graph": True, "persistent": True}
     out.update(plain_plans)
-    out["autotuned"] = dict(tuned, classes={f"{k[0]}ch-dm{int(k[1])}": {"nsub": v[0], "tiles": list(v[1]),
-                                                                         "ms_by_nsub": v[2]}
-                                            for k, v in classes.items()},
-                            tune_seconds=round(t_tune, 1), gain_vs_plan_defaults=tuned["value"] / plain_plans["value"])
+    if tune:
+        tuned = run(True)
+        print(f"batched (autotuned): {json.dumps(tuned)}", file=sys.stderr, flush=True)
+        out["autotuned"] = dict(tuned, classes={f"{k[0]}ch-dm{int(k[1])}": {"nsub": v[0], "tiles": list(v[1]),
+                                                                             "ms_by_nsub": v[2]}
+                                                for k, v in classes.items()},
+                                tune_seconds=round(t_tune, 1),
+                                gain_vs_plan_defaults=tuned["value"] / plain_plans["value"])
+    del inputs
+    torch.cuda.empty_cache()
     return out
 
 
@@ -442,6 +446,7 @@ def served_leg(torch, tx, synth, serve, runs_spec, lanes, max_slots):
     plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
     nchan, nt = len(wl.freqs), wl.nt
     t_blk = nt * wl.tsamp
+    adds_per_dm_sample = plan_adds(plan, nt) / (plan.ndm * nt)
     nbeams = 256
     runs = []
     slots = {}
@@ -470,6 +475,8 @@ def served_leg(torch, tx, synth, serve, runs_spec, lanes, max_slots):
                          "p99_ms": stats.p99_s * 1e3, "max_ms": stats.max_s * 1e3, "value": stats.throughput,
                          "gpu_busy": stats.gpu_s / stats.wall_s if stats.wall_s > 0 else None,
                          "lane_overlap": stats.lane_s / stats.gpu_s if stats.gpu_s > 0 else None,
+                         "adds_per_s": stats.throughput * adds_per_dm_sample,
+                         "frac_of_add_peak": stats.throughput * adds_per_dm_sample / PEAK_ADD16,
                          "p99_below_block": stats.p99_s < t_blk})
             print(f"served: {json.dumps(runs[-1])}", file=sys.stderr, flush=True)
         srv.close()
@@ -507,7 +514,9 @@ def octave_served_leg(torch, tx, synth, serve, runs_spec, lanes, max_slots, nbea
         arr = synth.poisson_arrivals(nbeams, nblocks, t_blk, speed, 50 + speed)
         _, stats = srv.run(arr, lambda b, k: pool[(b * 5 + k) % len(pool)])
         emitted = stats.dm_samples
+        apd = plan_adds(plan, nt) / (plan.ndm * nt)
         runs.append({"speed": speed, "blocks": stats.blocks, "batches": stats.batches,
+                     "adds_per_s": stats.throughput * apd, "frac_of_add_peak": stats.throughput * apd / PEAK_ADD16,
                      "mean_batch": round(stats.mean_batch, 2), "p50_ms": stats.p50_s * 1e3,
                      "p99_ms": stats.p99_s * 1e3, "max_ms": stats.max_s * 1e3, "value": stats.throughput,
                      "dm_samples": emitted, "gpu_busy": stats.gpu_s / stats.wall_s if stats.wall_s > 0 else None,
@@ -603,6 +612,69 @@ def cpu_baseline_extra(seconds):
     return {"kind": "oracle", "runs": out, "host_threads": nproc}
 
 
+def norm_leg(torch, tx, synth, steps=10):
+    """The normalised variant on the paper-scale block (Sec. 2.1 then the
+    path in float32): exact per-channel power sums on the device, inverse-
+    variance weights on the host, float32 two-stage dedispersion and the
+    float64 matched filter with candidates.  Timed per step (weights, upload,
+    dedispersion, candidates); per-kernel times from events."""
+    wl = synth.workload("paper-4096")
+    plan = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, wl.nsub)
+    nchan, nt, ndm = plan.nchan, wl.nt, plan.ndm
+    n = nt + plan.overlap
+    pitch = (n + 255) // 256 * 256
+    d_in = synth.device_normal_u8(torch, nchan, pitch, wl.seed, pulses=place_pulses(plan, wl, synth))
+    sums = torch.empty((nchan, 4), dtype=torch.int64, device="cuda")
+    y = torch.empty((ndm, nt), dtype=torch.float32, device="cuda")
+    cap = 1 << 20
+    cands = torch.empty((cap, 3), dtype=torch.int64, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    peaks = (torch.empty(ndm, dtype=torch.float64, device="cuda"),
+             torch.empty(ndm, dtype=torch.int32, device="cuda"),
+             torch.empty(ndm, dtype=torch.int64, device="cuda"))
+    d_s = torch.empty(nchan, dtype=torch.float32, device="cuda")
+    d_o = torch.empty(nchan, dtype=torch.float32, device="cuda")
+
+    def step():
+        tx.tx_channel_power_sums(d_in, nchan, n, sums)
+        scale, offset = tx.tx_norm_weights(sums.cpu().numpy(), n, tx.TX_WEIGHT_INVERSE_VAR)
+        d_s.copy_(torch.from_numpy(scale))
+        d_o.copy_(torch.from_numpy(offset))
+        tx.tx_dedisperse_norm(plan, d_in, nt, d_s, d_o, y)
+        tx.tx_candidates_f32(y, nt, wl.widths, wl.gamma, cands, count, peaks=peaks)
+
+    step()
+    torch.cuda.synchronize()
+    for k in (tx.TX_KERNEL_STAGE1, tx.TX_KERNEL_STAGE2, tx.TX_KERNEL_BOXCAR):
+        tx.tx_profile_collect(k)
+    tx.tx_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    tx.tx_profile_enable(False)
+    kern = {}
+    for name, k in (("stage1", tx.TX_KERNEL_STAGE1), ("stage2", tx.TX_KERNEL_STAGE2), ("boxcar", tx.TX_KERNEL_BOXCAR)):
+        ms, nl = tx.tx_profile_collect(k)
+        kern[name] = {"avg_ms": ms / max(nl, 1), "launches": nl}
+    best = int(torch.argmax(peaks[0]).item())
+    # float operations: a fused multiply-add and an add per first-stage term,
+    # an add per second-stage term
+    flops = 3 * plan.ngroups * nchan * nt + ndm * plan.nsub * nt
+    t12 = (kern["stage1"]["avg_ms"] + kern["stage2"]["avg_ms"]) * 1e-3
+    out = {"workload": "paper-4096 normalised (inverse-variance weights), float32", "ms_per_block": dt * 1e3,
+           "dm_trial_samples_per_s": ndm * nt / dt, "kernels_ms": kern, "candidates": int(count.item()),
+           "peak_dm_index": best, "peak_snr": float(peaks[0][best].item()),
+           "roofline": {"bound": "alu", "achieved": round(flops / t12 / 1e12, 3), "peak": 157.3,
+                        "unit": "TFLOP/s (fp32 vector)", "frac": round(flops / t12 / 157.3e12, 4),
+                        "flops_per_block": flops}}
+    del d_in, y, cands
+    torch.cuda.empty_cache()
+    tx.tx_pool_trim()
+    return out
+
+
 def serve_mod():
     from paper_2401_13834_amd import serve
     return serve
@@ -618,6 +690,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-beam batched launch")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--batched-no-tune", action="store_true",
+                    help="run the batched leg with each plan's own sub-band count and tiles only")
     ap.add_argument("--no-served", action="store_true", help="skip the served-stream runs")
     ap.add_argument("--served-runs", default="host:1:2,host:8:9,host:24:13,device:24:13,device:48:25",
                     help="source:speed:blocks-per-beam of the served runs (source host or device)")
@@ -631,6 +705,7 @@ def main():
     ap.add_argument("--octave-runs", default="8:9,24:9",
                     help="speed:blocks-per-beam of the served multi-octave runs")
     ap.add_argument("--no-latency", action="store_true", help="skip the plain-256 latency leg")
+    ap.add_argument("--no-norm", action="store_true", help="skip the normalised (float32) variant leg")
     ap.add_argument("--no-cpu-extra", action="store_true",
                     help="skip the CPU oracle at 1 thread and on the other workloads")
     ap.add_argument("--copy-probe", action="store_true",
@@ -764,7 +839,7 @@ def main():
         out["cluster"] = cluster_leg(torch, tx, synth)
         print(f"cluster: {json.dumps(out['cluster'])}", file=sys.stderr, flush=True)
     if not args.no_batched:
-        out["batched"] = batched_leg(torch, tx, synth, args.batched_steps)
+        out["batched"] = batched_leg(torch, tx, synth, args.batched_steps, tune=not args.batched_no_tune)
         print(f"batched: {json.dumps(out['batched'])}", file=sys.stderr, flush=True)
     if not args.no_served:
         serve = serve_mod()
@@ -782,6 +857,9 @@ def main():
                 spec.append((int(sp), int(nb)))
         out["octave_served"] = octave_served_leg(torch, tx, synth, serve_mod(), spec, args.served_lanes,
                                                  args.served_slots)
+    if not args.no_norm:
+        out["normalised"] = norm_leg(torch, tx, synth)
+        print(f"normalised: {json.dumps(out['normalised'])}", file=sys.stderr, flush=True)
     if not args.no_latency:
         out["latency_plain256"] = latency_leg(torch, tx, synth)
         print(f"latency: {json.dumps(out['latency_plain256'])}", file=sys.stderr, flush=True)

@@ -511,6 +511,17 @@ tx_status tx_candidates_f32(const float* d_dmt, int32_t ndm, int64_t nt, int64_t
                             double* d_snr, int32_t* d_width, int64_t* d_time, hipStream_t stream);
 
 /*
+ * tx_boxcar_snr_fixed: tx_boxcar_snr_f32 with the noise mean and sigma given
+ * (finite, sigma > 0) instead of estimated from each row: snr = ((S - w mean)
+ * / sigma) / sqrt(w) (Sec. 2.4 Eq. 5).  For checks of Eq. 5 and of the
+ * width-mismatch loss on noise-free pulses, and for series whose noise is
+ * known (a normalised block's).  Errors: TX_EINVAL.
+ */
+tx_status tx_boxcar_snr_fixed(const float* d_dmt, int32_t ndm, int64_t nt, int64_t pitch, const int32_t* widths,
+                              int32_t nw, double mean, double sigma, double* d_snr, int32_t* d_width,
+                              int64_t* d_time, hipStream_t stream);
+
+/*
  * tx_cluster: DBSCAN of thresholded DM-time points (Sec. 2.5) to remove
  * duplicate detections of one pulse.
  *

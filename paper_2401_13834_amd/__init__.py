@@ -275,6 +275,9 @@ _SIGS3 = {
     "tx_boxcar_snr_f32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _c_i32p,
                                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]),
+    "tx_boxcar_snr_fixed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _c_i32p,
+                                           ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "tx_candidates_f32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _c_i32p,
                                          ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -315,6 +318,14 @@ def tx_boxcar_snr_f32(dmt, nt, widths, snr, width, time, stream=None):
     w, wp = _widths(widths)
     _check(_setup_norm().tx_boxcar_snr_f32(_ptr(dmt), dmt.shape[0], int(nt), dmt.stride(0), wp, len(w), _ptr(snr),
                                            _ptr(width), _ptr(time), _stream(stream)), "tx_boxcar_snr_f32")
+
+
+def tx_boxcar_snr_fixed(dmt, nt, widths, mean, sigma, snr, width, time, stream=None):
+    """Peak S/N of float32 rows with a given noise mean and sigma."""
+    w, wp = _widths(widths)
+    _check(_setup_norm().tx_boxcar_snr_fixed(_ptr(dmt), dmt.shape[0], int(nt), dmt.stride(0), wp, len(w),
+                                             float(mean), float(sigma), _ptr(snr), _ptr(width), _ptr(time),
+                                             _stream(stream)), "tx_boxcar_snr_fixed")
 
 
 def tx_candidates_f32(dmt, nt, widths, gamma, cands, count, peaks=None, stream=None):

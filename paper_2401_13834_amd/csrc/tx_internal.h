@@ -182,6 +182,8 @@ struct BoxcarNormArgs {
     double gamma;
     int32_t want_peaks;
     int32_t want_cands;
+    int32_t fixed;          // 1: use fixed_mean / fixed_sigma instead of the row's statistics
+    double fixed_mean, fixed_sigma;
     double* snr;
     int32_t* width;
     int64_t* time;

@@ -299,9 +299,15 @@ __global__ __launch_bounds__(kThreads) void boxcar_norm_kernel(BoxcarNormArgs a)
         const double S2 = (sh.red2[0] + sh.red2[1]) + (sh.red2[2] + sh.red2[3]);
         const double mean = S1 / static_cast<double>(T);
         const double var = S2 / static_cast<double>(T) - mean * mean;
-        sh.mean = mean;
-        sh.inv = var > 0.0 ? 1.0 / __builtin_sqrt(var) : 0.0;
-        sh.state = var > 0.0 ? 0 : 1;
+        if (a.fixed) {                                  // given noise statistics
+            sh.mean = a.fixed_mean;
+            sh.inv = 1.0 / a.fixed_sigma;
+            sh.state = 0;
+        } else {
+            sh.mean = mean;
+            sh.inv = var > 0.0 ? 1.0 / __builtin_sqrt(var) : 0.0;
+            sh.state = var > 0.0 ? 0 : 1;
+        }
     }
     __syncthreads();
     if (sh.state != 0) {

@@ -35,7 +35,8 @@ tx_status fill_widths(const int32_t* widths, int32_t nw, int64_t nt, tx::BoxcarN
 
 tx_status boxcar_norm(const float* d_dmt, int32_t ndm, int64_t nt, int64_t pitch, const int32_t* widths, int32_t nw,
                       double gamma, bool cands, tx_cand* d_out, int64_t cap, int64_t* d_count, double* d_snr,
-                      int32_t* d_width, int64_t* d_time, hipStream_t stream) {
+                      int32_t* d_width, int64_t* d_time, hipStream_t stream, bool fixed = false, double mean = 0.0,
+                      double sigma = 1.0) {
     if (ndm < 0 || nt < 1 || nt > TX_MAX_NT_BOXCAR || pitch < nt || (ndm > 0 && !d_dmt)) return TX_EINVAL;
     tx::BoxcarNormArgs a{};
     tx_status st = fill_widths(widths, nw, nt, &a);
@@ -57,6 +58,9 @@ tx_status boxcar_norm(const float* d_dmt, int32_t ndm, int64_t nt, int64_t pitch
     a.cands = d_out;
     a.cap = cap;
     a.count = reinterpret_cast<unsigned long long*>(d_count);
+    a.fixed = fixed ? 1 : 0;
+    a.fixed_mean = mean;
+    a.fixed_sigma = sigma;
     return tx::status_of(tx::launch_boxcar_norm(a, stream));
 }
 
@@ -123,6 +127,15 @@ tx_status tx_boxcar_snr_f32(const float* d_dmt, int32_t ndm, int64_t nt, int64_t
     if (ndm > 0 && !(d_snr && d_width && d_time)) return TX_EINVAL;
     return boxcar_norm(d_dmt, ndm, nt, pitch, widths, nw, 0.0, false, nullptr, 0, nullptr, d_snr, d_width, d_time,
                        stream);
+}
+
+tx_status tx_boxcar_snr_fixed(const float* d_dmt, int32_t ndm, int64_t nt, int64_t pitch, const int32_t* widths,
+                              int32_t nw, double mean, double sigma, double* d_snr, int32_t* d_width, int64_t* d_time,
+                              hipStream_t stream) {
+    if (ndm > 0 && !(d_snr && d_width && d_time)) return TX_EINVAL;
+    if (!std::isfinite(mean) || !std::isfinite(sigma) || !(sigma > 0.0)) return TX_EINVAL;
+    return boxcar_norm(d_dmt, ndm, nt, pitch, widths, nw, 0.0, false, nullptr, 0, nullptr, d_snr, d_width, d_time,
+                       stream, true, mean, sigma);
 }
 
 tx_status tx_candidates_f32(const float* d_dmt, int32_t ndm, int64_t nt, int64_t pitch, const int32_t* widths,

@@ -165,3 +165,36 @@ def test_normalised_path_recovers_a_pulse_in_uneven_channels():
     Y = out.cpu().numpy().astype(np.float64)
     ws, _, _ = oracle.boxcar_peaks_float(Y[best:best + 1], wl.widths)
     assert abs(s[best] - ws[0]) <= 1e-9 * ws[0]
+
+
+@pytest.mark.parametrize("W", [4, 16, 64])
+def test_fixed_sigma_boxcar_width_mismatch_closed_form(W):
+    """Sec. 2.4's width mismatch on the GPU path: a noise-free boxcar pulse
+    of width W and unit amplitude, searched with width w and a fixed sigma,
+    has S/N sqrt(w) for w <= W and W / sqrt(w) for w >= W (relative to its
+    matched S/N sqrt(W): sqrt(w/W) and sqrt(W/w)), to 1e-12."""
+    torch = torch_cuda()
+    nt = 9000
+    y = np.zeros((1, nt), dtype=np.float32)
+    y[0, 3000:3000 + W] = 1.0
+    widths = [1, 2, 4, 8, 16, 32, 64, 128, 256]
+    d = torch.from_numpy(y).to("cuda")
+    for w in widths:
+        snr = torch.empty(1, dtype=torch.float64, device="cuda")
+        wid = torch.empty(1, dtype=torch.int32, device="cuda")
+        tim = torch.empty(1, dtype=torch.int64, device="cuda")
+        tx.tx_boxcar_snr_fixed(d, nt, [w], 0.0, 1.0, snr, wid, tim)
+        torch.cuda.synchronize()
+        want = np.sqrt(w) if w <= W else W / np.sqrt(w)
+        assert abs(float(snr.item()) - want) <= 1e-12 * want
+        assert np.isclose(float(snr.item()) / np.sqrt(W), np.sqrt(min(w, W) / max(w, W)), rtol=1e-12)
+        assert float(snr.item()) == pytest.approx(oracle.boxcar_snr_fixed(y[0], [w], 0.0, 1.0)[0], rel=1e-12)
+    # the matched width wins, at the pulse's start
+    snr = torch.empty(1, dtype=torch.float64, device="cuda")
+    wid = torch.empty(1, dtype=torch.int32, device="cuda")
+    tim = torch.empty(1, dtype=torch.int64, device="cuda")
+    tx.tx_boxcar_snr_fixed(d, nt, widths, 0.0, 1.0, snr, wid, tim)
+    torch.cuda.synchronize()
+    assert int(wid.item()) == W and int(tim.item()) == 3000
+    with pytest.raises(tx.TxError):
+        tx.tx_boxcar_snr_fixed(d, nt, widths, 0.0, 0.0, snr, wid, tim)
