@@ -174,6 +174,34 @@ def test_boxcar_peaks_match_oracle(nt, seed):
     assert np.array_equal(tim, want[2])
 
 
+@pytest.mark.parametrize("widths", [[3], [1, 2], [1, 2, 3], [2, 1000], [4, 8, 12, 20], [5], [1, 3, 5, 6, 7, 12, 33, 100],
+                                    list(range(1, 33)), [1, 2, 4, 8, 16, 31, 64, 127]],
+                         ids=lambda w: "w" + "_".join(map(str, w[:4])) + f"n{len(w)}")
+@pytest.mark.parametrize("nt", [4097, 10001])
+def test_boxcar_width_lists_match_oracle(widths, nt):
+    """Width lists beyond the powers of two: widths 1..3 only, repeats of a
+    short list's last width in the unused slots, lists that start past 3,
+    widths that are not multiples of 4, and all 32 widths."""
+    torch = torch_cuda()
+    _say(f"boxcar widths={widths} nt={nt}")
+    rng = np.random.default_rng(nt + len(widths))
+    rows = 12
+    Y = rng.integers(0, 60, size=(rows, nt)).astype(np.int32)
+    Y[1, nt - 2:] += 700                           # a pulse ending the row
+    Y[2, 4093:4100] += 400                         # a pulse across the first tile boundary
+    Y[3] = 11                                      # zero variance
+    Y[4, ::997] += 900                             # spikes in several tiles
+    d = torch.from_numpy(Y).to("cuda")
+    snr, wid, tim = gpu_peaks(d, nt, widths)
+    want = oracle.boxcar_peaks(Y, widths)
+    _assert_snr(snr, want[0])
+    assert np.array_equal(wid, want[1]) and np.array_equal(tim, want[2])
+    n, rec, _ = gpu_candidates(d, nt, widths, 4.0, with_peaks=True)
+    wc = oracle.boxcar_candidates(Y, widths, 4.0)
+    got = as_tuples(rec)
+    assert n == len(wc) and [c[:3] for c in got] == [c[:3] for c in wc]
+
+
 @pytest.mark.parametrize("nt", [8197, 4 * 4096, 70001])
 def test_boxcar_ties_and_candidates_across_tiles_match_oracle(nt):
     """Long rows with equal maxima in the first and the last tile (the
@@ -384,7 +412,7 @@ def test_all_tile_variants_match_oracle(case):
     n1 = len(tx.tx_tile_variants(1))
     n2 = len(tx.tx_tile_variants(2))
     combos = [(s1, l1, 0, 0) for s1 in range(n1) for l1 in (0, 8192, 16384)]
-    combos += [(0, 0, s2, l2) for s2 in range(n2) for l2 in (0, 8192, 24576, 65536)]
+    combos += [(0, 0, s2, l2) for s2 in range(n2) for l2 in (0, 8192, 24576, 45056, 65536, 98304)]
     for s1, l1, s2, l2 in combos:
         _say(f"  tiles {s1} {l1} {s2} {l2}")
         plan.set_tiles(s1, l1, s2, l2)
