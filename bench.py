@@ -28,26 +28,33 @@ sys.path.insert(0, ROOT)
 
 PEAK_ADD16 = 256 * 4 * 16 * 2 * 2.4e9   # 16-bit integer adds/s: 256 CUs x 64 lanes x 2 (packed) x 2.4 GHz
 # Three-operand (VOP3) instructions per clock per CU measured by tx_peaks on
-# MI355X (v_add3_u32 59.9, v_alignbyte_b32 58.7, v_perm_b32 59.7).
-MEASURED_VOP3_PER_CLK_CU = 59.4
+# MI355X (v_add3_u32 59.5, v_alignbyte_b32 58.7, v_perm_b32 59.8), and the
+# bytes per clock per CU of the first stage's paired 4-byte LDS reads at its
+# 9-dword lane stride (4.12 clocks per wavefront read of 512 bytes).
+MEASURED_VOP3_PER_CLK_CU = 59.3
+MEASURED_PAIRED_LDS_B_PER_CLK_CU = 124.3
 PAPER_DM_SAMPLES_PER_S = 4096 / 153e-6  # real time on one CPU core, 4096 channels and trials, 153 us
 
 
-KERNEL_SOURCES = {"stage1": "tx_kernels_dedisp.hip", "stage2": "tx_kernels_dedisp.hip",
-                  "boxcar": "tx_kernels_boxcar.hip", "transpose": "tx_kernels_transpose.hip",
-                  "stats": "tx_kernels_stats.hip", "downsample2": "tx_kernels_downsample.hip",
-                  "downsample4": "tx_kernels_downsample.hip"}
+KERNEL_SOURCES = {"stage1": ("tx_kernels_dedisp.hip",), "stage2": ("tx_kernels_dedisp.hip",),
+                  "boxcar": ("tx_kernels_boxcar.hip",), "transpose": ("tx_kernels_transpose.hip",),
+                  "stats": ("tx_kernels_stats.hip",), "downsample2": ("tx_kernels_downsample.hip",),
+                  "downsample4": ("tx_kernels_downsample.hip",),
+                  # the batch launch: its persistent dedispersion and boxcar kernels
+                  "batch": ("tx_kernels_dedisp.hip", "tx_kernels_boxcar.hip")}
 
 
 def kernel_source_hash(kernel):
-    """Hash of the kernel's source file without its comments and blank lines,
+    """Hash of the kernel's source files without comments and blank lines,
     so that the stored counters stay valid across edits of comments only."""
-    with open(os.path.join(ROOT, "paper_2401_13834_amd", "csrc", KERNEL_SOURCES[kernel])) as f:
-        src = f.read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    src = re.sub(r"//[^\n]*", "", src)
-    code = "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
-    return hashlib.sha256(code.encode()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2401_13834_amd", "csrc", name)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("\n".join(line.rstrip() for line in src.splitlines() if line.strip()).encode())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(kernel, workload):
@@ -413,12 +420,18 @@ def batched_leg(torch, tx, synth, steps, tune_effort=0, tune=True):
                 "speedup_vs_plain": t_plain / t_batch, "same_as_plain": bool(same),
                 "dm_samples_per_launch": dm_samples, "nsub_chosen": nsubs, "candidates": ncand,
                 "kernels_ms_direct_launch": kern,
-                "roofline": {"bound": "alu", "achieved": round(adds / t_batch / 1e12, 3),
-                             "peak": round(PEAK_ADD16 / 1e12, 3), "unit": "Tadd/s",
-                             "frac": round(adds / t_batch / PEAK_ADD16, 4), "adds_per_launch": adds,
-                             "alg_hbm_bytes_per_launch": alg, "alg_hbm_GBps": round(alg / t_batch / 1e9, 1),
-                             "alg_hbm_frac": round(alg / t_batch / 8e12, 4)}}
+                "roofline": dict({"bound": "alu", "achieved": round(adds / t_batch / 1e12, 3),
+                                  "peak": round(PEAK_ADD16 / 1e12, 3), "unit": "Tadd/s",
+                                  "frac": round(adds / t_batch / PEAK_ADD16, 4), "adds_per_launch": adds,
+                                  "alg_hbm_bytes_per_launch": alg, "alg_hbm_GBps": round(alg / t_batch / 1e9, 1),
+                                  "alg_hbm_frac": round(alg / t_batch / 8e12, 4)},
+                                 # counter bytes per launch, taken on the plan-default batch
+                                 **({} if tuned or traffic is None else
+                                    {"traffic": traffic, "traffic_over_alg": round(traffic / alg, 3),
+                                     "hbm_GBps": round(traffic / t_batch / 1e9, 1),
+                                     "hbm_frac": round(traffic / t_batch / 8e12, 4)}))}
 
+    traffic = load_traffic("batch", "batched-64")
     plain_plans = run(False)
     print(f"batched (plan defaults): {json.dumps(plain_plans)}", file=sys.stderr, flush=True)
     out = {"workload": "batched-64", "beams": len(beams), "graph": True, "persistent": True}
@@ -778,11 +791,11 @@ def main():
     # (Q + 1) / Q 4-byte LDS reads issued as paired reads (Q = output dwords
     # per lane of the tile variant in use).  Its two ceilings: 256 CUs x 4
     # SIMDs x 16 lanes x 2.4 GHz lane-ops at 4/3 adds each, and paired LDS
-    # reads at the 110 B/clk/CU measured on this part.
+    # reads at the rate measured on this part.
     q1 = tx.tx_tile_variants(1)[plan.resolved_tiles(nt)[0]][0] // 256
     valu_ceiling = 256 * 4 * 16 * 2.4e9 * 4 / 3 / 1e12
     valu_ceiling_measured = 256 * MEASURED_VOP3_PER_CLK_CU * 2.4e9 * 4 / 3 / 1e12
-    lds_ceiling = 110.0 * 256 * 2.4e9 / ((q1 + 1) / q1) / 1e12
+    lds_ceiling = MEASURED_PAIRED_LDS_B_PER_CLK_CU * 256 * 2.4e9 / ((q1 + 1) / q1) / 1e12
     loop_ceiling = min(valu_ceiling, lds_ceiling)
     roofline = {"bound": "alu", "kernel": "stage1", "achieved": round(achieved, 3),
                 "peak": round(PEAK_ADD16 / 1e12, 3), "unit": "Tadd/s", "frac": round(achieved * 1e12 / PEAK_ADD16, 4),

@@ -1,7 +1,9 @@
 // Measured peaks of the units the dedispersion kernels use, on the current
 // GPU: HBM copy bandwidth, 32-bit and packed 16-bit integer add rates, the
 // issue rates of the three-operand add, byte-align and byte-permute
-// instructions, and LDS read bandwidth.  Prints one JSON object.
+// instructions, and LDS read bandwidth and cost per read instruction
+// (aligned 4-, 8- and 16-byte reads, the first stage's paired 4-byte reads,
+// and 4-byte reads off dword alignment).  Prints one JSON object.
 //
 //   tx_peaks [--quick]
 #include <hip/hip_runtime.h>
@@ -135,6 +137,58 @@ __global__ __launch_bounds__(kThreads) void lds_kernel(uint32_t* out, int iters)
     out[blockIdx.x * kThreads + threadIdx.x] = acc;
 }
 
+// LDS reads in the first stage's form: every lane reads 10 consecutive dwords
+// (as five paired 4-byte reads) at a lane stride of 9 dwords, from a
+// 16-dword aligned base; indices stay below 3072 + 63 * 9 + 10 < 4096 + 16.
+__global__ __launch_bounds__(kThreads) void lds_stride9_kernel(uint32_t* out, int iters) {
+    __shared__ __align__(16) uint32_t buf[4096 + 16];
+    for (int i = threadIdx.x; i < 4096 + 16; i += kThreads) buf[i] = i * 2654435761u;
+    __syncthreads();
+    uint32_t acc = 0;
+    const int lane = threadIdx.x & 63;
+    int base = (threadIdx.x >> 6) * 256;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t* p = buf + ((base + u * 1024) & 3072) + 9 * lane + (i & 1);
+#pragma unroll
+            for (int c = 0; c < 10; ++c) acc += p[c];
+        }
+        base = (base + 64) & 4095;
+    }
+    out[blockIdx.x * kThreads + threadIdx.x] = acc;
+}
+
+// 4-byte LDS reads at a byte offset `off` (1..3) from a dword boundary,
+// consecutive lanes at consecutive dwords.  The first pass counts reads that
+// do not return the four bytes that follow the address.  The last byte read is
+// below 4 * (3072 + 63 + 1) + 3 < 4 * 4160.
+__device__ __forceinline__ uint32_t lds_pattern(int b) { return static_cast<uint32_t>((b * 37 + (b >> 8) * 11) & 0xFF); }
+
+__global__ __launch_bounds__(kThreads) void lds_unaligned_kernel(uint32_t* out, uint32_t* wrong, int iters, int off) {
+    __shared__ __align__(16) uint32_t buf[4160];
+    uint8_t* b8 = reinterpret_cast<uint8_t*>(buf);
+    for (int i = threadIdx.x; i < 4 * 4160; i += kThreads) b8[i] = static_cast<uint8_t>(lds_pattern(i));
+    __syncthreads();
+    uint32_t acc = 0, bad = 0;
+    const int lane = threadIdx.x & 63;
+    int base = (threadIdx.x >> 6) * 256;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int at = 4 * (((base + u * 1024) & 3072) + lane) + off;
+            const uint32_t v = *reinterpret_cast<const uint32_t*>(b8 + at);
+            acc += v;
+            if (i == 0)
+                bad += v != (lds_pattern(at) | lds_pattern(at + 1) << 8 | lds_pattern(at + 2) << 16 |
+                             lds_pattern(at + 3) << 24);
+        }
+        base = (base + 64) & 4095;
+    }
+    out[blockIdx.x * kThreads + threadIdx.x] = acc;
+    if (bad) atomicAdd(wrong, bad);
+}
+
 __global__ void copy_kernel(const uint4* __restrict__ in, uint4* __restrict__ out, size_t n) {
     size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -194,6 +248,19 @@ int main(int argc, char** argv) {
     float t_l8 = time_ms([&] { hipLaunchKernelGGL(lds_kernel<8>, dim3(blocks), dim3(kThreads), 0, 0, out, lit); }, 3);
     float t_l16 = time_ms([&] { hipLaunchKernelGGL(lds_kernel<16>, dim3(blocks), dim3(kThreads), 0, 0, out, lit); }, 3);
     auto lds_bw = [&](float ms, int w) { return lanes * lit * 8.0 * w / (ms * 1e-3); };
+    // clocks per wave-level read instruction per CU (reads of one wavefront)
+    auto lds_clk = [&](float ms, double wave_reads) { return ms * 1e-3 * clk_hz * cus / wave_reads; };
+    const double waves = (double)blocks * kThreads / 64;
+    float t_s9 = time_ms([&] { hipLaunchKernelGGL(lds_stride9_kernel, dim3(blocks), dim3(kThreads), 0, 0, out, lit); }, 3);
+    uint32_t* wrong;
+    CHECK(hipMalloc(&wrong, 4));
+    CHECK(hipMemset(wrong, 0, 4));
+    const int uit = lit / 8;
+    float t_ua = time_ms([&] { hipLaunchKernelGGL(lds_unaligned_kernel, dim3(blocks), dim3(kThreads), 0, 0, out, wrong,
+                                                  uit, 1); }, 3);
+    uint32_t n_wrong = 0;
+    CHECK(hipMemcpy(&n_wrong, wrong, 4, hipMemcpyDeviceToHost));
+    CHECK(hipFree(wrong));
 
     const size_t bytes = (size_t)(quick ? 1 : 4) << 30;
     uint4 *src, *dst;
@@ -210,10 +277,14 @@ int main(int argc, char** argv) {
                 "\"lds_b32_bytes_per_s\": %.4e, \"lds_b64_bytes_per_s\": %.4e, \"lds_b128_bytes_per_s\": %.4e, "
                 "\"lds_b128_bytes_per_clk_per_cu\": %.1f, \"lds_b32_bytes_per_clk_per_cu\": %.1f, "
                 "\"add3_per_clk_per_cu\": %.2f, \"alignbyte_per_clk_per_cu\": %.2f, \"perm_per_clk_per_cu\": %.2f, "
+                "\"lds_clk_per_wave_read\": {\"b32\": %.2f, \"b64\": %.2f, \"b128\": %.2f, "
+                "\"paired_b32_stride9\": %.2f, \"b32_byte_offset1\": %.2f}, \"lds_b32_byte_offset1_wrong\": %u, "
                 "\"hbm_copy_bytes_per_s\": %.4e}\n",
                 prop.name, cus, clk_hz / 1e6, add32, add16, perm_add, add32 / cus / clk_hz, add16 / cus / clk_hz,
                 lds_bw(t_l4, 4), lds_bw(t_l8, 8), lds_bw(t_l16, 16), lds_bw(t_l16, 16) / cus / clk_hz,
-                lds_bw(t_l4, 4) / cus / clk_hz, v3_rate[0], v3_rate[1], v3_rate[2], copy_bw);
+                lds_bw(t_l4, 4) / cus / clk_hz, v3_rate[0], v3_rate[1], v3_rate[2],
+                lds_clk(t_l4, waves * lit * 8), lds_clk(t_l8, waves * lit * 8), lds_clk(t_l16, waves * lit * 8),
+                lds_clk(t_s9, waves * lit * 4 * 5), lds_clk(t_ua, waves * uit * 4), n_wrong, copy_bw);
     CHECK(hipFree(src));
     CHECK(hipFree(dst));
     CHECK(hipFree(in));
