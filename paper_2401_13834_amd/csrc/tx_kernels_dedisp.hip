@@ -64,6 +64,14 @@ __device__ __forceinline__ int block_max(int v, int* red) {
     return v;
 }
 
+// A wavefront's own LDS span: its LDS operations complete in order, so its
+// later reads see its earlier writes; the fence keeps the compiler from moving
+// them across each other.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // ---------------------------------------------------------------------------
 // Stage 1: B[j][s][u] = sum over ch in s of x[ch][u + D(c_j, f_ch)].
 //
@@ -260,7 +268,7 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
             const uint32_t w23 = perm_b32(odd[jj][q], even, 0x07060302u);
             *reinterpret_cast<uint2*>(wb + 8 * (Q * lane + q)) = make_uint2(w01, w23);
         }
-        __syncthreads();
+        wave_lds_sync();
         if (j <= jl) {
             TX_GLOBAL uint16_t* out = to_global(a.B) + (static_cast<size_t>(j) * a.nsub + s) * a.B_pitch + u0;
 #pragma unroll
@@ -268,7 +276,7 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
                 *reinterpret_cast<TX_GLOBAL uint2*>(out + 4 * (lane + 64 * q)) =
                     *reinterpret_cast<const uint2*>(wb + 8 * (lane + 64 * q));
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 
@@ -481,7 +489,7 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
         if (Q > 1) {
 #pragma unroll
             for (int q = 0; q < Q; ++q) *reinterpret_cast<uint2*>(wb + 8 * (Q * lane + q)) = make_uint2(lo[ii][q], hi[ii][q]);
-            __syncthreads();
+            wave_lds_sync();
         }
         if (ii < ni) {
             TX_GLOBAL int32_t* out = to_global(a.Y) + static_cast<size_t>(i0 + ii) * a.y_pitch;
@@ -498,7 +506,7 @@ __device__ __forceinline__ void stage2_tile(const Stage2Args& a, int tile, uint8
                 }
             }
         }
-        if (Q > 1) __syncthreads();
+        if (Q > 1) wave_lds_sync();
     }
 }
 
