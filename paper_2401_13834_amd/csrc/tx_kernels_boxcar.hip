@@ -287,8 +287,8 @@ __device__ __forceinline__ void cand_tile(const BoxcarArgs& a, BoxShared<NWT>& s
 // Widths and 1/sqrt(w) of the row's job into LDS, the wavefronts' per-width
 // best cleared, and the per-(tile, width) maxima table reset.
 template <int NWT>
-__device__ __forceinline__ void row_setup(const BoxcarArgs& a, int ntiles, bool keep_tmax, BoxShared<NWT>& sh) {
-    const int tid = threadIdx.x;
+__device__ __forceinline__ void row_setup(const BoxcarArgs& a, int ntiles, bool keep_tmax, BoxShared<NWT>& sh,
+                                          int tid) {
     const int lane = tid & 63;
     const int wave = tid >> 6;
     if (tid < NWT) {
@@ -320,8 +320,8 @@ __device__ __forceinline__ void row_setup(const BoxcarArgs& a, int ntiles, bool 
 // per-(tile, width) maxima.
 template <int NWT>
 __device__ __forceinline__ void row_scan(const BoxcarArgs& a, int tlo, int thi, bool keep_tmax,
-                                         const TX_GLOBAL int32_t* __restrict__ y, bool vec, BoxShared<NWT>& sh) {
-    const int tid = threadIdx.x;
+                                         const TX_GLOBAL int32_t* __restrict__ y, bool vec, BoxShared<NWT>& sh,
+                                         int tid) {
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int T = a.nt;
@@ -356,8 +356,8 @@ __device__ __forceinline__ void row_scan(const BoxcarArgs& a, int tlo, int thi, 
 // row_scan left in LDS.
 template <int NWT>
 __device__ __forceinline__ void row_finish(const BoxcarArgs& a, int row, int ntiles, bool keep_tmax,
-                                           const TX_GLOBAL int32_t* __restrict__ y, bool vec, BoxShared<NWT>& sh) {
-    const int tid = threadIdx.x;
+                                           const TX_GLOBAL int32_t* __restrict__ y, bool vec, BoxShared<NWT>& sh,
+                                           int tid) {
     const int T = a.nt;
     const int L = kBoxTile + a.wmax;
     if (tid == 0) {
@@ -472,14 +472,14 @@ __device__ __forceinline__ void row_finish(const BoxcarArgs& a, int row, int nti
 
 
 template <int NWT>
-__device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh) {
+__device__ __forceinline__ void boxcar_row(const BoxcarArgs& a, int row, BoxShared<NWT>& sh, int tid) {
     const TX_GLOBAL int32_t* __restrict__ y = to_global(a.y) + static_cast<size_t>(row) * a.pitch;
     const bool vec = ((reinterpret_cast<uintptr_t>(a.y) + static_cast<uintptr_t>(row) * a.pitch * 4) & 15) == 0;
     const int ntiles = (a.nt + kBoxTile - 1) / kBoxTile;
     const bool keep_tmax = a.tmax_ok != 0;
-    row_setup<NWT>(a, ntiles, keep_tmax, sh);
-    row_scan<NWT>(a, 0, ntiles, keep_tmax, y, vec, sh);
-    row_finish<NWT>(a, row, ntiles, keep_tmax, y, vec, sh);
+    row_setup<NWT>(a, ntiles, keep_tmax, sh, tid);
+    row_scan<NWT>(a, 0, ntiles, keep_tmax, y, vec, sh, tid);
+    row_finish<NWT>(a, row, ntiles, keep_tmax, y, vec, sh, tid);
 }
 
 // Single job: one workgroup per row.
@@ -490,7 +490,7 @@ template <int NWT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void boxcar_kernel(BoxcarArgs a) {
     __shared__ BoxShared<NWT> sh;
     const int row = static_cast<int>(blockIdx.x);        // grid = rows
-    if (row < a.ndm) boxcar_row<NWT>(a, row, sh);
+    if (row < a.ndm) boxcar_row<NWT>(a, row, sh, static_cast<int>(threadIdx.x));
 }
 
 __device__ __forceinline__ int find_row_job(const int* __restrict__ prefix, int njobs, int v) {
@@ -515,7 +515,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
     const int* prefix = prefix_base + info[2];
     for_each_claimed(prefix[njobs], queue, [&](int v) {
         const int jb = find_row_job(prefix, njobs, v);
-        boxcar_row<NWT>(cj[jb], v - prefix[jb], sh);
+        // The thread index, opaque to the compiler in every row: else it
+        // keeps lane-dependent values of the row body live across rows.
+        int tv = static_cast<int>(threadIdx.x);
+        asm volatile("" : "+v"(tv));
+        boxcar_row<NWT>(cj[jb], v - prefix[jb], sh, tv);
     });
 }
 
