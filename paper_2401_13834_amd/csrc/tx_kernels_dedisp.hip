@@ -175,10 +175,24 @@ __device__ __forceinline__ void stage1_tile(const Stage1Args& a, int tile, uint8
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<uint8_t*>(row), static_cast<short>(0), nb & ~15, kRawBufferWord3);
             uint8_t* dst = dat + c * rowbytes;
-            for (int k = 0; 256 * k < W; ++k) {
-                const int i = lane + 64 * k;     // 16-byte piece of the row
+            // Piece i = lane + 64 k of the row.  Whole spans of 64 pieces, then
+            // the last partial span; the straddling piece is skipped only where
+            // the row has one (uniform branch).
+            const int kfull = W >> 8;
+            if (part < 0) {
+                for (int k = 0; k < kfull; ++k)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, to_lds(dst + 1024 * k), 16, 16 * lane + 1024 * k, 0,
+                                                             0, 0);
+            } else {
+                for (int k = 0; k < kfull; ++k)
+                    if (lane + 64 * k != part)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, to_lds(dst + 1024 * k), 16, 16 * lane + 1024 * k,
+                                                                 0, 0, 0);
+            }
+            {
+                const int i = lane + 64 * kfull;
                 if (4 * i < W && i != part)
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, to_lds(dst + 1024 * k), 16, 16 * i, 0, 0, 0);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, to_lds(dst + 1024 * kfull), 16, 16 * i, 0, 0, 0);
             }
             if (part >= 0 && (part & 63) == lane) {
                 const TX_GLOBAL uint8_t* src = to_global(row) + 16 * part;
