@@ -548,8 +548,14 @@ __global__ __launch_bounds__(kThreads) void stage1_kernel(Stage1Args a) {
     stage1_tile<Q, JW>(a, xcd_tile(blockIdx.x, a.nsub * a.n_ttiles * a.n_jchunks), lds, red, threadIdx.x);
 }
 
+// The batch form of the first stage is held to 5 waves per SIMD (102 VGPRs):
+// left alone the persistent loop's larger function is scheduled for 4 in most
+// variants (9 x 2: 110 VGPRs, 85 when held).  The 9 x 4 variant is left
+// alone: held, it spills 11 dwords and runs slower.
+#define TX_S1B_WAVES(Q, JW) __attribute__((amdgpu_waves_per_eu((Q) == 9 && (JW) == 4 ? 1 : 5)))
+
 template <int Q, int JW>
-__global__ __launch_bounds__(kThreads) void stage1_batch_kernel(const Stage1Args* __restrict__ jobs,
+__global__ __launch_bounds__(kThreads) TX_S1B_WAVES(Q, JW) void stage1_batch_kernel(const Stage1Args* __restrict__ jobs,
                                                                 const int* __restrict__ prefix_base,
                                                                 const int* __restrict__ info, uint32_t* queue) {
     extern __shared__ __align__(16) uint8_t lds[];
