@@ -365,6 +365,7 @@ def batched_leg(torch, tx, synth, steps, tune_effort=0, tune=True):
                 batch.launch(stream)
             ev1.record(stream)
             batch.wait()
+            ev1.synchronize()                      # recorded after the batch's own completion event
             t_batch = ev0.elapsed_time(ev1) * 1e-3 / steps
 
             def plain_round():
