@@ -54,6 +54,47 @@ __device__ __forceinline__ void for_each_claimed(int total, uint32_t* queue, F&&
         }
     }
 }
+
+namespace tx {
+
+__device__ __forceinline__ uint32_t align_b32(uint32_t hi, uint32_t lo, uint32_t nbytes) {
+    return __builtin_amdgcn_alignbyte(hi, lo, nbytes);
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// s_waitcnt operand for "vector memory count 0", other counters untouched
+// (vmcnt bits 3:0 and 15:14 zero, expcnt 6:4 = 7, lgkmcnt 11:8 = 15).
+constexpr int kWaitVm0 = 0x0F70;
+
+// Word 3 of a raw (stride 0) buffer resource on gfx9-family parts: 32-bit
+// data format, no swizzle, no thread-id offset.
+constexpr int kRawBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ __attribute__((address_space(3))) void* to_lds(uint8_t* p) {
+    return (__attribute__((address_space(3))) void*)(p);
+}
+
+// Consecutive workgroup ids are dealt round-robin to the 8 XCDs; give each XCD
+// a contiguous range of tiles so that tiles sharing input rows share an L2.
+__device__ __forceinline__ int xcd_tile(int bid, int total) {
+    const int nx = 8;
+    const int x = bid % nx, k = bid / nx;
+    const int q = total / nx, r = total % nx;
+    return x * q + min(x, r) + k;
+}
+
+// Largest v over a workgroup of 256 threads (red: 4 ints of LDS).
+__device__ __forceinline__ int block_max(int v, int* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    v = max(max(red[0], red[1]), max(red[2], red[3]));
+    __syncthreads();
+    return v;
+}
+
+}  // namespace tx
 #endif
 
 namespace tx {
@@ -132,13 +173,13 @@ struct BoxcarArgs {
 };
 
 // Dedispersion of normalised data and the float matched filter
-// (tx_kernels_norm.hip).  Stage 1: workgroups of kNormJ coarse trials and
-// kNormTT1 outputs (8 per lane); stage 2: kNormIW fine trials and kNormTT2
-// outputs (4 per lane).
-constexpr int kNormJ = 4;
-constexpr int kNormTT1 = 2048;
+// (tx_kernels_norm.hip).  Stage 1: workgroups of 4 kNormJW coarse trials and
+// 256 kNormQ outputs (4 kNormQ per lane); stage 2: kNormIW fine trials and
+// kNormTT2 outputs (3 per lane).
+constexpr int kNormJW = 2;                 // stage 1: coarse trials per wave (8 per workgroup)
+constexpr int kNormQ = 5;                  // stage 1: output dwords per lane (20 outputs; odd)
 constexpr int kNormIW = 16;
-constexpr int kNormTT2 = 1024;
+constexpr int kNormTT2 = 768;
 constexpr int kNormLds = 32 * 1024;
 
 struct Stage1NormArgs {

@@ -22,18 +22,6 @@ namespace tx {
 __device__ __forceinline__ uint32_t perm_b32(uint32_t hi, uint32_t lo, uint32_t sel) {
     return __builtin_amdgcn_perm(hi, lo, sel);
 }
-__device__ __forceinline__ uint32_t align_b32(uint32_t hi, uint32_t lo, uint32_t nbytes) {
-    return __builtin_amdgcn_alignbyte(hi, lo, nbytes);
-}
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// s_waitcnt operand for "vector memory count 0", other counters untouched
-// (vmcnt bits 3:0 and 15:14 zero, expcnt 6:4 = 7, lgkmcnt 11:8 = 15).
-constexpr int kWaitVm0 = 0x0F70;
-
-// Word 3 of a raw (stride 0) buffer resource on gfx9-family parts: 32-bit
-// data format, no swizzle, no thread-id offset.
-constexpr int kRawBufferWord3 = 0x00020000;
 
 __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
     const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint64_t>(v)), l);
@@ -41,28 +29,7 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
     return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
-__device__ __forceinline__ __attribute__((address_space(3))) void* to_lds(uint8_t* p) {
-    return (__attribute__((address_space(3))) void*)(p);
-}
 
-// Consecutive workgroup ids are dealt round-robin to the 8 XCDs; give each XCD
-// a contiguous range of tiles so that tiles sharing input rows share an L2.
-__device__ __forceinline__ int xcd_tile(int bid, int total) {
-    const int nx = 8;
-    const int x = bid % nx, k = bid / nx;
-    const int q = total / nx, r = total % nx;
-    return x * q + min(x, r) + k;
-}
-
-__device__ __forceinline__ int block_max(int v, int* red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    v = max(max(red[0], red[1]), max(red[2], red[3]));
-    __syncthreads();
-    return v;
-}
 
 // A wavefront's own LDS span: its LDS operations complete in order, so its
 // later reads see its earlier writes; the fence keeps the compiler from moving

@@ -27,35 +27,30 @@ namespace tx {
 
 namespace {
 
-__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ int block_max_i(int v, int* red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    v = max(max(red[0], red[1]), max(red[2], red[3]));
-    __syncthreads();
-    return v;
-}
-
 // Byte k of w as a float (one v_cvt_f32_ubyteN).
 __device__ __forceinline__ float byte_f(uint32_t w, int k) { return static_cast<float>((w >> (8 * k)) & 0xFFu); }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Stage 1.  Workgroup = (sub-band s, kNormJ coarse trials, kNormTT1 outputs):
-// the 4 wavefronts split the time tile, lane l of wave w owns the 8
-// consecutive outputs 8 (64 w + l) ..; every lane accumulates all the
-// workgroup's trials.  Channel rows are staged, a round of rows at a time, as
-// bytes from the first trial's shift rounded down to 16 bytes.
+// Stage 1.  Workgroup = (sub-band s, J = 4 kNormJW coarse trials, TT =
+// 256 kNormQ outputs): wave w owns trials j0 + w kNormJW .. and lane l the
+// 4 kNormQ consecutive outputs from 4 kNormQ l.  A lane reads the kNormQ + 1
+// input dwords of a (channel, trial) as paired 4-byte reads from one base
+// (kNormQ odd: the lanes' addresses fall in distinct banks) and takes each
+// output dword's 4 bytes with one byte align.  Channel rows are staged as
+// bytes, from the first trial's shift rounded down to 16 bytes, by buffer
+// loads straight into LDS (range-checked: zeros past a row's valid bytes),
+// double-buffered where two rounds of rows fit.  A per-(channel, trial)
+// table at the top of LDS holds each shift from the staging start.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void stage1_norm_kernel(Stage1NormArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
-    constexpr int J = kNormJ;
-    constexpr int TT = kNormTT1;
-    const int tile = static_cast<int>(blockIdx.x);
+    constexpr int Q = kNormQ;
+    constexpr int JW = kNormJW;
+    constexpr int J = JW * kWaves;
+    constexpr int TT = 256 * Q;
+    const int tile = xcd_tile(static_cast<int>(blockIdx.x), a.nsub * a.n_ttiles * a.n_jchunks);
     const int jc = tile % a.n_jchunks;
     const int rest = tile / a.n_jchunks;
     const int tt = rest % a.n_ttiles;
@@ -64,6 +59,8 @@ __global__ __launch_bounds__(kThreads) void stage1_norm_kernel(Stage1NormArgs a)
     const int jl = min(j0 + J, a.ngroups) - 1;
     const int u0 = tt * TT;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = uniform(tid >> 6);
     const int ch0 = s * a.m;
     const TX_GLOBAL int32_t* __restrict__ dT = to_global(a.dT);
     const size_t gp = static_cast<size_t>(a.gpad);
@@ -74,94 +71,137 @@ __global__ __launch_bounds__(kThreads) void stage1_norm_kernel(Stage1NormArgs a)
         const TX_GLOBAL int32_t* r = dT + static_cast<size_t>(ch0 + c) * gp;
         sp = max(sp, r[jl] - (r[j0] & ~15));
     }
-    sp = uniform_i(block_max_i(sp, red));
-    const int rowbytes = (sp + TT + 4 + 15) & ~15;        // staged bytes per row (one dword past the last output)
+    sp = uniform(block_max(sp, red));
+    const int W = ((sp >> 2) + 64 * Q + 1 + 3) & ~3;      // dwords per staged row
+    const int rowbytes = 4 * W;
 
     // Tables at the top of LDS: per (channel, trial) the shift from the
-    // channel's staging start; per channel its start.
-    const int tab_off = (a.lds_bytes - ((a.m * (J + 1) * 4 + 15) & ~15)) & ~15;
-    int32_t* tab = reinterpret_cast<int32_t*>(lds + tab_off);   // [m][J]
+    // channel's staging start; per channel its start, scale and -offset.
+    const int fix_off = (a.lds_bytes - ((a.m * (J + 3) * 4 + 15) & ~15)) & ~15;
+    int32_t* tab = reinterpret_cast<int32_t*>(lds + fix_off);   // [m][J]
     int32_t* st0 = tab + a.m * J;                                 // [m]
+    float* wsc = reinterpret_cast<float*>(st0 + a.m);             // [m]
+    float* wof = wsc + a.m;                                       // [m]
     for (int t = tid; t < a.m * J; t += kThreads) {
         const int c = t / J, k = t - c * J;
         const TX_GLOBAL int32_t* r = dT + static_cast<size_t>(ch0 + c) * gp;
         tab[t] = r[min(j0 + k, jl)] - (r[j0] & ~15);
     }
-    for (int c = tid; c < a.m; c += kThreads) st0[c] = dT[static_cast<size_t>(ch0 + c) * gp + j0] & ~15;
-    const int nch = max(1, min(a.m, tab_off / rowbytes));
+    for (int c = tid; c < a.m; c += kThreads) {
+        st0[c] = dT[static_cast<size_t>(ch0 + c) * gp + j0] & ~15;
+        wsc[c] = to_global(a.scale)[ch0 + c];
+        wof[c] = -to_global(a.offset)[ch0 + c];
+    }
+    const int nbuf = 2 * rowbytes <= fix_off ? 2 : 1;
+    const int nch = max(1, min(a.m, fix_off / nbuf / rowbytes));
+    const int buf_bytes = nch * rowbytes;
     __syncthreads();
 
-    float acc[J][8];
-#pragma unroll
-    for (int k = 0; k < J; ++k)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[k][q] = 0.0f;
-    const int ob = 8 * tid;                                       // this lane's first output
-    const TX_GLOBAL float* __restrict__ scale = to_global(a.scale);
-    const TX_GLOBAL float* __restrict__ offset = to_global(a.offset);
-
-    for (int cb = 0; cb < a.m; cb += nch) {
+    // Rows of channels [cb, cb + nch) into `dat`: wave w stages rows w, w + 4,
+    // ..., whole 16-byte pieces through a raw buffer resource sized to the
+    // row's whole valid pieces (zeros past them); the piece that straddles the
+    // row's end, if any, byte by byte.
+    auto stage = [&](int cb, uint8_t* dat) {
         const int nc = min(nch, a.m - cb);
-        // Stage rows [cb, cb + nc): 16-byte pieces where the whole piece is
-        // valid, byte by byte at the row's end; zeros past it.
-        for (int idx = tid; idx < nc * (rowbytes >> 4); idx += kThreads) {
-            const int c = idx / (rowbytes >> 4), piece = idx - c * (rowbytes >> 4);
-            const int64_t start = static_cast<int64_t>(u0) + st0[cb + c] + 16 * piece;
-            const TX_GLOBAL uint8_t* row = to_global(a.x) + static_cast<size_t>(ch0 + cb + c) * a.x_pitch;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (start + 16 <= a.x_len) {
-                v = *reinterpret_cast<const TX_GLOBAL uint4*>(row + start);
-            } else if (start < a.x_len) {
-                uint32_t d[4] = {0u, 0u, 0u, 0u};
-                for (int b = 0; b < static_cast<int>(a.x_len - start); ++b)
-                    d[b >> 2] |= static_cast<uint32_t>(row[start + b]) << (8 * (b & 3));
-                v = make_uint4(d[0], d[1], d[2], d[3]);
+        for (int c = wave; c < nc; c += kWaves) {
+            const int64_t start = static_cast<int64_t>(u0) + uniform(st0[cb + c]);
+            int64_t nb64 = a.x_len - start;                     // valid bytes of the staged row
+            nb64 = nb64 < 0 ? 0 : (nb64 > rowbytes ? rowbytes : nb64);
+            const int nb = uniform(static_cast<int>(nb64));
+            const int part = (nb & 15) ? nb >> 4 : -1;
+            const uint8_t* row = a.x + static_cast<size_t>(ch0 + cb + c) * a.x_pitch + start;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint8_t*>(row), static_cast<short>(0), nb & ~15, kRawBufferWord3);
+            uint8_t* dst = dat + c * rowbytes;
+            const int kfull = W >> 8;
+            for (int k = 0; k < kfull; ++k)
+                if (lane + 64 * k != part)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, to_lds(dst + 1024 * k), 16, 16 * lane + 1024 * k, 0,
+                                                             0, 0);
+            {
+                const int i = lane + 64 * kfull;
+                if (4 * i < W && i != part)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, to_lds(dst + 1024 * kfull), 16, 16 * i, 0, 0, 0);
             }
-            *reinterpret_cast<uint4*>(lds + c * rowbytes + 16 * piece) = v;
+            if (part >= 0 && (part & 63) == lane) {
+                const TX_GLOBAL uint8_t* src = to_global(row) + 16 * part;
+                uint32_t d[4] = {0u, 0u, 0u, 0u};
+                for (int b = 0; b < (nb & 15); ++b) d[b >> 2] |= static_cast<uint32_t>(src[b]) << (8 * (b & 3));
+                *reinterpret_cast<uint4*>(dst + 16 * part) = make_uint4(d[0], d[1], d[2], d[3]);
+            }
         }
-        __syncthreads();
-        for (int c = 0; c < nc; ++c) {
-            const float sc = scale[ch0 + cb + c];
-            const float of = -offset[ch0 + cb + c];
-            const uint8_t* row = lds + c * rowbytes;
+    };
+
+    float acc[JW][4 * Q];
 #pragma unroll
-            for (int k = 0; k < J; ++k) {
-                const int e = uniform_i(tab[(cb + c) * J + k]) + ob;   // byte of output ob for trial k
-                const uint32_t* p = reinterpret_cast<const uint32_t*>(row + (e & ~3));
-                const uint32_t sh = static_cast<uint32_t>(e & 3);
-                const uint32_t w0 = p[0], w1 = p[1], w2 = p[2];
-                const uint32_t a0 = __builtin_amdgcn_alignbyte(w1, w0, sh);
-                const uint32_t a1 = __builtin_amdgcn_alignbyte(w2, w1, sh);
+    for (int jj = 0; jj < JW; ++jj)
+#pragma unroll
+        for (int q = 0; q < 4 * Q; ++q) acc[jj][q] = 0.0f;
+    const int lane_b = 4 * Q * lane;                               // byte offset of the lane's first dword
+
+    stage(0, lds);
+    for (int cb = 0, r = 0; cb < a.m; cb += nch, ++r) {
+        const int nc = min(nch, a.m - cb);
+        const uint8_t* dat = lds + (r & (nbuf - 1)) * buf_bytes;
+        // This wave's rows of the round have landed; after the barrier every
+        // wave's have, and nobody still reads the other buffer.
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        __syncthreads();
+        if (nbuf == 2 && cb + nch < a.m) stage(cb + nch, lds + ((r + 1) & 1) * buf_bytes);
+        const int32_t* tw = tab + cb * J + wave * JW;
+        for (int c = 0; c < nc; ++c) {
+            const float sc = wsc[cb + c];                          // one address: a broadcast read
+            const float of = wof[cb + c];
+#pragma unroll
+            for (int jj = 0; jj < JW; ++jj) {
+                const int e = uniform(tw[c * J + jj]) + c * rowbytes;
+                const uint32_t k = static_cast<uint32_t>(e & 3);
+                const uint32_t* p = reinterpret_cast<const uint32_t*>(dat + (e & ~3) + lane_b);
+                uint32_t w[Q + 1];
+#pragma unroll
+                for (int q = 0; q <= Q; ++q) w[q] = p[q];
                 // the channel's normalised sample, rounded once, then added
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    acc[k][q] += __builtin_fmaf(byte_f(a0, q), sc, of);
-                    acc[k][q + 4] += __builtin_fmaf(byte_f(a1, q), sc, of);
+                for (int q = 0; q < Q; ++q) {
+                    const uint32_t v = align_b32(w[q + 1], w[q], k);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[jj][4 * q + b] += __builtin_fmaf(byte_f(v, b), sc, of);
                 }
             }
         }
-        __syncthreads();
+        if (nbuf == 1 && cb + nch < a.m) {
+            __syncthreads();
+            stage(cb + nch, lds);
+        }
     }
-    for (int k = 0; k < J; ++k) {
-        const int j = j0 + k;
-        if (j > jl) break;
-        TX_GLOBAL float* out = to_global(a.B) + (static_cast<size_t>(j) * a.nsub + s) * a.B_pitch + u0 + ob;
-        *reinterpret_cast<TX_GLOBAL float4*>(out) = make_float4(acc[k][0], acc[k][1], acc[k][2], acc[k][3]);
-        *reinterpret_cast<TX_GLOBAL float4*>(out + 4) = make_float4(acc[k][4], acc[k][5], acc[k][6], acc[k][7]);
+#pragma unroll
+    for (int jj = 0; jj < JW; ++jj) {
+        const int j = j0 + wave * JW + jj;
+        if (j <= jl) {
+            TX_GLOBAL float* out = to_global(a.B) + (static_cast<size_t>(j) * a.nsub + s) * a.B_pitch + u0 + 4 * Q * lane;
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                *reinterpret_cast<TX_GLOBAL float4*>(out + 4 * q) =
+                    make_float4(acc[jj][4 * q], acc[jj][4 * q + 1], acc[jj][4 * q + 2], acc[jj][4 * q + 3]);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Stage 2.  Workgroup = (group j, up to kNormIW of its trials, kNormTT2
-// outputs); lane tid owns the outputs t0 + tid + 256 k (k < 4), so every LDS
-// read of a trial is 64 consecutive floats of one row (no bank conflicts at
-// any shift).  Sub-band rows are staged a round at a time.
+// Stage 2.  Workgroup = (group j, up to kNormIW of its trials, TT = 768
+// outputs): lane l of wave w owns the 3 consecutive outputs from
+// 3 (64 w + l), so its words of a (sub-band, trial) are one paired and one
+// single 4-byte read from one base (3 is odd: the lanes' addresses fall in
+// distinct banks).  Sub-band rows are staged, a round at a time, as floats
+// from the first trial's shift rounded down to 4 floats, with loads straight
+// into LDS (16-byte pieces), double-buffered where two rounds fit; every
+// output adds its sub-bands in order.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void stage2_norm_kernel(Stage2NormArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     constexpr int IW = kNormIW;
     constexpr int TT = kNormTT2;
-    const int tile = static_cast<int>(blockIdx.x);
+    const int tile = xcd_tile(static_cast<int>(blockIdx.x), a.ngroups * a.n_ichunks * a.n_ttiles);
     const int ic = tile % a.n_ichunks;
     const int rest = tile / a.n_ichunks;
     const int tt = rest % a.n_ttiles;
@@ -173,6 +213,8 @@ __global__ __launch_bounds__(kThreads) void stage2_norm_kernel(Stage2NormArgs a)
     const int il = i0 + ni - 1;
     const int t0 = tt * TT;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = uniform(tid >> 6);
     const TX_GLOBAL int32_t* __restrict__ rT = to_global(a.rT);
     const size_t dp = static_cast<size_t>(a.dpad);
     int* red = reinterpret_cast<int*>(lds);
@@ -182,7 +224,7 @@ __global__ __launch_bounds__(kThreads) void stage2_norm_kernel(Stage2NormArgs a)
         const TX_GLOBAL int32_t* r = rT + static_cast<size_t>(s) * dp;
         sp = max(sp, r[il] - (r[i0] & ~3));
     }
-    sp = uniform_i(block_max_i(sp, red));
+    sp = uniform(block_max(sp, red));
     const int rowf = (sp + TT + 3) & ~3;                  // staged floats per row
     const int tab_off = (a.lds_bytes - ((IW * a.nsub * 4 + 15) & ~15)) & ~15;
     int32_t* tab = reinterpret_cast<int32_t*>(lds + tab_off);   // [nsub][IW]: shift from the staged start
@@ -191,43 +233,68 @@ __global__ __launch_bounds__(kThreads) void stage2_norm_kernel(Stage2NormArgs a)
         const TX_GLOBAL int32_t* r = rT + static_cast<size_t>(s) * dp;
         tab[t] = r[i0 + min(k, ni - 1)] - (r[i0] & ~3);
     }
-    const int nsb = max(1, min(a.nsub, tab_off / (rowf * 4)));
+    const int rowb = 4 * rowf;
+    const int nbuf = 2 * 4 * rowb <= tab_off ? 2 : 1;     // two rounds of at least 4 rows, or one buffer
+    const int nsb = max(1, min(a.nsub, tab_off / (nbuf * rowb)));
+    const int buf_bytes = nsb * rowb;
     __syncthreads();
 
-    float acc[IW][4];
+    const TX_GLOBAL float* Bj = to_global(a.B) + static_cast<size_t>(j) * a.nsub * a.B_pitch;
+    // Rows [sb, sb + nsb) into `dat`: wave w stages rows w, w + 4, ...
+    auto stage = [&](int sb, uint8_t* dat) {
+        const int ns = min(nsb, a.nsub - sb);
+        for (int r = wave; r < ns; r += kWaves) {
+            const int s = sb + r;
+            const TX_GLOBAL float* src = Bj + static_cast<size_t>(s) * a.B_pitch + t0 + (rT[static_cast<size_t>(s) * dp + i0] & ~3);
+            uint8_t* dst = dat + r * rowb;
+            for (int k = 0; 256 * k < rowf; ++k) {
+                const int i = lane + 64 * k;              // 16-byte piece (4 floats) of the row
+                if (4 * i < rowf)
+                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const TX_GLOBAL void*>(src + 4 * i),
+                                                     to_lds(dst + 1024 * k), 16, 0, 0);
+            }
+        }
+    };
+
+    float acc[IW][3];
 #pragma unroll
     for (int k = 0; k < IW; ++k)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[k][q] = 0.0f;
-    const TX_GLOBAL float* Bj = to_global(a.B) + static_cast<size_t>(j) * a.nsub * a.B_pitch;
-    float* rows = reinterpret_cast<float*>(lds);
-    for (int sb = 0; sb < a.nsub; sb += nsb) {
+        for (int q = 0; q < 3; ++q) acc[k][q] = 0.0f;
+    const int lo = 3 * (64 * wave + lane);                         // the lane's first output
+    stage(0, lds);
+    for (int sb = 0, rd = 0; sb < a.nsub; sb += nsb, ++rd) {
         const int ns = min(nsb, a.nsub - sb);
-        for (int idx = tid; idx < ns * (rowf >> 2); idx += kThreads) {
-            const int r = idx / (rowf >> 2), piece = idx - r * (rowf >> 2);
-            const int s = sb + r;
-            const TX_GLOBAL float* src = Bj + static_cast<size_t>(s) * a.B_pitch + t0 + (rT[static_cast<size_t>(s) * dp + i0] & ~3);
-            *reinterpret_cast<float4*>(rows + r * rowf + 4 * piece) =
-                *reinterpret_cast<const TX_GLOBAL float4*>(src + 4 * piece);
-        }
+        const float* rows = reinterpret_cast<const float*>(lds + (rd & (nbuf - 1)) * buf_bytes);
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
         __syncthreads();
+        if (nbuf == 2 && sb + nsb < a.nsub) stage(sb + nsb, lds + ((rd + 1) & 1) * buf_bytes);
         for (int r = 0; r < ns; ++r) {
-            const float* row = rows + r * rowf + tid;
+            const float* row = rows + r * rowf + lo;
 #pragma unroll
-            for (int k = 0; k < IW; ++k) {
-                const int e = uniform_i(tab[(sb + r) * IW + k]);
+            for (int k0 = 0; k0 < IW; k0 += 4) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[k][q] += row[e + 256 * q];
+                for (int k = k0; k < k0 + 4; ++k) {
+                    const float* p = row + uniform(tab[(sb + r) * IW + k]);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) acc[k][q] += p[q];
+                }
+                // a group of 4 trials' reads at a time (registers)
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
-        __syncthreads();
+        if (nbuf == 1 && sb + nsb < a.nsub) {
+            __syncthreads();
+            stage(sb + nsb, lds);
+        }
     }
-    for (int k = 0; k < ni; ++k) {
-        TX_GLOBAL float* out = to_global(a.Y) + static_cast<size_t>(i0 + k) * a.y_pitch;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t t = t0 + tid + 256 * q;
-            if (t < a.nt) out[t] = acc[k][q];
+    for (int k = 0; k < IW; ++k) {                      // compile-time indices: acc stays in registers
+        if (k < ni) {
+            TX_GLOBAL float* out = to_global(a.Y) + static_cast<size_t>(i0 + k) * a.y_pitch + t0 + lo;
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (t0 + lo + q < a.nt) out[q] = acc[k][q];
         }
     }
 }
@@ -457,17 +524,18 @@ NormGeom norm_geometry(const tx_plan_s* p, int64_t nt) {
     NormGeom g{};
     g.n_ttiles2 = static_cast<int32_t>((nt + kNormTT2 - 1) / kNormTT2);
     g.n_ichunks = (p->g + kNormIW - 1) / kNormIW;
-    g.n_jchunks = (p->ngroups + kNormJ - 1) / kNormJ;
+    g.n_jchunks = (p->ngroups + 4 * kNormJW - 1) / (4 * kNormJW);
     // stage 2 stages floats [start, start + rowf) of a series, start <= last
     // tile start + max extent; rowf <= spread + TT + 3
     const int sp2 = plan_spread2(p, kNormIW) + 3;
     const int64_t need = static_cast<int64_t>(std::max(g.n_ttiles2 - 1, 0)) * kNormTT2 + p->max_extent + sp2 + kNormTT2 + 4;
-    g.B_pitch = (std::max<int64_t>(need, nt + p->max_extent) + kNormTT1 - 1) / kNormTT1 * kNormTT1;
-    g.n_ttiles1 = static_cast<int32_t>(g.B_pitch / kNormTT1);
+    const int tt1 = 256 * kNormQ;
+    g.B_pitch = (std::max<int64_t>(need, nt + p->max_extent) + tt1 - 1) / tt1 * tt1;
+    g.n_ttiles1 = static_cast<int32_t>(g.B_pitch / tt1);
     g.ws_bytes = (static_cast<int64_t>(p->ngroups) * p->nsub * g.B_pitch * 4 + 255) / 256 * 256;
-    const int sp1 = plan_spread1(p, kNormJ) + 15;
-    const int row1 = (sp1 + kNormTT1 + 4 + 15) & ~15;
-    g.lds1 = std::max(kNormLds, row1 + ((p->m * (kNormJ + 1) * 4 + 15) & ~15) + 64);
+    const int sp1 = plan_spread1(p, 4 * kNormJW) + 15;
+    const int row1 = 4 * (((sp1 >> 2) + 64 * kNormQ + 1 + 3) & ~3);   // a staged row (as the kernel sizes it)
+    g.lds1 = std::max(kNormLds, row1 + ((p->m * (4 * kNormJW + 3) * 4 + 15) & ~15) + 64);
     const int row2 = ((sp2 + kNormTT2 + 3) & ~3) * 4;
     g.lds2 = std::max(kNormLds, row2 + ((kNormIW * p->nsub * 4 + 15) & ~15) + 64);
     g.ok = g.lds1 <= device_max_lds() && g.lds2 <= device_max_lds();
