@@ -499,8 +499,10 @@ tx_status tx_candidates(const int32_t* d_dmt, int32_t ndm, int64_t nt, int64_t p
  * a float32 DM x time array (Sec. 2.4 Eq. 5, Sec. 2.5), evaluated in float64:
  * per row the mean and population variance S2/T - (S1/T)^2 of its T values;
  * the window [t, t+w) inside the row has sum S (float64 running sums) and
- * snr = ((S - w * mean) / sigma) / sqrt(w).  Per width the earliest start of
- * the largest S/N, across widths the largest (ties to the smaller width); a
+ * snr = ((S - w * mean) / sigma) / sqrt(w).  Per width the largest S/N, at
+ * the earliest start of the largest window sum (the S/N never decreases with
+ * the sum; where two different sums round to the same S/N the start may be
+ * the later one), across widths the largest (ties to the smaller width); a
  * row of zero variance gives (0.0, widths[0], 0) and no candidates.  Other
  * arguments, limits and errors as the integer calls (no value-range flag).
  */

@@ -224,6 +224,7 @@ struct BoxcarNormArgs {
     int32_t want_peaks;
     int32_t want_cands;
     int32_t fixed;          // 1: use fixed_mean / fixed_sigma instead of the row's statistics
+    int32_t tmax_ok;        // the per-(tile, width) table fits the launch's dynamic LDS (set by the launcher)
     double fixed_mean, fixed_sigma;
     double* snr;
     int32_t* width;

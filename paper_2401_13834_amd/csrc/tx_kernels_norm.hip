@@ -11,12 +11,11 @@
 // coarse trials) and each lane turns the bytes of its outputs into one fused
 // multiply-add per channel; stage 2 stages float32 sub-band rows in LDS (any
 // element shift is an aligned 4-byte read) and adds.  The matched filter
-// reads each row twice: once for its float64 moments, once for float64
-// running sums per tile, S/N of every (start, width) in float64, the per-width
-// best and the thresholded list.  Every channel term is rounded to float32
-// once (a fused multiply-add) and then added, so a float32 output differs
-// from the exact sum by at most (m + nsub + 1) 2^-24 times the sum of the
-// absolute terms.
+// reads each row once (float64 moments and per-tile running sums, the largest
+// window sum per width) and again only the tiles holding candidates.  Every
+// channel term is rounded to float32 once (a fused multiply-add) and then
+// added, so a float32 output differs from the exact sum by at most
+// (m + nsub + 1) 2^-24 times the sum of the absolute terms.
 #include <algorithm>
 
 #include "tx_internal.h"
@@ -300,25 +299,50 @@ __global__ __launch_bounds__(kThreads) void stage2_norm_kernel(Stage2NormArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Matched filter of float series.  One workgroup per row: float64 sum and
-// sum of squares give the mean and sigma; then per tile of kBoxTile starts,
-// float64 running sums in LDS, and every start's S/N at every width (thread
-// tid owns the starts tid + 256 m).  Per width the largest S/N (earliest
-// start); across widths the largest (ties to the smaller width); a start
-// whose best S/N reaches gamma is listed.  NWT: widths the instance holds
-// (slots past the row's widths repeat its last width).
+// Matched filter of float series.  One workgroup per row, which reads the row
+// once, in tiles of kNormBoxTile window starts (thread tid owns the starts
+// tid + 256 m):
+//  * each tile's float64 running sums of its kNormBoxTile + longest-width
+//    samples go to LDS; the same loads accumulate the float64 sum and sum of
+//    squares of the row;
+//  * for a fixed width the S/N is a non-decreasing function of the window
+//    sum, so the per-width peak is found on the sums alone: every lane keeps
+//    the largest sum of its starts per width, the wavefront's largest is
+//    compared with the wavefront's best so far, and only when it beats it (a
+//    few tiles per row) does the wavefront look up the earliest start
+//    reaching it; each wavefront's largest sums per (tile, width) are kept in
+//    LDS where they fit.
+// Then the mean and sigma give each width's peak S/N (the largest over widths,
+// ties to the smaller width), and per width S*, the least float64 sum whose
+// S/N (the same float64 expression) reaches gamma, by bisection over the
+// ordered doubles.  Only tiles where some wavefront's largest sum reaches S*
+// are scanned again, and there the wavefront evaluates its starts' S/N at
+// every width and lists those whose best reaches gamma.  NWT: widths the
+// instance holds (slots past the row's widths repeat its last width).
 // ---------------------------------------------------------------------------
+constexpr int kNormBoxTile = 4096;
+constexpr int kNormBoxPer = kNormBoxTile / kThreads;                 // starts per thread and tile
+constexpr int kNormScanPer = (kNormBoxTile + TX_MAX_WIDTH) / kThreads;  // running-sum samples per thread
+constexpr int kNormTmaxLds = 16 * 1024;
+
+template <int NWT>
 struct NormBoxShared {
-    double P[kBoxTile + TX_MAX_WIDTH + 16];
     double wsum[kWaves];
     double red1[kWaves], red2[kWaves];
-    double bs[kWaves][TX_MAX_WIDTHS];
-    int32_t bt[kWaves][TX_MAX_WIDTHS];
-    int32_t wd[TX_MAX_WIDTHS];
-    double rs[TX_MAX_WIDTHS];
+    double wm[kWaves][NWT];              // per wavefront: largest sum per width in this tile,
+    double wS[kWaves][NWT];              // the largest so far, and
+    int32_t wT[kWaves][NWT];             // its earliest start
+    double sthr[NWT];                    // least sum reaching gamma per width (NaN: none)
+    int32_t wd[NWT];
+    double rs[NWT];
     double mean, inv;
     int state;
 };
+
+// Dynamic LDS: the running sums P of a tile (kNormBoxTile + longest width +
+// 1 values), then (where it fits) the table [tile][NWT] of the workgroup's
+// largest sum per tile and width.
+extern __shared__ double tx_nbox_dyn[];
 
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -326,14 +350,231 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
+// One step of a wavefront max of a float64: both halves moved by the same DPP
+// pattern (lanes it does not write take -inf), then the larger kept.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double wave_max_step_d(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, static_cast<uint32_t>(b), CTRL, ROWS, 0xF, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0xFFF00000u, static_cast<uint32_t>(b >> 32), CTRL, ROWS, 0xF, false);
+    const double o = __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+    return __builtin_fmax(v, o);
+}
+
+// Wavefront max (quad, half-row and row permutes, then the row broadcasts of
+// 15 and 31), read from lane 63.  No operand is NaN.
+__device__ __forceinline__ double wave_max_d(double v) {
+    v = wave_max_step_d<0xB1, 0xF>(v);
+    v = wave_max_step_d<0x4E, 0xF>(v);
+    v = wave_max_step_d<0x141, 0xF>(v);
+    v = wave_max_step_d<0x140, 0xF>(v);
+    v = wave_max_step_d<0x142, 0xA>(v);
+    v = wave_max_step_d<0x143, 0xC>(v);
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(b)), 63);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(b >> 32)), 63);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ int32_t wave_min_i32_n(int32_t v) {
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0xB1, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x4E, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x141, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x140, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x142, 0xA, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x143, 0xC, 0xF, false));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// S/N of a window sum (the one expression used for peaks, candidates and S*).
+__device__ __forceinline__ double snr_f(double S, int w, double mean, double inv, double rsw) {
+    return ((S - static_cast<double>(w) * mean) * inv) * rsw;
+}
+
+// Doubles in a signed 64-bit order (for non-NaN values): the bits for
+// non-negative ones, the magnitude bits flipped for negative ones.  The map
+// is its own inverse.
+__device__ __forceinline__ int64_t dbl_key(int64_t bits) { return bits ^ ((bits >> 63) & INT64_MAX); }
+
+// Least double S in [-inf, +inf] with snr_f(S) >= gamma (snr_f does not
+// decrease with S: inv and rsw are positive); NaN when none reaches it.
+__device__ __forceinline__ double least_sum_reaching(double gamma, int w, double mean, double inv, double rsw) {
+    const double ninf = -__builtin_inf(), pinf = __builtin_inf();
+    if (snr_f(ninf, w, mean, inv, rsw) >= gamma) return ninf;
+    if (!(snr_f(pinf, w, mean, inv, rsw) >= gamma)) return __builtin_nan("");
+    int64_t lo = dbl_key(__builtin_bit_cast(int64_t, ninf));    // fails
+    int64_t hi = dbl_key(__builtin_bit_cast(int64_t, pinf));    // passes
+    while (static_cast<uint64_t>(hi) - static_cast<uint64_t>(lo) > 1u) {
+        const int64_t mid = static_cast<int64_t>(static_cast<uint64_t>(lo) +
+                                                 (static_cast<uint64_t>(hi) - static_cast<uint64_t>(lo)) / 2u);
+        if (snr_f(__builtin_bit_cast(double, dbl_key(mid)), w, mean, inv, rsw) >= gamma) hi = mid; else lo = mid;
+    }
+    return __builtin_bit_cast(double, dbl_key(hi));
+}
+
+// Float64 running sums P[e] = sum of y[t0 .. t0 + e) for e <= L (zeros past
+// T): each thread sums kNormScanPer consecutive samples; a wavefront scan and
+// the earlier wavefronts' totals give its base.  COUNT: add the tile's own
+// samples (e < kNormBoxTile) to the sum and sum of squares.
+template <bool COUNT, int NWT>
+__device__ __forceinline__ void norm_scan_tile(const TX_GLOBAL float* __restrict__ y, int T, int t0, int L, bool vec,
+                                               NormBoxShared<NWT>& sh, int tid, double& m1, double& m2) {
+    constexpr int kPer = kNormScanPer;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int e0 = kPer * tid;
+    const int64_t tb = static_cast<int64_t>(t0) + e0;
+    double v[kPer];
+    if (vec && e0 + kPer <= L && tb + kPer <= T) {
+#pragma unroll
+        for (int k = 0; k < kPer / 4; ++k) {
+            const float4 q = *reinterpret_cast<const TX_GLOBAL float4*>(y + tb + 4 * k);
+            v[4 * k] = q.x;
+            v[4 * k + 1] = q.y;
+            v[4 * k + 2] = q.z;
+            v[4 * k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) v[k] = (e0 + k < L && tb + k < T) ? static_cast<double>(y[tb + k]) : 0.0;
+    }
+    if (COUNT) {
+        const int own = kNormBoxTile - e0;           // samples of this tile (the rest belong to the next)
+        double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const double x = k < own ? v[k] : 0.0;
+            a1 += x;
+            a2 += x * x;
+        }
+        m1 += a1;
+        m2 += a2;
+    }
+    double run = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) run += v[k];
+    double incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double up = __shfl_up(incl, o);
+        if (lane >= o) incl += up;
+    }
+    if (lane == 63) sh.wsum[wave] = incl;
+    __syncthreads();
+    double base = incl - run;
+    for (int w2 = 0; w2 < wave; ++w2) base += sh.wsum[w2];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (e0 + k <= L) tx_nbox_dyn[e0 + k] = base;
+        base += v[k];
+    }
+    __syncthreads();
+}
+
+// Per-width largest sums of one tile (each wavefront's in sh.wm) and the
+// wavefront bests.  TAIL: some windows reach past the row end (they count as
+// -inf).
+template <int NWT, bool TAIL>
+__device__ __forceinline__ void norm_peak_tile(NormBoxShared<NWT>& sh, int T, int t0, int tid) {
+    const int wave = tid >> 6;
+    double Pt[kNormBoxPer];
+#pragma unroll
+    for (int j = 0; j < kNormBoxPer; ++j) Pt[j] = tx_nbox_dyn[tid + 256 * j];
+    double tm[NWT];
+#pragma unroll
+    for (int i = 0; i < NWT; ++i) {
+        const int w = sh.wd[i];
+        const double* p = tx_nbox_dyn + tid + w;
+        double m = -__builtin_inf();
+#pragma unroll
+        for (int j = 0; j < kNormBoxPer; ++j) {
+            double S = p[256 * j] - Pt[j];
+            if (TAIL) S = t0 + tid + 256 * j + w <= T ? S : -__builtin_inf();
+            m = __builtin_fmax(m, S);
+        }
+        tm[i] = m;
+        // Keep each width's LDS reads next to their arithmetic.
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // Wavefront maxima (independent reductions, interleaved), left in LDS
+    // for the rolled loop below to read by width.
+    double wm[NWT];
+#pragma unroll
+    for (int i = 0; i < NWT; ++i) wm[i] = wave_max_d(tm[i]);
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < NWT; ++i) sh.wm[wave][i] = wm[i];
+    }
+#pragma unroll 1
+    for (int ii = 0; ii < NWT; ++ii) {
+        const double m = sh.wm[wave][ii];
+        if (m > sh.wS[wave][ii]) {                      // wavefront-uniform, a few tiles per row
+            const int w = sh.wd[ii];
+            int32_t first = INT32_MAX;
+#pragma unroll 1
+            for (int j = kNormBoxPer - 1; j >= 0; --j) {   // rolled: this path is rare
+                const int e = tid + 256 * j;
+                const int t = t0 + e;
+                const double S = tx_nbox_dyn[e + w] - tx_nbox_dyn[e];
+                first = ((!TAIL || t + w <= T) && S == m) ? t : first;
+            }
+            const int32_t ft = wave_min_i32_n(first);
+            if ((tid & 63) == 0) {
+                sh.wS[wave][ii] = m;
+                sh.wT[wave][ii] = ft;
+            }
+        }
+    }
+}
+
+// A wavefront's candidates in one tile: every start whose best S/N over the
+// widths (ties to the smaller width) reaches gamma.
+template <int NWT>
+__device__ __forceinline__ void norm_cand_wave(const BoxcarNormArgs& a, NormBoxShared<NWT>& sh, int row, int t0, double mean,
+                                               double inv, int tid) {
+    const int T = a.nt;
+#pragma unroll 1
+    for (int j = 0; j < kNormBoxPer; ++j) {
+        const int e = tid + 256 * j;
+        const int t = t0 + e;
+        if (t >= T) break;
+        const double pe = tx_nbox_dyn[e];
+        double best = -__builtin_inf();
+        int bw = -1;
+        for (int i = 0; i < a.ne; ++i) {
+            const int w = sh.wd[i];
+            if (t + w > T) continue;
+            const double sn = snr_f(tx_nbox_dyn[e + w] - pe, w, mean, inv, sh.rs[i]);
+            if (bw < 0 || sn > best) {
+                best = sn;
+                bw = w;
+            }
+        }
+        if (bw > 0 && best >= a.gamma) {
+            const unsigned long long slot = atomicAdd(a.count, 1ull);
+            if (static_cast<long long>(slot) < a.cap) {
+                tx_cand c;
+                c.dm_index = row;
+                c.width = bw;
+                c.time = t;
+                c.snr = best;
+                to_global(a.cands)[slot] = c;
+            }
+        }
+    }
+}
+
 template <int NWT>
 __global__ __launch_bounds__(kThreads) void boxcar_norm_kernel(BoxcarNormArgs a) {
-    __shared__ NormBoxShared sh;
+    __shared__ NormBoxShared<NWT> sh;
     const int row = static_cast<int>(blockIdx.x);
     if (row >= a.ndm) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int T = a.nt;
     const TX_GLOBAL float* __restrict__ y = to_global(a.y) + static_cast<size_t>(row) * a.pitch;
+    const bool vec = ((reinterpret_cast<uintptr_t>(a.y) + static_cast<uintptr_t>(row) * a.pitch * 4) & 15) == 0;
+    const bool keep_tmax = a.tmax_ok != 0;
+    const int L = kNormBoxTile + a.wmax;
+    double* tmax = tx_nbox_dyn + ((L + 2) & ~1);
     if (tid < NWT) {
         int32_t w = 0;
         double r = 0.0;
@@ -346,19 +587,42 @@ __global__ __launch_bounds__(kThreads) void boxcar_norm_kernel(BoxcarNormArgs a)
         sh.wd[tid] = w;
         sh.rs[tid] = r;
     }
-
-    // moments
-    double s1 = 0.0, s2 = 0.0;
-    for (int t = tid; t < T; t += kThreads) {
-        const double v = static_cast<double>(y[t]);
-        s1 += v;
-        s2 += v * v;
-    }
-    s1 = wave_sum_d(s1);
-    s2 = wave_sum_d(s2);
     if (lane == 0) {
-        sh.red1[wave] = s1;
-        sh.red2[wave] = s2;
+#pragma unroll
+        for (int i = 0; i < NWT; ++i) {
+            sh.wS[wave][i] = -__builtin_inf();
+            sh.wT[wave][i] = 0;
+        }
+    }
+    // (the first tile's barriers order these writes before their reads)
+
+    const int ntiles = (T + kNormBoxTile - 1) / kNormBoxTile;
+    double m1 = 0.0, m2 = 0.0;
+    for (int tile = 0; tile < ntiles; ++tile) {
+        const int t0 = tile * kNormBoxTile;
+        // The thread index, opaque to the compiler in every tile: else it
+        // hoists lane-dependent addresses out of this loop.
+        int tv = tid;
+        asm volatile("" : "+v"(tv));
+        norm_scan_tile<true, NWT>(y, T, t0, L, vec, sh, tv, m1, m2);
+        if (a.ne > 0) {
+            if (t0 + kNormBoxTile + a.wmax > T) norm_peak_tile<NWT, true>(sh, T, t0, tv);
+            else norm_peak_tile<NWT, false>(sh, T, t0, tv);
+        }
+        __syncthreads();
+        // The workgroup's largest sum per width of this tile (the next tile's
+        // barriers order this before sh.wm is written again).
+        if (keep_tmax && tid < NWT)
+            tmax[tile * NWT + tid] = __builtin_fmax(__builtin_fmax(sh.wm[0][tid], sh.wm[1][tid]),
+                                                    __builtin_fmax(sh.wm[2][tid], sh.wm[3][tid]));
+    }
+
+    // Statistics.
+    m1 = wave_sum_d(m1);
+    m2 = wave_sum_d(m2);
+    if (lane == 0) {
+        sh.red1[wave] = m1;
+        sh.red2[wave] = m2;
     }
     __syncthreads();
     if (tid == 0) {
@@ -386,117 +650,24 @@ __global__ __launch_bounds__(kThreads) void boxcar_norm_kernel(BoxcarNormArgs a)
         return;
     }
     const double mean = sh.mean, inv = sh.inv;
-    double bs[NWT];
-    int32_t bt[NWT];
-#pragma unroll
-    for (int i = 0; i < NWT; ++i) {
-        bs[i] = -__builtin_inf();
-        bt[i] = 0;
-    }
-    const int ntiles = (T + kBoxTile - 1) / kBoxTile;
-    const int L = kBoxTile + a.wmax;
-    for (int tile = 0; tile < ntiles; ++tile) {
-        const int t0 = tile * kBoxTile;
-        // Running sums P[e] = sum of y[t0 .. t0 + e), e <= L (zeros past T):
-        // each thread sums 24 consecutive samples; a wavefront scan and the
-        // earlier wavefronts' totals give its base.
-        constexpr int kPer = 24;
-        const int e0 = kPer * tid;
-        double v[kPer];
-        double run = 0.0;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int e = e0 + k;
-            const int64_t t = static_cast<int64_t>(t0) + e;
-            v[k] = (e < L && t < T) ? static_cast<double>(y[t]) : 0.0;
-            run += v[k];
-        }
-        double incl = run;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const double up = __shfl_up(incl, o);
-            if (lane >= o) incl += up;
-        }
-        if (lane == 63) sh.wsum[wave] = incl;
-        __syncthreads();
-        double base = incl - run;
-        for (int w2 = 0; w2 < wave; ++w2) base += sh.wsum[w2];
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if (e0 + k <= L) sh.P[e0 + k] = base;
-            base += v[k];
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int m = 0; m < kBoxTile / kThreads; ++m) {
-            const int e = tid + 256 * m;
-            const int t = t0 + e;
-            if (t >= T) break;
-            const double pe = sh.P[e];
-            double best = -__builtin_inf();
-            int bw = -1;
-#pragma unroll
-            for (int i = 0; i < NWT; ++i) {
-                const int w = sh.wd[i];
-                if (i >= a.ne || t + w > T) continue;
-                const double S = sh.P[e + w] - pe;
-                const double sn = ((S - static_cast<double>(w) * mean) * inv) * sh.rs[i];
-                if (sn > bs[i]) {                          // starts increase: the first maximum stays
-                    bs[i] = sn;
-                    bt[i] = t;
-                }
-                if (bw < 0 || sn > best) {
-                    best = sn;
-                    bw = w;
-                }
-            }
-            if (a.want_cands && bw > 0 && best >= a.gamma) {
-                const unsigned long long slot = atomicAdd(a.count, 1ull);
-                if (static_cast<long long>(slot) < a.cap) {
-                    tx_cand c;
-                    c.dm_index = row;
-                    c.width = bw;
-                    c.time = t;
-                    c.snr = best;
-                    to_global(a.cands)[slot] = c;
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // Per width: the largest S/N over the workgroup, the earliest start on ties.
-#pragma unroll
-    for (int i = 0; i < NWT; ++i) {
-        double s = bs[i];
-        int32_t t = bt[i];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const double s2o = __shfl_xor(s, o);
-            const int32_t t2o = __shfl_xor(t, o);
-            if (s2o > s || (s2o == s && t2o < t)) {
-                s = s2o;
-                t = t2o;
-            }
-        }
-        if (lane == 0) {
-            sh.bs[wave][i] = s;
-            sh.bt[wave][i] = t;
-        }
-    }
-    __syncthreads();
+
+    // The row's peak: per width the largest sum over the wavefronts (earliest
+    // start on ties) and its S/N; the largest S/N over widths, ties to the
+    // smaller width.
     if (tid == 0 && a.want_peaks) {
         double best = 0.0;
         int bw = -1;
         int64_t btm = 0;
         for (int i = 0; i < a.ne; ++i) {
-            double s = sh.bs[0][i];
-            int32_t t = sh.bt[0][i];
+            double S = sh.wS[0][i];
+            int32_t t = sh.wT[0][i];
             for (int w2 = 1; w2 < kWaves; ++w2)
-                if (sh.bs[w2][i] > s || (sh.bs[w2][i] == s && sh.bt[w2][i] < t)) {
-                    s = sh.bs[w2][i];
-                    t = sh.bt[w2][i];
+                if (sh.wS[w2][i] > S || (sh.wS[w2][i] == S && sh.wT[w2][i] < t)) {
+                    S = sh.wS[w2][i];
+                    t = sh.wT[w2][i];
                 }
-            if (s == -__builtin_inf()) continue;
+            if (S == -__builtin_inf()) continue;
+            const double s = snr_f(S, sh.wd[i], mean, inv, sh.rs[i]);
             if (bw < 0 || s > best) {
                 best = s;
                 bw = sh.wd[i];
@@ -511,6 +682,24 @@ __global__ __launch_bounds__(kThreads) void boxcar_norm_kernel(BoxcarNormArgs a)
         to_global(a.snr)[row] = best;
         to_global(a.width)[row] = bw;
         to_global(a.time)[row] = btm;
+    }
+
+    // Candidates: only tiles whose largest sum reaches some width's S*; every
+    // tile where the table did not fit.
+    if (a.want_cands && a.ne > 0) {
+        if (tid < a.ne) sh.sthr[tid] = least_sum_reaching(a.gamma, sh.wd[tid], mean, inv, sh.rs[tid]);
+        __syncthreads();
+        for (int tile = 0; tile < ntiles; ++tile) {
+            bool hit = !keep_tmax;
+            if (keep_tmax)
+                for (int i = 0; i < a.ne; ++i) hit = hit || tmax[tile * NWT + i] >= sh.sthr[i];
+            if (!hit) continue;                           // workgroup-uniform
+            const int t0 = tile * kNormBoxTile;
+            double u1 = 0.0, u2 = 0.0;
+            norm_scan_tile<false, NWT>(y, T, t0, L, vec, sh, tid, u1, u2);
+            norm_cand_wave(a, sh, row, t0, mean, inv, tid);
+            __syncthreads();
+        }
     }
 }
 
@@ -609,14 +798,23 @@ hipError_t launch_boxcar_norm(const BoxcarNormArgs& a, hipStream_t stream) {
         if (e != hipSuccess) return e;
     }
     if (a.ndm <= 0) return hipSuccess;
+    // Dynamic LDS: the running sums (sized by the longest width), then the
+    // workgroup's largest sum per (tile, width) where it fits in
+    // kNormTmaxLds; otherwise candidates rescan every tile.
+    BoxcarNormArgs b = a;
+    const int nwt = boxcar_nwt(a.ne);
+    const int pbytes = ((kNormBoxTile + a.wmax + 2) & ~1) * 8;
+    const int64_t tbytes = static_cast<int64_t>((a.nt + kNormBoxTile - 1) / kNormBoxTile) * nwt * 8;
+    b.tmax_ok = tbytes <= kNormTmaxLds ? 1 : 0;
+    const int lds = pbytes + (b.tmax_ok ? static_cast<int>(tbytes) : 0);
     const int prof = prof_begin(TX_KERNEL_BOXCAR, stream);
-    switch (boxcar_nwt(a.ne)) {
-        case 4: hipLaunchKernelGGL(boxcar_norm_kernel<4>, dim3(a.ndm), dim3(kThreads), 0, stream, a); break;
-        case 8: hipLaunchKernelGGL(boxcar_norm_kernel<8>, dim3(a.ndm), dim3(kThreads), 0, stream, a); break;
-        case 10: hipLaunchKernelGGL(boxcar_norm_kernel<10>, dim3(a.ndm), dim3(kThreads), 0, stream, a); break;
-        case 12: hipLaunchKernelGGL(boxcar_norm_kernel<12>, dim3(a.ndm), dim3(kThreads), 0, stream, a); break;
-        case 16: hipLaunchKernelGGL(boxcar_norm_kernel<16>, dim3(a.ndm), dim3(kThreads), 0, stream, a); break;
-        default: hipLaunchKernelGGL(boxcar_norm_kernel<32>, dim3(a.ndm), dim3(kThreads), 0, stream, a); break;
+    switch (nwt) {
+        case 4: hipLaunchKernelGGL(boxcar_norm_kernel<4>, dim3(a.ndm), dim3(kThreads), lds, stream, b); break;
+        case 8: hipLaunchKernelGGL(boxcar_norm_kernel<8>, dim3(a.ndm), dim3(kThreads), lds, stream, b); break;
+        case 10: hipLaunchKernelGGL(boxcar_norm_kernel<10>, dim3(a.ndm), dim3(kThreads), lds, stream, b); break;
+        case 12: hipLaunchKernelGGL(boxcar_norm_kernel<12>, dim3(a.ndm), dim3(kThreads), lds, stream, b); break;
+        case 16: hipLaunchKernelGGL(boxcar_norm_kernel<16>, dim3(a.ndm), dim3(kThreads), lds, stream, b); break;
+        default: hipLaunchKernelGGL(boxcar_norm_kernel<32>, dim3(a.ndm), dim3(kThreads), lds, stream, b); break;
     }
     const hipError_t e = hipGetLastError();
     prof_end(prof, stream);

@@ -85,10 +85,15 @@ def test_dedisperse_norm_within_rounding_bound(shape, weighting):
         assert abs(float(np.mean(want[0]))) < 0.2 * np.sqrt(nchan)
 
 
-@pytest.mark.parametrize("nt,seed", [(5, 1), (4096, 2), (4097, 3), (10000, 4)])
-def test_float_boxcar_matches_oracle_on_the_same_series(nt, seed):
+W7 = [1, 2, 4, 8, 16, 32, 64]
+
+
+@pytest.mark.parametrize("nt,seed,widths", [(5, 1, W7), (4096, 2, W7), (4097, 3, W7), (10000, 4, W7),
+                                            (9000, 5, list(range(1, 33))), (20000, 6, [3, 5, 100, 1000]),
+                                            (70001, 7, [1 << k for k in range(10)])])
+def test_float_boxcar_matches_oracle_on_the_same_series(nt, seed, widths):
     torch = torch_cuda()
-    _say(f"float boxcar nt={nt}")
+    _say(f"float boxcar nt={nt} widths={len(widths)}")
     rng = np.random.default_rng(seed)
     rows = 12
     Y = rng.standard_normal((rows, nt)).astype(np.float32) * 8.0
@@ -96,7 +101,6 @@ def test_float_boxcar_matches_oracle_on_the_same_series(nt, seed):
     Y[3, nt // 2] += 60.0
     Y[4, :min(nt, 40)] += 9.0
     Y[5, -min(nt, 3):] += 30.0
-    widths = [1, 2, 4, 8, 16, 32, 64]
     d = torch.from_numpy(Y).to("cuda")
     snr = torch.empty(rows, dtype=torch.float64, device="cuda")
     wid = torch.empty(rows, dtype=torch.int32, device="cuda")

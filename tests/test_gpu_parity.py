@@ -236,6 +236,37 @@ def test_boxcar_ties_and_candidates_across_tiles_match_oracle(nt):
     assert np.array_equal(peaks[1], want[1]) and np.array_equal(peaks[2], want[2])
 
 
+@pytest.mark.parametrize("widths,nt", [(list(range(1, 33)), 530001),
+                                       (sorted([1 << k for k in range(11)] + [3, 5, 6, 7, 12, 24, 48, 96, 200]), 1 << 20)])
+def test_boxcar_long_rows_without_tile_maxima_match_oracle(widths, nt):
+    """Rows so long that the per-(tile, width) maxima do not fit the kernel's
+    16 KB table (tiles of 4096 starts x width slots x 4 bytes; only the
+    32-slot instance, rows up to the 2^20 limit): candidates then come from a
+    second scan of every tile.  Pulses at the row end, in a middle tile and
+    spread over many tiles."""
+    torch = torch_cuda()
+    ntiles = -(-nt // 4096)
+    assert ntiles * len(widths) * 4 > 16 * 1024          # the path without the table
+    _say(f"boxcar long rows widths={len(widths)} nt={nt}")
+    rng = np.random.default_rng(nt)
+    Y = rng.integers(0, 60, size=(3, nt)).astype(np.int32)
+    Y[0, nt - 3:] += 500
+    Y[1, ::40961] += 900
+    Y[2, 123456:123470] += 300
+    d = torch.from_numpy(Y).to("cuda")
+    snr, wid, tim = gpu_peaks(d, nt, widths)
+    want = oracle.boxcar_peaks(Y, widths)
+    _assert_snr(snr, want[0])
+    assert np.array_equal(wid, want[1]) and np.array_equal(tim, want[2])
+    n, rec, peaks = gpu_candidates(d, nt, widths, 6.0, with_peaks=True)
+    wc = oracle.boxcar_candidates(Y, widths, 6.0)
+    assert n == len(wc) and len(wc) > 0
+    got = as_tuples(rec)
+    assert [c[:3] for c in got] == [c[:3] for c in wc]
+    _assert_snr([c[3] for c in got], [c[3] for c in wc])
+    _assert_snr(peaks[0], want[0])
+
+
 def test_boxcar_out_of_range_rows_are_flagged():
     torch = torch_cuda()
     Y = np.random.default_rng(3).integers(0, 100, size=(3, 500)).astype(np.int32)
