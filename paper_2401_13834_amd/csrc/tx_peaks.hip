@@ -189,6 +189,98 @@ __global__ __launch_bounds__(kThreads) void lds_unaligned_kernel(uint32_t* out, 
     if (bad) atomicAdd(wrong, bad);
 }
 
+// Issue rates of single VALU forms: each instruction issued from inline asm
+// (arithmetic only), 8 independent chains per lane, 32 per loop step.
+// Kinds: 0 v_add_u32, 1 v_add3_u32, 2 v_alignbyte_b32, 3 v_perm_b32,
+// 4 v_pk_add_u16, 5 v_add_u32 with SDWA byte/word selects, 6 v_add_f32,
+// 7 v_fma_f32, 8 v_fma_mix_f32 (float16 operand), 9 v_add_f64, 10 v_max_f64.
+constexpr int kIssueKinds = 11;
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void issue_kernel(const uint32_t* in, uint32_t* out, int iters) {
+    uint32_t a[8];
+    double d[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        a[i] = in[i];
+        d[i] = static_cast<double>(in[i]);
+    }
+    const uint32_t b = in[16], c = in[17];
+    const double db = static_cast<double>(in[18]);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if constexpr (KIND == 0) asm volatile("v_add_u32_e32 %0, %1, %0" : "+v"(a[i]) : "v"(b));
+                else if constexpr (KIND == 1) asm volatile("v_add3_u32 %0, %1, %2, %0" : "+v"(a[i]) : "v"(b), "v"(c));
+                else if constexpr (KIND == 2) asm volatile("v_alignbyte_b32 %0, %1, %0, %2" : "+v"(a[i]) : "v"(b), "v"(c));
+                else if constexpr (KIND == 3) asm volatile("v_perm_b32 %0, %1, %0, %2" : "+v"(a[i]) : "v"(b), "v"(c));
+                else if constexpr (KIND == 4) asm volatile("v_pk_add_u16 %0, %1, %0" : "+v"(a[i]) : "v"(b));
+                else if constexpr (KIND == 5)
+                    asm volatile("v_add_u32_sdwa %0, %1, %0 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_2 "
+                                 "src1_sel:WORD_1"
+                                 : "+v"(a[i])
+                                 : "v"(b));
+                else if constexpr (KIND == 6) asm volatile("v_add_f32_e32 %0, %1, %0" : "+v"(a[i]) : "v"(b));
+                else if constexpr (KIND == 7) asm volatile("v_fma_f32 %0, %1, %2, %0" : "+v"(a[i]) : "v"(b), "v"(c));
+                else if constexpr (KIND == 8)
+                    asm volatile("v_fma_mix_f32 %0, %1, %2, %0 op_sel_hi:[1,0,0]" : "+v"(a[i]) : "v"(b), "v"(c));
+                else if constexpr (KIND == 9) asm volatile("v_add_f64 %0, %1, %0" : "+v"(d[i]) : "v"(db));
+                else asm volatile("v_max_f64 %0, %1, %0" : "+v"(d[i]) : "v"(db));
+            }
+    }
+    uint32_t x = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x ^= a[i] ^ static_cast<uint32_t>(__double_as_longlong(d[i]));
+    out[blockIdx.x * kThreads + threadIdx.x] = x;
+}
+
+// LDS writes: every lane writes W bytes (W = 4, 8, 16) at natural alignment,
+// consecutive lanes at consecutive addresses; indices below 3072 + 64 * 4.
+template <int W>
+__global__ __launch_bounds__(kThreads) void lds_write_kernel(uint32_t* out, int iters) {
+    __shared__ __align__(16) uint32_t buf[4096 + 16];
+    constexpr int D = W / 4;
+    const int lane = threadIdx.x & 63;
+    int base = (threadIdx.x >> 6) * 256;
+    uint32_t x = threadIdx.x;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = ((base + u * 1024) & 3072) + D * lane;
+            if constexpr (D == 4) *reinterpret_cast<uint4*>(&buf[idx]) = make_uint4(x, x + 1, x + 2, x + 3);
+            else if constexpr (D == 2) *reinterpret_cast<uint2*>(&buf[idx]) = make_uint2(x, x + 1);
+            else buf[idx] = x;
+            x += 5;
+        }
+        base = (base + 64) & 4095;
+    }
+    __syncthreads();
+    out[blockIdx.x * kThreads + threadIdx.x] = buf[threadIdx.x * 4];
+}
+
+// 16-byte LDS reads 4 bytes past a 16-byte boundary (the form an arbitrary
+// dword shift would need), lanes 16 bytes apart.  Indices stay below
+// 3072 + 63 * 4 + 1 + 4 < 4096 + 16.
+__global__ __launch_bounds__(kThreads) void lds_b128_off4_kernel(uint32_t* out, int iters) {
+    __shared__ __align__(16) uint32_t buf[4096 + 16];
+    for (int i = threadIdx.x; i < 4096 + 16; i += kThreads) buf[i] = i * 2654435761u;
+    __syncthreads();
+    uint32_t acc = 0;
+    const int lane = threadIdx.x & 63;
+    int base = (threadIdx.x >> 6) * 256;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = ((base + u * 1024) & 3072) + 4 * lane + 1;
+            const uint4 v = *static_cast<const uint4*>(__builtin_assume_aligned(&buf[idx], 16));
+            acc += v.x ^ v.y ^ v.z ^ v.w;
+        }
+        base = (base + 64) & 4095;
+    }
+    out[blockIdx.x * kThreads + threadIdx.x] = acc;
+}
+
 __global__ void copy_kernel(const uint4* __restrict__ in, uint4* __restrict__ out, size_t n) {
     size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -262,6 +354,33 @@ int main(int argc, char** argv) {
     CHECK(hipMemcpy(&n_wrong, wrong, 4, hipMemcpyDeviceToHost));
     CHECK(hipFree(wrong));
 
+    float t_is[kIssueKinds];
+    {
+        std::vector<uint32_t> hv(64);
+        for (int i = 0; i < 64; ++i) hv[i] = 0x3f800000u + 3u * i;   // small positive floats as bits
+        CHECK(hipMemcpy(in, hv.data(), 256, hipMemcpyHostToDevice));
+        const int it2 = quick ? 2000 : 20000;
+        auto run_is = [&](auto kern) {
+            return time_ms([&] { hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), 0, 0, in, out, it2); }, 3);
+        };
+        t_is[0] = run_is(issue_kernel<0>);
+        t_is[1] = run_is(issue_kernel<1>);
+        t_is[2] = run_is(issue_kernel<2>);
+        t_is[3] = run_is(issue_kernel<3>);
+        t_is[4] = run_is(issue_kernel<4>);
+        t_is[5] = run_is(issue_kernel<5>);
+        t_is[6] = run_is(issue_kernel<6>);
+        t_is[7] = run_is(issue_kernel<7>);
+        t_is[8] = run_is(issue_kernel<8>);
+        t_is[9] = run_is(issue_kernel<9>);
+        t_is[10] = run_is(issue_kernel<10>);
+        for (int k = 0; k < kIssueKinds; ++k) t_is[k] = static_cast<float>(lanes * it2 * 32 / (t_is[k] * 1e-3) / cus / clk_hz);
+    }
+    float t_w4 = time_ms([&] { hipLaunchKernelGGL(lds_write_kernel<4>, dim3(blocks), dim3(kThreads), 0, 0, out, lit); }, 3);
+    float t_w8 = time_ms([&] { hipLaunchKernelGGL(lds_write_kernel<8>, dim3(blocks), dim3(kThreads), 0, 0, out, lit); }, 3);
+    float t_w16 = time_ms([&] { hipLaunchKernelGGL(lds_write_kernel<16>, dim3(blocks), dim3(kThreads), 0, 0, out, lit); }, 3);
+    float t_r16o = time_ms([&] { hipLaunchKernelGGL(lds_b128_off4_kernel, dim3(blocks), dim3(kThreads), 0, 0, out, uit); }, 3);
+
     const size_t bytes = (size_t)(quick ? 1 : 4) << 30;
     uint4 *src, *dst;
     CHECK(hipMalloc(&src, bytes));
@@ -278,13 +397,21 @@ int main(int argc, char** argv) {
                 "\"lds_b128_bytes_per_clk_per_cu\": %.1f, \"lds_b32_bytes_per_clk_per_cu\": %.1f, "
                 "\"add3_per_clk_per_cu\": %.2f, \"alignbyte_per_clk_per_cu\": %.2f, \"perm_per_clk_per_cu\": %.2f, "
                 "\"lds_clk_per_wave_read\": {\"b32\": %.2f, \"b64\": %.2f, \"b128\": %.2f, "
-                "\"paired_b32_stride9\": %.2f, \"b32_byte_offset1\": %.2f}, \"lds_b32_byte_offset1_wrong\": %u, "
+                "\"paired_b32_stride9\": %.2f, \"b32_byte_offset1\": %.2f, \"b128_dword_offset1\": %.2f}, "
+                "\"lds_b32_byte_offset1_wrong\": %u, "
+                "\"lds_clk_per_wave_write\": {\"b32\": %.2f, \"b64\": %.2f, \"b128\": %.2f}, "
+                "\"issue_lane_instr_per_clk_per_cu\": {\"v_add_u32\": %.1f, \"v_add3_u32\": %.1f, "
+                "\"v_alignbyte_b32\": %.1f, \"v_perm_b32\": %.1f, \"v_pk_add_u16\": %.1f, "
+                "\"v_add_u32_sdwa\": %.1f, \"v_add_f32\": %.1f, \"v_fma_f32\": %.1f, \"v_fma_mix_f32\": %.1f, "
+                "\"v_add_f64\": %.1f, \"v_max_f64\": %.1f}, "
                 "\"hbm_copy_bytes_per_s\": %.4e}\n",
                 prop.name, cus, clk_hz / 1e6, add32, add16, perm_add, add32 / cus / clk_hz, add16 / cus / clk_hz,
                 lds_bw(t_l4, 4), lds_bw(t_l8, 8), lds_bw(t_l16, 16), lds_bw(t_l16, 16) / cus / clk_hz,
                 lds_bw(t_l4, 4) / cus / clk_hz, v3_rate[0], v3_rate[1], v3_rate[2],
                 lds_clk(t_l4, waves * lit * 8), lds_clk(t_l8, waves * lit * 8), lds_clk(t_l16, waves * lit * 8),
-                lds_clk(t_s9, waves * lit * 4 * 5), lds_clk(t_ua, waves * uit * 4), n_wrong, copy_bw);
+                lds_clk(t_s9, waves * lit * 4 * 5), lds_clk(t_ua, waves * uit * 4), lds_clk(t_r16o, waves * uit * 4),
+                n_wrong, lds_clk(t_w4, waves * lit * 4), lds_clk(t_w8, waves * lit * 4), lds_clk(t_w16, waves * lit * 4),
+                t_is[0], t_is[1], t_is[2], t_is[3], t_is[4], t_is[5], t_is[6], t_is[7], t_is[8], t_is[9], t_is[10], copy_bw);
     CHECK(hipFree(src));
     CHECK(hipFree(dst));
     CHECK(hipFree(in));
