@@ -180,7 +180,11 @@ constexpr int kNormJW = 2;                 // stage 1: coarse trials per wave (8
 constexpr int kNormQ = 5;                  // stage 1: output dwords per lane (20 outputs; odd)
 constexpr int kNormIW = 16;
 constexpr int kNormTT2 = 768;
-constexpr int kNormLds = 32 * 1024;
+// Default LDS per workgroup of the two stages: 20 KB lets 8 workgroups share
+// a CU (the register limit of both kernels), which measured faster than
+// fewer workgroups with larger or double-buffered staging rounds.
+constexpr int kNormLds = 20 * 1024;        // stage 2
+constexpr int kNormLds1 = 20 * 1024;       // stage 1
 
 struct Stage1NormArgs {
     const uint8_t* x;       // input rows (16-byte aligned)

@@ -724,7 +724,7 @@ NormGeom norm_geometry(const tx_plan_s* p, int64_t nt) {
     g.ws_bytes = (static_cast<int64_t>(p->ngroups) * p->nsub * g.B_pitch * 4 + 255) / 256 * 256;
     const int sp1 = plan_spread1(p, 4 * kNormJW) + 15;
     const int row1 = 4 * (((sp1 >> 2) + 64 * kNormQ + 1 + 3) & ~3);   // a staged row (as the kernel sizes it)
-    g.lds1 = std::max(kNormLds, row1 + ((p->m * (4 * kNormJW + 3) * 4 + 15) & ~15) + 64);
+    g.lds1 = std::max(kNormLds1, row1 + ((p->m * (4 * kNormJW + 3) * 4 + 15) & ~15) + 64);
     const int row2 = ((sp2 + kNormTT2 + 3) & ~3) * 4;
     g.lds2 = std::max(kNormLds, row2 + ((kNormIW * p->nsub * 4 + 15) & ~15) + 64);
     g.ok = g.lds1 <= device_max_lds() && g.lds2 <= device_max_lds();
