@@ -34,6 +34,9 @@ PEAK_ADD16 = 256 * 4 * 16 * 2 * 2.4e9   # 16-bit integer adds/s: 256 CUs x 64 la
 MEASURED_VOP3_PER_CLK_CU = 59.3
 MEASURED_PAIRED_LDS_B_PER_CLK_CU = 124.3
 PAPER_DM_SAMPLES_PER_S = 4096 / 153e-6  # real time on one CPU core, 4096 channels and trials, 153 us
+# Plain-copy HBM rate (bytes read + written per second) that tx_peaks measures
+# on this part: the practical HBM ceiling beside the 8 TB/s published peak.
+MEASURED_COPY_BYTES_PER_S = 4.47e12
 
 
 KERNEL_SOURCES = {"stage1": ("tx_kernels_dedisp.hip",), "stage2": ("tx_kernels_dedisp.hip",),
@@ -810,6 +813,19 @@ def main():
                 "loop_ceiling_measured_Tadd_s": round(min(valu_ceiling_measured, lds_ceiling), 2),
                 "loop_ceiling_measured_frac": round(achieved / min(valu_ceiling_measured, lds_ceiling), 4)}
 
+    # The other two kernels of the step against HBM: counter bytes per launch
+    # (committed rocprofv3 summary, current source only) over event time.
+    def hbm_entry(k, adds=None):
+        t = kern[k]["avg_ms"] * 1e-3
+        tr = load_traffic(k, args.workload)
+        e = {"ms": round(t * 1e3, 4), "traffic": tr,
+             "hbm_GBps": None if tr is None else round(tr / t / 1e9, 1),
+             "hbm_frac": None if tr is None else round(tr / t / 8e12, 4),
+             "copy_frac": None if tr is None else round(tr / t / MEASURED_COPY_BYTES_PER_S, 4)}
+        if adds is not None:
+            e.update({"achieved_Tadd_s": round(adds / t / 1e12, 3), "add_frac": round(adds / t / PEAK_ADD16, 4)})
+        return e
+
     out = {
         "metric": "dedispersed DM-trial samples/s (plain one-beam-per-launch path)",
         "value": value,
@@ -835,6 +851,7 @@ def main():
         "adds_per_step": adds1 + adds2,
         "candidates_last_step": ncand,
         "roofline": roofline,
+        "roofline_kernels": {"stage2": hbm_entry("stage2", adds2), "boxcar": hbm_entry("boxcar")},
     }
     del d_in, y, cands
     torch.cuda.synchronize()
