@@ -145,6 +145,27 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, dtype, name):
+    """Argument check: ``t`` is a tensor of ``dtype`` ("uint8", "int32", ...)
+    whose rows, if it has two dimensions, are contiguous (the library takes a
+    base pointer and a row pitch in elements of that type)."""
+    if t is None:
+        return t
+    if str(t.dtype) != "torch." + dtype:
+        raise TypeError(f"{name}: a {dtype} tensor is expected, not {t.dtype}")
+    if t.dim() == 2 and t.numel() > 0 and t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name}: the rows of the tensor must be contiguous")
+    return t
+
+
+def _need_peaks(peaks, name):
+    if peaks is not None:
+        _need(peaks[0], "float64", name + " snr")
+        _need(peaks[1], "int32", name + " width")
+        _need(peaks[2], "int64", name + " time")
+    return peaks
+
+
 class Plan:
     """Owner of a ``tx_plan_t``."""
 
@@ -252,6 +273,8 @@ def tx_plan(freqs_mhz, tsamp_s, dms, nsub, *, dms_per_group=0, host_only=False):
 
 def tx_dedisperse(plan, d_in, nt, d_out, stream=None, ws=None):
     """d_in: uint8 device tensor [nchan, in_pitch]; d_out: int32 [ndm, out_pitch]."""
+    _need(d_in, "uint8", "tx_dedisperse d_in")
+    _need(d_out, "int32", "tx_dedisperse d_out")
     in_pitch = d_in.stride(0) * d_in.element_size()
     out_pitch = d_out.stride(0)
     if ws is None:
@@ -308,6 +331,10 @@ def tx_norm_weights(sums, nt, weighting=TX_WEIGHT_UNIT):
 
 def tx_dedisperse_norm(plan, d_in, nt, d_scale, d_offset, d_out, stream=None):
     """d_in uint8 [nchan, pitch]; d_scale, d_offset float32 [nchan]; d_out float32 [ndm, pitch]."""
+    _need(d_in, "uint8", "tx_dedisperse_norm d_in")
+    _need(d_scale, "float32", "tx_dedisperse_norm d_scale")
+    _need(d_offset, "float32", "tx_dedisperse_norm d_offset")
+    _need(d_out, "float32", "tx_dedisperse_norm d_out")
     in_pitch = d_in.stride(0) * d_in.element_size()
     _check(_setup_norm().tx_dedisperse_norm(plan.handle, _ptr(d_in), in_pitch, int(nt), _ptr(d_scale),
                                             _ptr(d_offset), _ptr(d_out), d_out.stride(0), _stream(stream)),
@@ -315,6 +342,8 @@ def tx_dedisperse_norm(plan, d_in, nt, d_scale, d_offset, d_out, stream=None):
 
 
 def tx_boxcar_snr_f32(dmt, nt, widths, snr, width, time, stream=None):
+    _need(dmt, "float32", "tx_boxcar_snr_f32 dmt")
+    _need_peaks((snr, width, time), "tx_boxcar_snr_f32")
     w, wp = _widths(widths)
     _check(_setup_norm().tx_boxcar_snr_f32(_ptr(dmt), dmt.shape[0], int(nt), dmt.stride(0), wp, len(w), _ptr(snr),
                                            _ptr(width), _ptr(time), _stream(stream)), "tx_boxcar_snr_f32")
@@ -322,6 +351,8 @@ def tx_boxcar_snr_f32(dmt, nt, widths, snr, width, time, stream=None):
 
 def tx_boxcar_snr_fixed(dmt, nt, widths, mean, sigma, snr, width, time, stream=None):
     """Peak S/N of float32 rows with a given noise mean and sigma."""
+    _need(dmt, "float32", "tx_boxcar_snr_fixed dmt")
+    _need_peaks((snr, width, time), "tx_boxcar_snr_fixed")
     w, wp = _widths(widths)
     _check(_setup_norm().tx_boxcar_snr_fixed(_ptr(dmt), dmt.shape[0], int(nt), dmt.stride(0), wp, len(w),
                                              float(mean), float(sigma), _ptr(snr), _ptr(width), _ptr(time),
@@ -330,6 +361,9 @@ def tx_boxcar_snr_fixed(dmt, nt, widths, mean, sigma, snr, width, time, stream=N
 
 def tx_candidates_f32(dmt, nt, widths, gamma, cands, count, peaks=None, stream=None):
     """As tx_candidates, for a float32 DM x time tensor."""
+    _need(dmt, "float32", "tx_candidates_f32 dmt")
+    _need(count, "int64", "tx_candidates_f32 count")
+    _need_peaks(peaks, "tx_candidates_f32")
     w, wp = _widths(widths)
     cap = (cands.numel() * cands.element_size()) // CAND_DTYPE.itemsize
     p = (ctypes.c_void_p(0),) * 3 if peaks is None else tuple(_ptr(t) for t in peaks)
@@ -343,6 +377,8 @@ TX_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 def tx_dedisperse_noalloc(plan, d_in, nt, d_out, stream=None):
     """tx_dedisperse through the library's fixed scratch (no allocation)."""
+    _need(d_in, "uint8", "tx_dedisperse_noalloc d_in")
+    _need(d_out, "int32", "tx_dedisperse_noalloc d_out")
     in_pitch = d_in.stride(0) * d_in.element_size()
     _check(lib().tx_dedisperse_noalloc(plan.handle, _ptr(d_in), in_pitch, int(nt), _ptr(d_out), d_out.stride(0),
                                        _stream(stream)), "tx_dedisperse_noalloc")
@@ -351,6 +387,8 @@ def tx_dedisperse_noalloc(plan, d_in, nt, d_out, stream=None):
 def tx_transpose_tf(d_tf, nchan, nt, d_ft, stream=None):
     """d_tf: uint8 device tensor [>= nt, >= nchan] (time-major); d_ft: uint8
     device tensor [>= nchan, >= nt] receiving d_ft[c, t] = d_tf[t, c]."""
+    _need(d_tf, "uint8", "tx_transpose_tf d_tf")
+    _need(d_ft, "uint8", "tx_transpose_tf d_ft")
     _check(lib().tx_transpose_tf(_ptr(d_tf), d_tf.stride(0) * d_tf.element_size(), int(nchan), int(nt), _ptr(d_ft),
                                  d_ft.stride(0) * d_ft.element_size(), _stream(stream)), "tx_transpose_tf")
 
@@ -358,6 +396,8 @@ def tx_transpose_tf(d_tf, nchan, nt, d_ft, stream=None):
 def tx_channel_power_sums(d_in, nchan, nt, d_sums, stream=None):
     """d_in: uint8 device tensor [nchan, >= nt]; d_sums: int64 device tensor
     [nchan, 4] receiving sum x, x^2, x^3, x^4 per channel (as uint64 bits)."""
+    _need(d_in, "uint8", "tx_channel_power_sums d_in")
+    _need(d_sums, "int64", "tx_channel_power_sums d_sums")
     _check(lib().tx_channel_power_sums(_ptr(d_in), d_in.stride(0) * d_in.element_size(), int(nchan), int(nt),
                                        _ptr(d_sums), _stream(stream)), "tx_channel_power_sums")
 
@@ -376,6 +416,7 @@ def tx_cluster(plan, cands, n, radius, min_pts, stream=None):
     (int64 [>= n, 3], as filled by tx_candidates).  Returns device tensors
     (sorted records [n, 3], labels int32 [n], reps int64 [n], nclusters
     int64 [1])."""
+    _need(cands, "int64", "tx_cluster cands")
     import torch
     n = int(n)
     dev = cands.device
@@ -391,6 +432,8 @@ def tx_cluster(plan, cands, n, radius, min_pts, stream=None):
 def tx_downsample(d_in, nchan, nt_out, k, d_out, stream=None):
     """d_in: uint8 device tensor [nchan, >= k*nt_out]; d_out: uint8 device
     tensor [nchan, >= nt_out] receiving the rounded means of k samples."""
+    _need(d_in, "uint8", "tx_downsample d_in")
+    _need(d_out, "uint8", "tx_downsample d_out")
     _check(lib().tx_downsample(_ptr(d_in), d_in.stride(0) * d_in.element_size(), int(nchan), int(nt_out), int(k),
                                _ptr(d_out), d_out.stride(0) * d_out.element_size(), _stream(stream)), "tx_downsample")
 
@@ -416,6 +459,9 @@ class Ranges:
     def dedisperse(self, d_in, nt, d_outs, stream=None):
         """d_in: uint8 device tensor [nchan, >= input_len(nt)]; d_outs[r]: int32
         device tensor [plans[r].ndm, >= nt / factors[r]]."""
+        _need(d_in, "uint8", "Ranges.dedisperse d_in")
+        for o in d_outs:
+            _need(o, "int32", "Ranges.dedisperse d_outs")
         outs = (ctypes.c_void_p * len(d_outs))(*[_ptr(o) for o in d_outs])
         pitches = (ctypes.c_int64 * len(d_outs))(*[o.stride(0) for o in d_outs])
         _check(lib().tx_ranges_dedisperse(self._h, _ptr(d_in), d_in.stride(0) * d_in.element_size(), int(nt), outs,
@@ -440,6 +486,8 @@ def _widths(widths):
 
 def tx_boxcar_snr(dmt, nt, widths, snr, width, time, stream=None):
     """dmt: int32 device tensor [ndm, pitch]; outputs float64/int32/int64 device [ndm]."""
+    _need(dmt, "int32", "tx_boxcar_snr dmt")
+    _need_peaks((snr, width, time), "tx_boxcar_snr")
     w, wp = _widths(widths)
     _check(lib().tx_boxcar_snr(_ptr(dmt), dmt.shape[0], int(nt), dmt.stride(0), wp, len(w), _ptr(snr),
                                _ptr(width), _ptr(time), _stream(stream)), "tx_boxcar_snr")
@@ -448,6 +496,9 @@ def tx_boxcar_snr(dmt, nt, widths, snr, width, time, stream=None):
 def tx_candidates(dmt, nt, widths, gamma, cands, count, peaks=None, stream=None):
     """cands: device tensor of at least cap*24 bytes (uint8 [cap, 24] or int64 [cap, 3]);
     count: int64 device tensor [1]; peaks: optional (snr, width, time) device tensors."""
+    _need(dmt, "int32", "tx_candidates dmt")
+    _need(count, "int64", "tx_candidates count")
+    _need_peaks(peaks, "tx_candidates")
     w, wp = _widths(widths)
     cap = (cands.numel() * cands.element_size()) // CAND_DTYPE.itemsize
     if peaks is None:
@@ -594,6 +645,8 @@ class Stream:
 
     def push(self, block, nt, d_out, stream=None):
         """block: uint8 tensor [nchan, >= nt] on the device or in (pinned) host memory."""
+        _need(block, "uint8", "Stream.push block")
+        _need(d_out, "int32", "Stream.push d_out")
         on_dev = 1 if block.is_cuda else 0
         n = ctypes.c_int64()
         _check(lib().tx_stream_push(self._h, _ptr(block), block.stride(0) * block.element_size(), int(nt), on_dev,
@@ -604,6 +657,8 @@ class Stream:
     def push_tf(self, block, nt, d_out, stream=None):
         """block: time-major uint8 tensor [>= nt, >= nchan] (one row of channels
         per time sample) on the device or in (pinned) host memory."""
+        _need(block, "uint8", "Stream.push_tf block")
+        _need(d_out, "int32", "Stream.push_tf d_out")
         on_dev = 1 if block.is_cuda else 0
         n = ctypes.c_int64()
         _check(lib().tx_stream_push_tf(self._h, _ptr(block), block.stride(0) * block.element_size(), int(nt), on_dev,
@@ -645,6 +700,8 @@ class Stream:
 
 
 def _box(widths, gamma, peaks, cands, count):
+    _need_peaks(peaks, "batch boxcar")
+    _need(count, "int64", "batch boxcar count")
     if peaks is None:
         return None, None
     w = np.ascontiguousarray(widths, dtype=np.int32)
@@ -670,6 +727,8 @@ class Batch:
         self._keep = []
 
     def add(self, plan, d_in, nt, d_out, widths=None, gamma=6.0, peaks=None, cands=None, count=None):
+        _need(d_in, "uint8", "Batch.add d_in")
+        _need(d_out, "int32", "Batch.add d_out")
         bx, w = _box(widths, gamma, peaks, cands, count)
         self._keep.append(w)
         _check(lib().tx_batch_add(self._h, plan.handle, _ptr(d_in), d_in.stride(0) * d_in.element_size(), int(nt),
@@ -677,6 +736,8 @@ class Batch:
                "tx_batch_add")
 
     def add_stream(self, stream_obj, block, nt, d_out, widths=None, gamma=6.0, peaks=None, cands=None, count=None):
+        _need(block, "uint8", "Batch.add_stream block")
+        _need(d_out, "int32", "Batch.add_stream d_out")
         bx, w = _box(widths, gamma, peaks, cands, count)
         self._keep.append(w)
         _check(lib().tx_batch_add_stream(self._h, stream_obj.handle, _ptr(block),
@@ -687,6 +748,8 @@ class Batch:
     def add_stream_tf(self, stream_obj, block, nt, d_out, widths=None, gamma=6.0, peaks=None, cands=None,
                       count=None):
         """add_stream for a time-major block [>= nt, >= nchan]."""
+        _need(block, "uint8", "Batch.add_stream_tf block")
+        _need(d_out, "int32", "Batch.add_stream_tf d_out")
         bx, w = _box(widths, gamma, peaks, cands, count)
         self._keep.append(w)
         _check(lib().tx_batch_add_stream_tf(self._h, stream_obj.handle, _ptr(block),

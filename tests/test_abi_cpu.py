@@ -188,3 +188,30 @@ def test_norm_weights_host_call_equals_oracle(weighting):
     assert scale[7] == 0.0 and offset[7] == 0.0
     with pytest.raises(tx.TxError):
         tx.tx_norm_weights(sums, n, 2)
+
+
+def test_binding_refuses_tensors_of_the_wrong_type():
+    """The binding passes base pointers and row pitches in elements of the
+    declared type, so a tensor of another type (say an int64 DM x time array
+    given to the int32 boxcar) or with strided rows is refused before any
+    library call."""
+    torch = pytest.importorskip("torch")
+    widths = [1, 2, 4]
+    snr = torch.empty(2, dtype=torch.float64)
+    wid = torch.empty(2, dtype=torch.int32)
+    tim = torch.empty(2, dtype=torch.int64)
+    with pytest.raises(TypeError):
+        tx.tx_boxcar_snr(torch.zeros((2, 16), dtype=torch.int64), 16, widths, snr, wid, tim)
+    with pytest.raises(TypeError):
+        tx.tx_boxcar_snr_f32(torch.zeros((2, 16), dtype=torch.float64), 16, widths, snr, wid, tim)
+    with pytest.raises(TypeError):
+        tx.tx_boxcar_snr(torch.zeros((2, 16), dtype=torch.int32), 16, widths, snr.float(), wid, tim)
+    with pytest.raises(TypeError):
+        tx.tx_candidates(torch.zeros((2, 16), dtype=torch.int32), 16, widths, 6.0,
+                         torch.zeros((4, 3), dtype=torch.int64), torch.zeros(1, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        tx.tx_boxcar_snr(torch.zeros((16, 2), dtype=torch.int32).t(), 16, widths, snr, wid, tim)
+    with pytest.raises(TypeError):
+        tx.tx_dedisperse(None, torch.zeros((4, 64), dtype=torch.int32), 16, torch.zeros((4, 16), dtype=torch.int32))
+    with pytest.raises(TypeError):
+        tx.tx_channel_power_sums(torch.zeros((4, 64), dtype=torch.uint8), 4, 64, torch.zeros((4, 4), dtype=torch.int32))
