@@ -169,6 +169,9 @@ tx_status tx_plan_destroy(tx_plan_t plan);
 /*
  * Bytes of device scratch that tx_dedisperse_ws needs for output length nt
  * (the first-stage series of every coarse group and sub-band, uint16).
+ * TX_ENOTSUP, as tx_dedisperse answers it, when a staged row of the plan's
+ * tiles does not fit the device's LDS (a group of trials spanning a very
+ * wide range of delays).
  */
 tx_status tx_dedisperse_ws_size(tx_plan_t plan, int64_t nt, int64_t* bytes);
 

@@ -264,7 +264,13 @@ tx_status tx_plan_destroy(tx_plan_t p) {
 
 tx_status tx_dedisperse_ws_size(tx_plan_t p, int64_t nt, int64_t* bytes) {
     if (!p || !bytes || nt < 0) return TX_EINVAL;
-    *bytes = nt == 0 ? 0 : tx::dedisp_geometry(p, nt, current_tiles(p)).ws_bytes;
+    if (nt == 0) {
+        *bytes = 0;
+        return TX_OK;
+    }
+    const tx::DedispGeom g = tx::dedisp_geometry(p, nt, current_tiles(p));
+    if (!g.ok) return TX_ENOTSUP;                  // as tx_dedisperse would answer
+    *bytes = g.ws_bytes;
     return TX_OK;
 }
 
