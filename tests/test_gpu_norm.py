@@ -202,3 +202,46 @@ def test_fixed_sigma_boxcar_width_mismatch_closed_form(W):
     assert int(wid.item()) == W and int(tim.item()) == 3000
     with pytest.raises(tx.TxError):
         tx.tx_boxcar_snr_fixed(d, nt, widths, 0.0, 0.0, snr, wid, tim)
+
+
+@pytest.mark.parametrize("widths,nt", [(list(range(1, 33)), 600001),
+                                       (sorted([1 << k for k in range(11)] + [3, 5, 6, 7, 12, 24, 48, 96, 200]), 1 << 20)])
+def test_float_boxcar_long_rows_without_tile_table(widths, nt):
+    """Float rows too long for the filter's per-(tile, width) table (tiles of
+    4096 starts x width slots x 8 bytes over 16 KB): candidates then come from
+    a second scan of every tile."""
+    torch = torch_cuda()
+    assert -(-nt // 4096) * 32 * 8 > 16 * 1024
+    _say(f"float boxcar long rows nt={nt} widths={len(widths)}")
+    rng = np.random.default_rng(nt)
+    Y = rng.standard_normal((3, nt)).astype(np.float32) * 5.0
+    Y[0, nt - 3:] += 40.0
+    Y[1, ::40961] += 60.0
+    Y[2, 123456:123470] += 25.0
+    d = torch.from_numpy(Y).to("cuda")
+    rows = Y.shape[0]
+    snr = torch.empty(rows, dtype=torch.float64, device="cuda")
+    wid = torch.empty(rows, dtype=torch.int32, device="cuda")
+    tim = torch.empty(rows, dtype=torch.int64, device="cuda")
+    raw = torch.zeros((1 << 16, 3), dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gamma = 6.0
+    tx.tx_candidates_f32(d, nt, widths, gamma, raw, cnt, peaks=(snr, wid, tim))
+    torch.cuda.synchronize()
+    Yd = Y.astype(np.float64)
+    ws, ww, wt = oracle.boxcar_peaks_float(Yd, widths)
+    gs, gw, gt = snr.cpu().numpy(), wid.cpu().numpy(), tim.cpu().numpy()
+    assert np.allclose(gs, ws, rtol=1e-9, atol=1e-12)
+    for r in range(rows):
+        if (gw[r], gt[r]) != (ww[r], wt[r]):     # a near tie: the GPU's pick must be as good
+            s = oracle.boxcar_snr_series_float(Yd[r], int(gw[r]))[int(gt[r])]
+            assert abs(s - ws[r]) <= 1e-9 * abs(ws[r])
+    n = int(cnt.item())
+    got = {(c[0], c[1]): c for c in as_tuples(tx.parse_candidates(raw.cpu().numpy(), n))}
+    want = {(c[0], c[1]): c for c in oracle.boxcar_candidates_float(Yd, widths, gamma)}
+    assert len(want) > 0
+    for k in set(got) ^ set(want):               # only points at the threshold may differ
+        c = got.get(k) or want.get(k)
+        assert abs(c[3] - gamma) < 1e-9 * gamma, c
+    for k in set(got) & set(want):
+        assert abs(got[k][3] - want[k][3]) <= 1e-9 * abs(want[k][3])
