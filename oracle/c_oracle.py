@@ -6,7 +6,6 @@ pin it to the NumPy oracle and to brute force, and the benchmark times it as
 the CPU baseline."""
 
 import ctypes
-import os
 
 import numpy as np
 

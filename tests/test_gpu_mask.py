@@ -11,7 +11,7 @@ import pytest
 import oracle
 import synth
 import paper_2401_13834_amd as tx
-from gpu_helpers import device_block, gpu_dedisperse, round_up, torch_cuda
+from gpu_helpers import device_block, gpu_dedisperse, torch_cuda
 
 pytestmark = pytest.mark.gpu
 

@@ -12,7 +12,7 @@ import pytest
 import oracle
 import synth
 import paper_2401_13834_amd as tx
-from gpu_helpers import as_tuples, device_block, round_up, torch_cuda
+from gpu_helpers import as_tuples, device_block, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
