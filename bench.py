@@ -34,9 +34,13 @@ PEAK_ADD16 = 256 * 4 * 16 * 2 * 2.4e9   # 16-bit integer adds/s: 256 CUs x 64 la
 MEASURED_VOP3_PER_CLK_CU = 59.3
 MEASURED_PAIRED_LDS_B_PER_CLK_CU = 124.3
 PAPER_DM_SAMPLES_PER_S = 4096 / 153e-6  # real time on one CPU core, 4096 channels and trials, 153 us
-# Plain-copy HBM rate (bytes read + written per second) that tx_peaks measures
-# on this part: the practical HBM ceiling beside the 8 TB/s published peak.
-MEASURED_COPY_BYTES_PER_S = 4.47e12
+# HBM rates that tx_peaks measures on this part, the practical ceilings beside
+# the 8 TB/s published peak: a copy with 8 loads in flight per thread (bytes
+# read + written per second) and a read-only stream.  The write rate follows
+# from the two: a copy of B bytes takes B / read + B / write.
+MEASURED_COPY_BYTES_PER_S = 4.94e12
+MEASURED_READ_BYTES_PER_S = 5.98e12
+MEASURED_WRITE_BYTES_PER_S = 1.0 / (2.0 / MEASURED_COPY_BYTES_PER_S - 1.0 / MEASURED_READ_BYTES_PER_S)
 
 
 KERNEL_SOURCES = {"stage1": ("tx_kernels_dedisp.hip",), "stage2": ("tx_kernels_dedisp.hip",),
@@ -60,9 +64,10 @@ def kernel_source_hash(kernel):
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, workload):
+def load_traffic(kernel, workload, split=False):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+    was taken on the current kernel source (with split: bytes read and bytes
+    written)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -72,6 +77,10 @@ def load_traffic(kernel, workload):
     ent = data.get(f"{kernel}:{workload}")
     if not ent or ent.get("source_hash") != kernel_source_hash(kernel):
         return None
+    if split:
+        if ent.get("read_bytes") is None or ent.get("write_bytes") is None:
+            return None
+        return ent["read_bytes"], ent["write_bytes"]
     return ent.get("hbm_bytes_per_launch")
 
 
@@ -822,6 +831,12 @@ def main():
              "hbm_GBps": None if tr is None else round(tr / t / 1e9, 1),
              "hbm_frac": None if tr is None else round(tr / t / 8e12, 4),
              "copy_frac": None if tr is None else round(tr / t / MEASURED_COPY_BYTES_PER_S, 4)}
+        rw = load_traffic(k, args.workload, split=True)
+        if rw is not None:
+            # Time to stream the kernel's own counter bytes at the measured
+            # read and write rates, and the fraction of the launch time it is.
+            floor = rw[0] / MEASURED_READ_BYTES_PER_S + rw[1] / MEASURED_WRITE_BYTES_PER_S
+            e.update({"stream_floor_ms": round(floor * 1e3, 4), "stream_frac": round(floor / t, 4)})
         if adds is not None:
             e.update({"achieved_Tadd_s": round(adds / t / 1e12, 3), "add_frac": round(adds / t / PEAK_ADD16, 4)})
         return e

@@ -1,5 +1,6 @@
 // Measured peaks of the units the dedispersion kernels use, on the current
-// GPU: HBM copy bandwidth, 32-bit and packed 16-bit integer add rates, the
+// GPU: HBM copy bandwidth (one and several 16-byte loads in flight per
+// thread) and read-only bandwidth, 32-bit and packed 16-bit integer add rates, the
 // issue rates of the three-operand add, byte-align and byte-permute
 // instructions, and LDS read bandwidth and cost per read instruction
 // (aligned 4-, 8- and 16-byte reads, the first stage's paired 4-byte reads,
@@ -287,6 +288,42 @@ __global__ void copy_kernel(const uint4* __restrict__ in, uint4* __restrict__ ou
     for (; i < n; i += stride) out[i] = in[i];
 }
 
+// The same copy with U independent 16-byte loads in flight per thread before
+// their stores (pieces i, i + stride, ..., i + (U - 1) stride), then the
+// pieces left over one at a time.  More bytes in flight per CU than the plain
+// copy, whose one outstanding load per thread can leave HBM waiting on latency.
+template <int U>
+__global__ void copy_u_kernel(const uint4* __restrict__ in, uint4* __restrict__ out, size_t n) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = in[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) out[i + u * stride] = v[u];
+    }
+    for (; i < n; i += stride) out[i] = in[i];
+}
+
+// Read-only stream: U independent 16-byte loads per thread per step, folded
+// into one word per thread that is stored at the end (so no load is dropped).
+template <int U>
+__global__ void read_u_kernel(const uint4* __restrict__ in, size_t n, uint32_t* __restrict__ out) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    uint32_t acc = 0;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = in[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    }
+    for (; i < n; i += stride) acc ^= in[i].x;
+    out[blockIdx.x * (size_t)blockDim.x + threadIdx.x] = acc;
+}
+
 template <typename F>
 static float time_ms(F f, int reps) {
     hipEvent_t a, b;
@@ -389,6 +426,35 @@ int main(int argc, char** argv) {
     const size_t n = bytes / 16;
     float t_cp = time_ms([&] { hipLaunchKernelGGL(copy_kernel, dim3(cus * 16), dim3(256), 0, 0, src, dst, n); }, 5);
     const double copy_bw = 2.0 * bytes / (t_cp * 1e-3);
+    // Copies and read-only streams with 4 or 8 loads in flight per thread, on
+    // grids of 8 and 32 workgroups of 256 threads per CU: the best of each.
+    const int grids[2] = {cus * 8, cus * 32};
+    uint32_t* sink;
+    CHECK(hipMalloc(&sink, (size_t)grids[1] * 256 * sizeof(uint32_t)));
+    double copy_u_bw = 0.0, read_u_bw = 0.0;
+    int copy_u_best[2] = {0, 0}, read_u_best[2] = {0, 0};
+    for (int gi = 0; gi < 2; ++gi) {
+        const int gb = grids[gi];
+        const float c4 = time_ms([&] { hipLaunchKernelGGL(copy_u_kernel<4>, dim3(gb), dim3(256), 0, 0, src, dst, n); }, 5);
+        const float c8 = time_ms([&] { hipLaunchKernelGGL(copy_u_kernel<8>, dim3(gb), dim3(256), 0, 0, src, dst, n); }, 5);
+        const float r4 = time_ms([&] { hipLaunchKernelGGL(read_u_kernel<4>, dim3(gb), dim3(256), 0, 0, src, n, sink); }, 5);
+        const float r8 = time_ms([&] { hipLaunchKernelGGL(read_u_kernel<8>, dim3(gb), dim3(256), 0, 0, src, n, sink); }, 5);
+        const float cs[2] = {c4, c8}, rs[2] = {r4, r8};
+        for (int k = 0; k < 2; ++k) {
+            const double cb = 2.0 * bytes / (cs[k] * 1e-3), rb = 1.0 * bytes / (rs[k] * 1e-3);
+            if (cb > copy_u_bw) {
+                copy_u_bw = cb;
+                copy_u_best[0] = 4 << k;
+                copy_u_best[1] = gb / cus;
+            }
+            if (rb > read_u_bw) {
+                read_u_bw = rb;
+                read_u_best[0] = 4 << k;
+                read_u_best[1] = gb / cus;
+            }
+        }
+    }
+    CHECK(hipFree(sink));
 
     std::printf("{\"device\": \"%s\", \"cus\": %d, \"clock_mhz\": %.0f, "
                 "\"add32_per_s\": %.4e, \"add16_packed_per_s\": %.4e, \"perm_add_pairs_per_s\": %.4e, "
@@ -404,14 +470,18 @@ int main(int argc, char** argv) {
                 "\"v_alignbyte_b32\": %.1f, \"v_perm_b32\": %.1f, \"v_pk_add_u16\": %.1f, "
                 "\"v_add_u32_sdwa\": %.1f, \"v_add_f32\": %.1f, \"v_fma_f32\": %.1f, \"v_fma_mix_f32\": %.1f, "
                 "\"v_add_f64\": %.1f, \"v_max_f64\": %.1f}, "
-                "\"hbm_copy_bytes_per_s\": %.4e}\n",
+                "\"hbm_copy_bytes_per_s\": %.4e, "
+                "\"hbm_copy_inflight_bytes_per_s\": %.4e, \"hbm_copy_inflight_loads_per_thread\": %d, "
+                "\"hbm_copy_inflight_workgroups_per_cu\": %d, "
+                "\"hbm_read_bytes_per_s\": %.4e, \"hbm_read_loads_per_thread\": %d, \"hbm_read_workgroups_per_cu\": %d}\n",
                 prop.name, cus, clk_hz / 1e6, add32, add16, perm_add, add32 / cus / clk_hz, add16 / cus / clk_hz,
                 lds_bw(t_l4, 4), lds_bw(t_l8, 8), lds_bw(t_l16, 16), lds_bw(t_l16, 16) / cus / clk_hz,
                 lds_bw(t_l4, 4) / cus / clk_hz, v3_rate[0], v3_rate[1], v3_rate[2],
                 lds_clk(t_l4, waves * lit * 8), lds_clk(t_l8, waves * lit * 8), lds_clk(t_l16, waves * lit * 8),
                 lds_clk(t_s9, waves * lit * 4 * 5), lds_clk(t_ua, waves * uit * 4), lds_clk(t_r16o, waves * uit * 4),
                 n_wrong, lds_clk(t_w4, waves * lit * 4), lds_clk(t_w8, waves * lit * 4), lds_clk(t_w16, waves * lit * 4),
-                t_is[0], t_is[1], t_is[2], t_is[3], t_is[4], t_is[5], t_is[6], t_is[7], t_is[8], t_is[9], t_is[10], copy_bw);
+                t_is[0], t_is[1], t_is[2], t_is[3], t_is[4], t_is[5], t_is[6], t_is[7], t_is[8], t_is[9], t_is[10], copy_bw,
+                copy_u_bw, copy_u_best[0], copy_u_best[1], read_u_bw, read_u_best[0], read_u_best[1]);
     CHECK(hipFree(src));
     CHECK(hipFree(dst));
     CHECK(hipFree(in));
