@@ -38,8 +38,8 @@ PAPER_DM_SAMPLES_PER_S = 4096 / 153e-6  # real time on one CPU core, 4096 channe
 # the 8 TB/s published peak: a copy with 8 loads in flight per thread (bytes
 # read + written per second) and a read-only stream.  The write rate follows
 # from the two: a copy of B bytes takes B / read + B / write.
-MEASURED_COPY_BYTES_PER_S = 4.94e12
-MEASURED_READ_BYTES_PER_S = 5.98e12
+MEASURED_COPY_BYTES_PER_S = 4.91e12
+MEASURED_READ_BYTES_PER_S = 5.94e12
 MEASURED_WRITE_BYTES_PER_S = 1.0 / (2.0 / MEASURED_COPY_BYTES_PER_S - 1.0 / MEASURED_READ_BYTES_PER_S)
 
 
