@@ -83,8 +83,9 @@ typedef struct tx_plan_s* tx_plan_t;
  *                     nchan / nsub <= 256 (the first stage sums up to 256
  *                     uint8 channels exactly in 16 bits).  0 asks the plan to
  *                     pick nsub itself (the divisor of nchan with at most 256
- *                     channels per sub-band that minimises the additions per
- *                     output sample).
+ *                     channels per sub-band that minimises N_c * nchan +
+ *                     2.5 * ndm * nsub, the additions per output sample of
+ *                     the two stages weighted by their cost on MI355X).
  *
  * Delays follow Sec. 2.3 Eq. 1 with k = 4.148808e3 s MHz^2 pc^-1 cm^3:
  *   D(DM, f) = floor(((k*DM) * (1/(f*f) - 1/(fref*fref))) / tsamp + 0.5),

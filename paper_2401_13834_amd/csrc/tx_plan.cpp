@@ -50,7 +50,13 @@ static int32_t group_rule(const std::vector<double>& f, int32_t nsub, int32_t nd
 }
 
 // Automatic sub-band count: the divisor of nchan with at most 256 channels per
-// sub-band that minimises additions per output sample, nchan/g + nsub.
+// sub-band that minimises the modelled time per output sample,
+// N_c * N_f + kStage2AddCost * N_DM * nsub.  A second-stage addition costs
+// about 2.5 first-stage ones on MI355X: the first stage sums 35 T byte-adds/s
+// and the second 16 T adds/s on the paper-scale block, and the uneven
+// 64-beam batch runs fastest at about the sub-band counts this weight picks.
+constexpr double kStage2AddCost = 2.5;
+
 static int32_t choose_nsub(const std::vector<double>& f, int32_t ndm) {
     const int32_t nchan = static_cast<int32_t>(f.size());
     int32_t best = -1;
@@ -59,7 +65,7 @@ static int32_t choose_nsub(const std::vector<double>& f, int32_t ndm) {
         if (nchan % ns != 0 || nchan / ns > kMaxChansPerSub) continue;
         int32_t g = group_rule(f, ns, ndm);
         int32_t ngroups = (ndm + g - 1) / g;
-        double cost = static_cast<double>(ngroups) * nchan + static_cast<double>(ndm) * ns;
+        double cost = static_cast<double>(ngroups) * nchan + kStage2AddCost * static_cast<double>(ndm) * ns;
         if (best < 0 || cost < best_cost) {
             best = ns;
             best_cost = cost;

@@ -75,14 +75,20 @@ def test_host_plan_random_shapes_equal_oracle(seed):
     assert np.array_equal(p.tables()["extent"], ref.extent)
 
 
-def test_automatic_subband_count_minimises_additions():
-    wl = synth.workload("paper-4096")
+@pytest.mark.parametrize("name", ["paper-4096", "batched-0", "batched-1", "batched-2", "batched-5"])
+def test_automatic_subband_count_minimises_weighted_additions(name):
+    """nsub = 0: the divisor of nchan (at most 256 channels per sub-band) that
+    minimises N_c * nchan + 2.5 * ndm * nsub, as documented in the header."""
+    if name.startswith("batched-"):
+        wl = synth.batched_beams()[int(name.split("-")[1])]
+    else:
+        wl = synth.workload(name)
     p = tx.tx_plan(wl.freqs, wl.tsamp, wl.dms, 0, host_only=True)
     nchan, ndm = len(wl.freqs), len(wl.dms)
 
     def cost(ns):
         g = oracle.group_size_rule(wl.freqs, ns, ndm)
-        return -(-ndm // g) * nchan + ndm * ns
+        return -(-ndm // g) * nchan + 2.5 * ndm * ns
 
     cands = [ns for ns in range(1, nchan + 1) if nchan % ns == 0 and nchan // ns <= 256]
     assert p.nsub in cands
