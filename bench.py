@@ -47,8 +47,9 @@ KERNEL_SOURCES = {"stage1": ("tx_kernels_dedisp.hip",), "stage2": ("tx_kernels_d
                   "boxcar": ("tx_kernels_boxcar.hip",), "transpose": ("tx_kernels_transpose.hip",),
                   "stats": ("tx_kernels_stats.hip",), "downsample2": ("tx_kernels_downsample.hip",),
                   "downsample4": ("tx_kernels_downsample.hip",),
-                  # the batch launch: its persistent dedispersion and boxcar kernels
-                  "batch": ("tx_kernels_dedisp.hip", "tx_kernels_boxcar.hip")}
+                  # the batch launch: its persistent dedispersion and boxcar kernels,
+                  # and the plan code that picks each beam's sub-band count
+                  "batch": ("tx_kernels_dedisp.hip", "tx_kernels_boxcar.hip", "tx_plan.cpp")}
 
 
 def kernel_source_hash(kernel):
